@@ -1,0 +1,168 @@
+/*
+ * alb.h -- C ABI of the adaptive load balancer (ALB) traversal library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library runs data-driven graph traversals in bulk-synchronous rounds
+ * (paper Section 2, "Graph Analytics"): each round applies a push operator to
+ * the out-edges of every active vertex.  Work is balanced as in Section 4.1:
+ * Algorithm 1 inspects every active vertex, sends those whose out-degree is at
+ * least a threshold to a "huge" worklist and processes the others with the
+ * thread / wavefront / workgroup bins of TWC (Section 3); Algorithm 2 spreads
+ * the edges of the huge vertices cyclically over every launched thread and
+ * finds each edge's source by a binary search in the prefix sum of the huge
+ * degrees.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns alb_status; nothing throws or aborts across the ABI.
+ *    On failure alb_last_error() returns a thread-local detail string, the
+ *    output arrays are unspecified and *stats (if given) is zeroed.
+ *  - Graphs are CSR: row_offsets has n+1 int32 entries, row_offsets[0] = 0,
+ *    non-decreasing, row_offsets[n] = m; col has m int32 entries in [0, n);
+ *    weights (optional) has m non-negative int32 entries.  0 <= m < 2^31.
+ *  - Label outputs have n elements and are owned by the caller.  By default
+ *    they are host pointers and the call returns when they are filled.  With
+ *    options.out_on_device != 0 they are device pointers (for example a torch
+ *    tensor's data_ptr()), written in stream order on options.stream; the
+ *    call then returns after enqueueing the copy-out and the stats are valid
+ *    on return.
+ *  - Unreachable levels and distances are INT32_MAX.
+ *  - A graph handle is immutable after creation; calls on one handle may run
+ *    concurrently (each takes its own workspace).
+ */
+#ifndef ALB_H
+#define ALB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct alb_graph_s *alb_graph;
+
+typedef enum {
+  ALB_OK = 0,
+  ALB_E_INVAL = -1,       /* bad argument or malformed CSR */
+  ALB_E_NOMEM = -2,       /* host or device allocation failed */
+  ALB_E_DEVICE = -3,      /* HIP runtime error, no usable GPU, or a device-side abort */
+  ALB_E_RANGE = -4,       /* a shortest-path distance could exceed INT32_MAX - 1 */
+  ALB_E_OVERFLOW = -5,    /* a device worklist exceeded its capacity */
+  ALB_E_UNSUPPORTED = -6  /* option value not implemented */
+} alb_status;
+
+/* Which vertices take the cyclic (Algorithm 2) path.
+ * ALB:      out-degree >= threshold (Algorithm 1).
+ * TWC_ONLY: none (threshold above every degree; plain TWC, Section 3).
+ * LB_ALL:   every active vertex with at least one edge (threshold 0; the
+ *           paper's "D-IrGL (LB)" configuration, Section 5.1). */
+typedef enum { ALB_MODE_ALB = 0, ALB_MODE_TWC_ONLY = 1, ALB_MODE_LB_ALL = 2 } alb_mode;
+
+/* Round driver.  HOST_LOOP launches one kernel per phase and reads two
+ * counters back per round.  PERSISTENT runs every round inside one
+ * cooperative launch with grid-wide barriers between phases.  AUTO picks
+ * PERSISTENT when the device supports cooperative launches. */
+typedef enum { ALB_LAUNCH_AUTO = 0, ALB_LAUNCH_HOST_LOOP = 1, ALB_LAUNCH_PERSISTENT = 2 } alb_launch;
+
+/* Graph creation flags. */
+enum {
+  ALB_SYMMETRIC = 1u,       /* caller asserts the CSR already holds both directions of every edge */
+  ALB_BUILD_SYMMETRIC = 2u  /* create adds the reverse of every edge on the host (for alb_cc) */
+};
+
+typedef struct {
+  uint32_t struct_size;      /* sizeof(alb_options); set by alb_options_init */
+  int32_t mode;              /* alb_mode */
+  int64_t huge_threshold;    /* ALB mode: < 0 = launched threads (Section 4.1 default) */
+  int32_t wg_size;           /* 0 = 256; one of 64, 256, 1024 */
+  int32_t wave_cutoff;       /* TWC wavefront bin: degree >= this (0 = 64) */
+  int32_t wg_cutoff;         /* TWC workgroup bin: degree >= this (0 = wg_size) */
+  int32_t distribution;      /* 0 = cyclic (Section 4.1 default); others unsupported */
+  int32_t dedup;             /* -1 = default (on for sssp and cc), 0 = off, 1 = on */
+  int32_t launch;            /* alb_launch */
+  int32_t grid_wgs;          /* 0 = every resident workgroup; else this many workgroups */
+  int64_t worklist_capacity; /* 0 = automatic (n with dedup, n + m without) */
+  void *stream;              /* hipStream_t; NULL = the library's stream */
+  uint32_t out_on_device;    /* outputs are device pointers (see above) */
+  int32_t reserved[7];
+} alb_options;
+
+typedef struct {
+  int32_t rounds;            /* BSP rounds run (PageRank: iterations) */
+  int32_t kernel_launches;   /* traversal kernels launched (1 in persistent mode) */
+  int64_t launched_threads;  /* T: threads of the traversal grid */
+  int64_t huge_threshold;    /* threshold actually used (INT64_MAX = none huge) */
+  int64_t frontier_vertices; /* sum over rounds of active-vertex count */
+  int64_t edges_examined;    /* sum over rounds of the out-degrees of active vertices */
+  int64_t huge_vertices;     /* sum over rounds of the huge worklist size */
+  int64_t huge_edges;        /* sum over rounds of the huge vertices' edges */
+  int64_t pushes;            /* vertices pushed to a next-round worklist */
+  double device_ms;          /* device time from label initialisation to the last round */
+  double kernel_ms;          /* device time of the traversal rounds alone */
+} alb_stats;
+
+/* Fill *opt with defaults.  Returns ALB_E_INVAL for NULL. */
+alb_status alb_options_init(alb_options *opt);
+
+/* Copy a host CSR to the current HIP device and return a handle that owns the
+ * device copy.  The caller keeps ownership of the host arrays.  `weights` may
+ * be NULL (then alb_sssp is refused).  Validation follows the conventions
+ * above; with weights, max(w) * (n - 1) must be < INT32_MAX (ALB_E_RANGE
+ * otherwise).  ALB_BUILD_SYMMETRIC drops the weights. */
+alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, const int32_t *col,
+                            const int32_t *weights, uint32_t flags, alb_graph *out);
+
+/* Release the device copy and every cached workspace.  NULL is a no-op. */
+alb_status alb_graph_destroy(alb_graph g);
+
+/* Vertex and edge counts, the maximum out-degree and the device bytes held
+ * (graph plus cached workspaces).  Any output pointer may be NULL. */
+alb_status alb_graph_info(alb_graph g, int32_t *n, int64_t *m, int32_t *max_out_degree, size_t *device_bytes);
+
+/* Breadth-first search from `source` (push, top-down every round; Section 5):
+ * level[v] = hop distance, INT32_MAX if unreachable. */
+alb_status alb_bfs(alb_graph g, int32_t source, int32_t *level, const alb_options *opt, alb_stats *stats);
+
+/* Single-source shortest paths from `source` with the graph's weights: a
+ * data-driven Bellman-Ford whose operator is the relaxation of Section 4.3
+ * (atomic minimum).  dist[v] = shortest distance, INT32_MAX if unreachable. */
+alb_status alb_sssp(alb_graph g, int32_t source, int32_t *dist, const alb_options *opt, alb_stats *stats);
+
+/* Weakly connected components by min-label propagation (push).  The handle
+ * must be symmetric (ALB_SYMMETRIC or ALB_BUILD_SYMMETRIC), else
+ * ALB_E_INVAL.  label[v] = the smallest vertex id of v's component. */
+alb_status alb_cc(alb_graph g, int32_t *label, const alb_options *opt, alb_stats *stats);
+
+/* PageRank, fp32, push over out-edges, exactly `iterations` synchronous
+ * iterations from rank = 1/n:  r'(v) = (1-d)/n + d * (sum over in-edges (u,v)
+ * of r(u)/outdeg(u) + D/n), D = total rank of vertices without out-edges.
+ * 0 < damping < 1, iterations >= 0. */
+alb_status alb_pagerank(alb_graph g, float damping, int32_t iterations, float *rank, const alb_options *opt,
+                        alb_stats *stats);
+
+/* One round of the balancer on an explicit frontier, with an operator that
+ * records instead of updating labels (for checking the distribution).  Host
+ * pointers.  Inputs: frontier[nf] (vertex ids).  Outputs:
+ *   bins[nf]       Algorithm 1 bin of each entry: 0 thread, 1 wavefront,
+ *                  2 workgroup, 3 huge;
+ *   work[nf], *nwork   the huge worklist in the order the device built it;
+ *   prefix[nf + 1] its exclusive degree prefix (prefixWork), prefix[*nwork] = e;
+ *   edge_hits[m]   how many times each CSR edge was processed;
+ *   edge_thread[m] the global thread index that processed it last;
+ *   next[...], *nnext  the pushed destinations (every processed edge pushes its
+ *                  destination; capacity = sum of the frontier's degrees).
+ * `next` may be NULL to skip the copy.  Uses opt->mode, huge_threshold,
+ * wg_size, cutoffs, launch and grid_wgs like the traversals do. */
+alb_status alb_trace_round(alb_graph g, const int32_t *frontier, int64_t nf, const alb_options *opt,
+                           int8_t *bins, int32_t *work, int64_t *nwork, int64_t *prefix, int32_t *edge_hits,
+                           int32_t *edge_thread, int32_t *next, int64_t *nnext, alb_stats *stats);
+
+/* Static strings; never NULL. */
+const char *alb_status_str(alb_status s);
+const char *alb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALB_H */

@@ -1,0 +1,274 @@
+"""Python binding of libalb.so (include/alb.h): argument marshalling only.
+
+Every traversal step runs in the HIP kernels of libalb.so.  torch is used only
+to hand over device buffers (a CUDA tensor's data_ptr) and streams.  If the
+library is not built this module raises ImportError at import time: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libalb.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libalb.so is not built (python -m paper_1911_09135_amd.build); "
+                      "the ALB library has no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC = 1, 2
+MODES = {"alb": 0, "twc": 1, "twc_only": 1, "lb_all": 2}
+LAUNCHES = {"auto": 0, "host": 1, "host_loop": 1, "persistent": 2}
+INF = np.iinfo(np.int32).max
+BIN_THREAD, BIN_WAVE, BIN_WG, BIN_HUGE = 0, 1, 2, 3
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("mode", ctypes.c_int32),
+        ("huge_threshold", ctypes.c_int64),
+        ("wg_size", ctypes.c_int32),
+        ("wave_cutoff", ctypes.c_int32),
+        ("wg_cutoff", ctypes.c_int32),
+        ("distribution", ctypes.c_int32),
+        ("dedup", ctypes.c_int32),
+        ("launch", ctypes.c_int32),
+        ("grid_wgs", ctypes.c_int32),
+        ("worklist_capacity", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+        ("out_on_device", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("rounds", ctypes.c_int32),
+        ("kernel_launches", ctypes.c_int32),
+        ("launched_threads", ctypes.c_int64),
+        ("huge_threshold", ctypes.c_int64),
+        ("frontier_vertices", ctypes.c_int64),
+        ("edges_examined", ctypes.c_int64),
+        ("huge_vertices", ctypes.c_int64),
+        ("huge_edges", ctypes.c_int64),
+        ("pushes", ctypes.c_int64),
+        ("device_ms", ctypes.c_double),
+        ("kernel_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp, _i32, _i64, _u32, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float
+_POpt, _PSt = ctypes.POINTER(Options), ctypes.POINTER(Stats)
+_sig = {
+    "alb_options_init": ([_POpt], ctypes.c_int),
+    "alb_graph_create": ([_i32, _i64, _vp, _vp, _vp, _u32, ctypes.POINTER(_vp)], ctypes.c_int),
+    "alb_graph_destroy": ([_vp], ctypes.c_int),
+    "alb_graph_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                        ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "alb_bfs": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_sssp": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_cc": ([_vp, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_pagerank": ([_vp, _f32, _i32, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_trace_round": ([_vp, _vp, _i64, _POpt, _vp, _vp, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp,
+                         ctypes.POINTER(_i64), _PSt], ctypes.c_int),
+    "alb_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "alb_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class AlbError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = "%s: %s (%s)" % (where, _lib.alb_status_str(status).decode(), _lib.alb_last_error().decode())
+        super().__init__(msg)
+
+
+def _check(status: int, where: str) -> None:
+    if status != ALB_OK:
+        raise AlbError(status, where)
+
+
+def make_options(mode: str = "alb", threshold: Optional[int] = None, wg_size: int = 0, wave_cutoff: int = 0,
+                 wg_cutoff: int = 0, dedup: Optional[bool] = None, launch: str = "auto", grid_wgs: int = 0,
+                 worklist_capacity: int = 0, stream=None, out_on_device: bool = False,
+                 distribution: int = 0) -> Options:
+    o = Options()
+    _check(_lib.alb_options_init(ctypes.byref(o)), "alb_options_init")
+    o.mode = MODES[mode]
+    o.huge_threshold = -1 if threshold is None else int(threshold)
+    o.wg_size = int(wg_size)
+    o.wave_cutoff = int(wave_cutoff)
+    o.wg_cutoff = int(wg_cutoff)
+    o.distribution = int(distribution)
+    o.dedup = -1 if dedup is None else int(bool(dedup))
+    o.launch = LAUNCHES[launch]
+    o.grid_wgs = int(grid_wgs)
+    o.worklist_capacity = int(worklist_capacity)
+    o.stream = _stream_handle(stream)
+    o.out_on_device = 1 if out_on_device else 0
+    return o
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # a torch.cuda.Stream
+
+
+def _i32arr(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Graph:
+    """Device-resident CSR graph (alb_graph_create)."""
+
+    def __init__(self, off, col, weights=None, symmetric: bool = False, build_symmetric: bool = False):
+        off, col = _i32arr(off), _i32arr(col)
+        w = None if weights is None else _i32arr(weights)
+        n = off.shape[0] - 1
+        flags = (ALB_SYMMETRIC if symmetric else 0) | (ALB_BUILD_SYMMETRIC if build_symmetric else 0)
+        h = _vp()
+        _check(_lib.alb_graph_create(n, col.shape[0], off.ctypes.data, col.ctypes.data if col.size else None,
+                                     None if w is None else w.ctypes.data, flags, ctypes.byref(h)),
+               "alb_graph_create")
+        self._h = h
+        self.n = n
+        n_, m_, md = _i32(), _i64(), _i32()
+        _check(_lib.alb_graph_info(h, ctypes.byref(n_), ctypes.byref(m_), ctypes.byref(md), None), "alb_graph_info")
+        self.m = m_.value
+        self.max_out_degree = md.value
+
+    @classmethod
+    def from_csr(cls, g, **kw) -> "Graph":
+        """From any object with .off, .col and optional .w (for example graphgen.Graph)."""
+        return cls(g.off, g.col, getattr(g, "w", None), **kw)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph is closed")
+        return self._h
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.alb_graph_info(self.handle, None, None, None, ctypes.byref(b)), "alb_graph_info")
+        return b.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.alb_graph_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _out_buffer(g: Graph, out, dtype):
+    """Returns (pointer, result object, on_device)."""
+    if out is None:
+        arr = np.empty(g.n, dtype=dtype)
+        return arr.ctypes.data, arr, False
+    if isinstance(out, np.ndarray):
+        if out.dtype != dtype or out.shape != (g.n,) or not out.flags.c_contiguous:
+            raise ValueError("out must be a contiguous %s array of length n" % np.dtype(dtype).name)
+        return out.ctypes.data, out, False
+    # a torch tensor on the GPU
+    if not out.is_cuda or not out.is_contiguous() or out.numel() != g.n:
+        raise ValueError("out must be a contiguous CUDA tensor of length n")
+    return out.data_ptr(), out, True
+
+
+def _run(fn, g: Graph, out, dtype, opts: dict, *args):
+    ptr, res, dev = _out_buffer(g, out, dtype)
+    if dev and opts.get("stream") is None:
+        import torch
+
+        opts = dict(opts, stream=torch.cuda.current_stream())
+    o = make_options(out_on_device=dev, **opts)
+    st = Stats()
+    _check(fn(g.handle, *args, ptr, ctypes.byref(o), ctypes.byref(st)), fn.__name__)
+    return res, st.as_dict()
+
+
+def bfs(g: Graph, source: int, out=None, **opts):
+    """Levels from `source` (int32, INF unreachable) and the stats dict."""
+    return _run(_lib.alb_bfs, g, out, np.int32, opts, int(source))
+
+
+def sssp(g: Graph, source: int, out=None, **opts):
+    return _run(_lib.alb_sssp, g, out, np.int32, opts, int(source))
+
+
+def cc(g: Graph, out=None, **opts):
+    return _run(_lib.alb_cc, g, out, np.int32, opts)
+
+
+def pagerank(g: Graph, damping: float = 0.85, iterations: int = 50, out=None, **opts):
+    return _run(_lib.alb_pagerank, g, out, np.float32, opts, ctypes.c_float(damping), int(iterations))
+
+
+def trace_round(g: Graph, frontier, off=None, **opts) -> dict:
+    """One recorded round on an explicit frontier (alb_trace_round)."""
+    fr = _i32arr(frontier)
+    nf = fr.shape[0]
+    bins = np.empty(nf, dtype=np.int8)
+    work = np.empty(max(nf, 1), dtype=np.int32)
+    prefix = np.empty(nf + 1, dtype=np.int64)
+    hits = np.empty(max(g.m, 1), dtype=np.int32)
+    thr = np.empty(max(g.m, 1), dtype=np.int32)
+    if off is not None:
+        cap = int(np.diff(_i32arr(off).astype(np.int64))[fr].sum())
+    else:
+        cap = g.m * nf  # upper bound when the caller gives no degrees
+    nxt = np.empty(max(cap, nf, 1), dtype=np.int32)
+    nwork, nnext = _i64(), _i64()
+    o = make_options(**opts)
+    st = Stats()
+    _check(_lib.alb_trace_round(g.handle, fr.ctypes.data, nf, ctypes.byref(o), bins.ctypes.data, work.ctypes.data,
+                                ctypes.byref(nwork), prefix.ctypes.data, hits.ctypes.data, thr.ctypes.data,
+                                nxt.ctypes.data, ctypes.byref(nnext), ctypes.byref(st)), "alb_trace_round")
+    k = nwork.value
+    return {"bins": bins, "work": work[:k].copy(), "prefix": prefix[:k + 1].copy(), "edge_hits": hits[:g.m],
+            "edge_thread": thr[:g.m], "next": nxt[:nnext.value].copy(), "stats": st.as_dict()}
+
+
+def algorithmic_bytes(kind: str, stats: dict, n: int = 0, iterations: int = 0) -> int:
+    """Bytes a push round must move whatever the schedule:
+      bfs, cc:  16 B per active vertex (worklist entry, two offsets, label)
+                 + 8 B per examined edge (column, destination label) + 4 B per push
+      sssp:     16 B per active vertex + 12 B per examined edge (adds the weight) + 4 B per push
+      pagerank: per iteration 8 B per edge (column, accumulator update) and 24 B per vertex
+                (rank, offsets, accumulator read and clear, rank write)."""
+    if kind in ("bfs", "cc"):
+        return 16 * stats["frontier_vertices"] + 8 * stats["edges_examined"] + 4 * stats["pushes"]
+    if kind == "sssp":
+        return 16 * stats["frontier_vertices"] + 12 * stats["edges_examined"] + 4 * stats["pushes"]
+    if kind == "pagerank":
+        return 8 * stats["edges_examined"] + 24 * n * iterations
+    raise KeyError(kind)

@@ -1,0 +1,804 @@
+// Host runtime behind include/alb.h: argument validation, the device-resident
+// graph, cached per-call workspaces and the round drivers (host loop or one
+// persistent cooperative launch).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/alb.h"
+#include "alb_internal.h"
+
+using namespace alb;
+
+namespace {
+
+thread_local std::string g_err;
+
+alb_status fail(alb_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess) {                                                                             \
+      if (e_ == hipErrorOutOfMemory) return fail(ALB_E_NOMEM, "%s: %s", #expr, hipGetErrorString(e_)); \
+      return fail(ALB_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));                                \
+    }                                                                                                   \
+  } while (0)
+
+struct Workspace {
+  uint32_t qcap = 0;
+  int32_t n = 0;
+  bool busy = false;
+  int32_t *q0 = nullptr, *q1 = nullptr, *work = nullptr, *stamp = nullptr, *labels = nullptr;
+  uint32_t *prefix = nullptr;
+  float *rank = nullptr, *acc = nullptr;
+  Ctl *ctl = nullptr;
+  Ctl *h_ctl = nullptr;  // pinned host mirror
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  size_t bytes = 0;
+
+  void release() {
+    (void)hipFree(q0);
+    (void)hipFree(q1);
+    (void)hipFree(work);
+    (void)hipFree(prefix);
+    (void)hipFree(stamp);
+    (void)hipFree(labels);
+    (void)hipFree(rank);
+    (void)hipFree(acc);
+    (void)hipFree(ctl);
+    if (h_ctl) (void)hipHostFree(h_ctl);
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+    *this = Workspace();
+  }
+};
+
+}  // namespace
+
+struct alb_graph_s {
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t max_deg = 0;
+  bool symmetric = false;
+  bool weighted = false;
+  int device = 0;
+  int cus = 0;
+  bool coop = false;
+  uint64_t clock_khz = 100000;
+  int32_t *d_off = nullptr, *d_col = nullptr, *d_w = nullptr;
+  hipStream_t stream = nullptr;
+  size_t graph_bytes = 0;
+  std::mutex mu;
+  std::vector<Workspace *> pool;
+};
+
+namespace {
+
+// --------------------------------------------------------------------------
+// CSR validation and host symmetrisation
+// --------------------------------------------------------------------------
+
+alb_status validate_csr(int32_t n, int64_t m, const int32_t *off, const int32_t *col, const int32_t *w) {
+  if (n < 1) return fail(ALB_E_INVAL, "n must be >= 1 (got %d)", n);
+  if (m < 0 || m >= ((int64_t)1 << 31)) return fail(ALB_E_INVAL, "m must be in [0, 2^31) (got %lld)", (long long)m);
+  if (!off) return fail(ALB_E_INVAL, "row_offsets is NULL");
+  if (m > 0 && !col) return fail(ALB_E_INVAL, "col is NULL");
+  if (off[0] != 0) return fail(ALB_E_INVAL, "row_offsets[0] must be 0 (got %d)", off[0]);
+  for (int32_t v = 0; v < n; ++v)
+    if (off[v + 1] < off[v]) return fail(ALB_E_INVAL, "row_offsets decreases at vertex %d", v);
+  if ((int64_t)off[n] != m) return fail(ALB_E_INVAL, "row_offsets[n] = %d differs from m = %lld", off[n], (long long)m);
+  for (int64_t p = 0; p < m; ++p)
+    if (col[p] < 0 || col[p] >= n) return fail(ALB_E_INVAL, "col[%lld] = %d out of range", (long long)p, col[p]);
+  if (w) {
+    int64_t wmax = 0;
+    for (int64_t p = 0; p < m; ++p) {
+      if (w[p] < 0) return fail(ALB_E_INVAL, "weights[%lld] = %d is negative", (long long)p, w[p]);
+      wmax = std::max<int64_t>(wmax, w[p]);
+    }
+    if (wmax * (int64_t)(n - 1) >= (int64_t)INT32_MAX)
+      return fail(ALB_E_RANGE, "max weight %lld x (n - 1) = %lld does not fit below INT32_MAX", (long long)wmax,
+                  (long long)(wmax * (int64_t)(n - 1)));
+  }
+  return ALB_OK;
+}
+
+template <class F>
+void parallel_rows(int32_t n, F f) {
+  unsigned t = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 65536) t = 1;
+  std::vector<std::thread> th;
+  std::atomic<int32_t> next{0};
+  auto body = [&] {
+    for (;;) {
+      int32_t b = next.fetch_add(4096);
+      if (b >= n) break;
+      int32_t e = std::min(n, b + 4096);
+      for (int32_t v = b; v < e; ++v) f(v);
+    }
+  };
+  for (unsigned i = 1; i < t; ++i) th.emplace_back(body);
+  body();
+  for (auto &x : th) x.join();
+}
+
+// Both directions of every edge, rows sorted, duplicates and self-loops removed.
+alb_status symmetrise(int32_t n, const int32_t *off, const int32_t *col, std::vector<int32_t> &soff,
+                      std::vector<int32_t> &scol) {
+  try {
+    int64_t m = off[n];
+    std::vector<int64_t> cnt((size_t)n + 1, 0);
+    for (int32_t u = 0; u < n; ++u) {
+      cnt[u + 1] += off[u + 1] - off[u];
+      for (int32_t p = off[u]; p < off[u + 1]; ++p) cnt[(size_t)col[p] + 1]++;
+    }
+    for (int32_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+    std::vector<int32_t> raw((size_t)cnt[n]);
+    std::vector<int64_t> cur(cnt.begin(), cnt.end() - 1);
+    for (int32_t u = 0; u < n; ++u)
+      for (int32_t p = off[u]; p < off[u + 1]; ++p) {
+        raw[(size_t)cur[u]++] = col[p];
+        raw[(size_t)cur[col[p]]++] = u;
+      }
+    (void)m;
+    std::vector<int64_t> keep((size_t)n, 0);
+    parallel_rows(n, [&](int32_t v) {
+      int32_t *b = raw.data() + cnt[v], *e = raw.data() + cnt[v + 1];
+      std::sort(b, e);
+      int64_t k = 0;
+      for (int32_t *p = b; p < e; ++p) {
+        if (*p == v) continue;
+        if (k > 0 && b[k - 1] == *p) continue;
+        b[k++] = *p;
+      }
+      keep[v] = k;
+    });
+    soff.assign((size_t)n + 1, 0);
+    int64_t total = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      soff[v] = (int32_t)total;
+      total += keep[v];
+      if (total >= ((int64_t)1 << 31)) return fail(ALB_E_INVAL, "symmetrised graph has 2^31 or more edges");
+    }
+    soff[n] = (int32_t)total;
+    scol.resize((size_t)total);
+    parallel_rows(n, [&](int32_t v) {
+      std::copy(raw.data() + cnt[v], raw.data() + cnt[v] + keep[v], scol.data() + soff[v]);
+    });
+  } catch (const std::bad_alloc &) {
+    return fail(ALB_E_NOMEM, "host allocation failed while symmetrising");
+  }
+  return ALB_OK;
+}
+
+// --------------------------------------------------------------------------
+// Workspaces
+// --------------------------------------------------------------------------
+
+struct Needs {
+  uint32_t qcap;
+  bool stamp, labels, pr;
+};
+
+template <class T>
+hipError_t dalloc(T **p, size_t count, size_t &bytes) {
+  size_t b = sizeof(T) * std::max<size_t>(count, 1);
+  hipError_t e = hipMalloc((void **)p, b);
+  if (e == hipSuccess) bytes += b;
+  return e;
+}
+
+alb_status ws_fill(Workspace *w, int32_t n, const Needs &nd) {
+  w->n = n;
+  w->qcap = nd.qcap;
+  HIP_TRY(dalloc(&w->q0, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->q1, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->work, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->prefix, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->stamp, (size_t)n, w->bytes));
+  HIP_TRY(dalloc(&w->labels, (size_t)n, w->bytes));
+  HIP_TRY(dalloc(&w->rank, (size_t)n, w->bytes));
+  HIP_TRY(dalloc(&w->acc, (size_t)n, w->bytes));
+  HIP_TRY(dalloc(&w->ctl, 1, w->bytes));
+  HIP_TRY(hipHostMalloc((void **)&w->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  for (auto &e : w->ev) HIP_TRY(hipEventCreate(&e));
+  return ALB_OK;
+}
+
+alb_status ws_acquire(alb_graph g, const Needs &nd, Workspace **out) {
+  std::lock_guard<std::mutex> lk(g->mu);
+  for (Workspace *w : g->pool)
+    if (!w->busy && w->qcap >= nd.qcap) {
+      w->busy = true;
+      *out = w;
+      return ALB_OK;
+    }
+  // grow a free one that is too small, else make a new one
+  Workspace *w = nullptr;
+  for (Workspace *x : g->pool)
+    if (!x->busy) {
+      w = x;
+      w->release();
+      break;
+    }
+  bool fresh = false;
+  if (!w) {
+    w = new (std::nothrow) Workspace();
+    if (!w) return fail(ALB_E_NOMEM, "host allocation failed");
+    fresh = true;
+  }
+  alb_status s = ws_fill(w, g->n, nd);
+  if (s != ALB_OK) {
+    std::string keep = g_err;
+    w->release();
+    if (!fresh) g->pool.erase(std::find(g->pool.begin(), g->pool.end(), w));
+    delete w;
+    g_err = keep;
+    return s;
+  }
+  if (fresh) g->pool.push_back(w);
+  w->busy = true;
+  *out = w;
+  return ALB_OK;
+}
+
+void ws_release(alb_graph g, Workspace *w) {
+  std::lock_guard<std::mutex> lk(g->mu);
+  w->busy = false;
+}
+
+struct WsGuard {
+  alb_graph g;
+  Workspace *w;
+  ~WsGuard() {
+    if (w) ws_release(g, w);
+  }
+};
+
+// --------------------------------------------------------------------------
+// Options
+// --------------------------------------------------------------------------
+
+alb_options defaults() {
+  alb_options o;
+  std::memset(&o, 0, sizeof o);
+  o.struct_size = sizeof(alb_options);
+  o.mode = ALB_MODE_ALB;
+  o.huge_threshold = -1;
+  o.wg_size = 256;
+  o.wave_cutoff = 64;
+  o.wg_cutoff = 0;
+  o.distribution = 0;
+  o.dedup = -1;
+  o.launch = ALB_LAUNCH_AUTO;
+  o.grid_wgs = 0;
+  o.worklist_capacity = 0;
+  o.stream = nullptr;
+  o.out_on_device = 0;
+  return o;
+}
+
+alb_status resolve_options(const alb_options *user, alb_options &o) {
+  o = defaults();
+  if (user) {
+    if (user->struct_size != sizeof(alb_options))
+      return fail(ALB_E_INVAL, "alb_options.struct_size = %u, expected %zu (use alb_options_init)", user->struct_size,
+                  sizeof(alb_options));
+    o = *user;
+  }
+  if (o.mode < ALB_MODE_ALB || o.mode > ALB_MODE_LB_ALL) return fail(ALB_E_INVAL, "bad mode %d", o.mode);
+  if (o.wg_size == 0) o.wg_size = 256;
+  if (!supported_wg(o.wg_size)) return fail(ALB_E_UNSUPPORTED, "wg_size %d not built (64, 256, 1024)", o.wg_size);
+  if (o.wave_cutoff == 0) o.wave_cutoff = 64;
+  if (o.wg_cutoff == 0) o.wg_cutoff = o.wg_size;
+  if (o.wave_cutoff < 1 || o.wg_cutoff < 1) return fail(ALB_E_INVAL, "cutoffs must be >= 1");
+  if (o.distribution != 0) return fail(ALB_E_UNSUPPORTED, "only the cyclic distribution (0) is implemented");
+  if (o.dedup < -1 || o.dedup > 1) return fail(ALB_E_INVAL, "bad dedup %d", o.dedup);
+  if (o.launch < ALB_LAUNCH_AUTO || o.launch > ALB_LAUNCH_PERSISTENT) return fail(ALB_E_INVAL, "bad launch %d", o.launch);
+  if (o.grid_wgs < 0) return fail(ALB_E_INVAL, "grid_wgs must be >= 0");
+  if (o.worklist_capacity < 0 || o.worklist_capacity > 0xfffffffeLL) return fail(ALB_E_INVAL, "bad worklist_capacity");
+  return ALB_OK;
+}
+
+// --------------------------------------------------------------------------
+// The round driver shared by every traversal
+// --------------------------------------------------------------------------
+
+struct Job {
+  OpKind op;
+  int32_t source = -1;        // BFS / SSSP
+  uint32_t nfront0 = 0;       // size of the round-0 worklist
+  bool identity_first = false;
+  bool all_rounds = false;     // PageRank
+  int32_t max_rounds = 0;
+  float damping = 0.85f;
+  const int32_t *h_frontier = nullptr;  // trace: explicit round-0 worklist (host)
+  int32_t *d_hits = nullptr, *d_thread = nullptr;
+  int8_t *d_bins = nullptr;
+  uint32_t qcap_min = 0;
+};
+
+struct RunOut {
+  Workspace *ws = nullptr;
+  uint32_t qcap = 0;
+  int32_t *d_labels = nullptr;  // where labels ended up on the device
+  float *d_rank = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+void zero_stats(alb_stats *st) {
+  if (st) std::memset(st, 0, sizeof *st);
+}
+
+alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_out, alb_stats *st, WsGuard &guard,
+                   RunOut &ro) {
+  HIP_TRY(hipSetDevice(g->device));
+  const hipStream_t stream = o.stream ? (hipStream_t)o.stream : g->stream;
+  ro.stream = stream;
+  const int wg = o.wg_size;
+
+  int per_cu = 0;
+  HIP_TRY(persistent_occupancy(job.op, wg, &per_cu));
+  if (per_cu < 1) return fail(ALB_E_DEVICE, "persistent kernel does not fit on a CU with wg_size %d", wg);
+  const int resident = per_cu * g->cus;
+  int launch = o.launch;
+  if (launch == ALB_LAUNCH_AUTO) launch = g->coop ? ALB_LAUNCH_PERSISTENT : ALB_LAUNCH_HOST_LOOP;
+  if (launch == ALB_LAUNCH_PERSISTENT && !g->coop)
+    return fail(ALB_E_UNSUPPORTED, "device does not support cooperative launches");
+  const int grid = o.grid_wgs > 0 ? o.grid_wgs : resident;
+  if (launch == ALB_LAUNCH_PERSISTENT && grid > resident)
+    return fail(ALB_E_INVAL, "grid_wgs %d exceeds the %d co-resident workgroups", grid, resident);
+  const int64_t T = (int64_t)grid * wg;
+
+  int64_t threshold;
+  if (o.mode == ALB_MODE_TWC_ONLY)
+    threshold = INT64_MAX;
+  else if (o.mode == ALB_MODE_LB_ALL)
+    threshold = 0;
+  else
+    threshold = o.huge_threshold < 0 ? T : o.huge_threshold;
+
+  bool dedup = false;
+  if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);
+  uint64_t qcap;
+  if (o.worklist_capacity > 0)
+    qcap = (uint64_t)o.worklist_capacity;
+  else if (job.op == OP_BFS || dedup || job.op == OP_PR)
+    qcap = (uint64_t)g->n;
+  else
+    qcap = (uint64_t)g->n + (uint64_t)g->m;
+  qcap = std::max<uint64_t>(qcap, std::max<uint64_t>(job.qcap_min, job.nfront0));
+  qcap = std::max<uint64_t>(qcap, 1);
+  if (qcap > 0xfffffffeULL) qcap = 0xfffffffeULL;
+
+  Needs nd{(uint32_t)qcap, dedup, true, job.op == OP_PR};
+  Workspace *ws = nullptr;
+  alb_status s = ws_acquire(g, nd, &ws);
+  if (s != ALB_OK) return s;
+  guard.g = g;
+  guard.w = ws;
+  ro.ws = ws;
+  ro.qcap = (uint32_t)qcap;
+
+  Args a;
+  std::memset(&a, 0, sizeof a);
+  a.off = g->d_off;
+  a.col = g->d_col;
+  a.w = g->d_w;
+  a.n = g->n;
+  a.qcap = (uint32_t)qcap;  // the workspace may be larger; honour the requested capacity
+  a.q0 = ws->q0;
+  a.q1 = ws->q1;
+  a.work = ws->work;
+  a.prefix = ws->prefix;
+  a.stamp = dedup ? ws->stamp : nullptr;
+  a.ctl = ws->ctl;
+  a.threshold = threshold;
+  a.c_wave = o.wave_cutoff;
+  a.c_wg = o.wg_cutoff;
+  a.identity_first = job.identity_first;
+  a.all_rounds = job.all_rounds;
+  a.max_rounds = job.max_rounds;
+  a.round = 0;
+  a.timeout_ticks = g->clock_khz * 1000ull * 30ull;  // 30 s per barrier wait
+  a.labels = nullptr;
+  if (job.op == OP_BFS || job.op == OP_SSSP || job.op == OP_CC)
+    a.labels = dev_out ? (int32_t *)dev_out : ws->labels;
+  if (job.op == OP_PR) {
+    a.rank = dev_out ? (float *)dev_out : ws->rank;
+    a.acc = ws->acc;
+    a.damping = job.damping;
+  }
+  a.hits = job.d_hits;
+  a.thread_of = job.d_thread;
+  a.bins = job.d_bins;
+  ro.d_labels = a.labels;
+  ro.d_rank = a.rank;
+
+  if (job.h_frontier && job.nfront0)
+    HIP_TRY(hipMemcpyAsync(ws->q0, job.h_frontier, sizeof(int32_t) * job.nfront0, hipMemcpyHostToDevice, stream));
+
+  HIP_TRY(hipEventRecord(ws->ev[0], stream));
+  HIP_TRY(launch_init(job.op, a, job.source, job.nfront0, stream));
+  HIP_TRY(hipEventRecord(ws->ev[1], stream));
+
+  int launches = 0;
+  int rounds = 0;
+  if (launch == ALB_LAUNCH_PERSISTENT) {
+    if (job.max_rounds > 0) {
+      HIP_TRY(launch_persistent(job.op, wg, grid, a, stream));
+      launches = 1;
+    }
+  } else {
+    for (int r = 0; r < job.max_rounds; ++r) {
+      a.round = r;
+      if (!job.all_rounds) {
+        // the worklist for round r is known on the device; stop if empty
+        HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (ws->h_ctl->overflow != 0xffffffffu) break;
+        if (ws->h_ctl->qcount[r % 3] == 0) break;
+      }
+      HIP_TRY(launch_twc(job.op, wg, grid, a, stream));
+      ++launches;
+      HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (ws->h_ctl->overflow != 0xffffffffu) break;
+      if ((ws->h_ctl->huge[r & 1] >> 32) != 0) {  // launch the LB kernel only when imbalance was found
+        HIP_TRY(launch_lb(job.op, wg, grid, a, stream));
+        ++launches;
+      }
+      if (job.op == OP_PR) {
+        HIP_TRY(launch_pr_update(wg, grid, a, stream));
+        ++launches;
+      }
+      rounds = r + 1;
+    }
+  }
+  HIP_TRY(hipEventRecord(ws->ev[2], stream));
+  HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const Ctl &c = *ws->h_ctl;
+  if (c.abort) return fail(ALB_E_DEVICE, "a grid barrier wait timed out; the device run was abandoned");
+  if (c.overflow != 0xffffffffu)
+    return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", a.qcap, c.overflow);
+  if (launch == ALB_LAUNCH_PERSISTENT) rounds = (int)c.rounds;
+  if (!job.all_rounds && job.max_rounds > 1 && rounds >= job.max_rounds && c.qcount[rounds % 3] != 0)
+    return fail(ALB_E_DEVICE, "no convergence within %d rounds", job.max_rounds);
+
+  if (st) {
+    float ms_all = 0.f, ms_k = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms_all, ws->ev[0], ws->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&ms_k, ws->ev[1], ws->ev[2]));
+    st->rounds = rounds;
+    st->kernel_launches = launches;
+    st->launched_threads = T;
+    st->huge_threshold = threshold;
+    st->frontier_vertices = (int64_t)c.st_frontier;
+    st->edges_examined = (int64_t)(c.st_edges_twc + c.st_edges_lb);
+    st->huge_vertices = (int64_t)c.st_huge_v;
+    st->huge_edges = (int64_t)c.st_edges_lb;
+    st->pushes = (int64_t)c.st_pushes;
+    st->device_ms = ms_all;
+    st->kernel_ms = ms_k;
+  }
+  return ALB_OK;
+}
+
+alb_status check_graph(alb_graph g) {
+  if (!g) return fail(ALB_E_INVAL, "graph handle is NULL");
+  return ALB_OK;
+}
+
+// Traversal entry: run, then copy labels out (host outputs are synchronous).
+alb_status traverse(alb_graph g, const Job &job, void *out, size_t elem, const alb_options *user, alb_stats *st) {
+  alb_options o;
+  alb_status s = resolve_options(user, o);
+  if (s != ALB_OK) return s;
+  WsGuard guard{nullptr, nullptr};
+  RunOut ro;
+  s = run_job(g, job, o, o.out_on_device ? out : nullptr, st, guard, ro);
+  if (s != ALB_OK) return s;
+  if (!o.out_on_device) {
+    const void *src = job.op == OP_PR ? (const void *)ro.d_rank : (const void *)ro.d_labels;
+    HIP_TRY(hipMemcpyAsync(out, src, elem * (size_t)g->n, hipMemcpyDeviceToHost, ro.stream));
+    HIP_TRY(hipStreamSynchronize(ro.stream));
+  }
+  return ALB_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+
+extern "C" {
+
+alb_status alb_options_init(alb_options *opt) {
+  if (!opt) return fail(ALB_E_INVAL, "options pointer is NULL");
+  *opt = defaults();
+  return ALB_OK;
+}
+
+const char *alb_status_str(alb_status s) {
+  switch (s) {
+    case ALB_OK: return "ALB_OK";
+    case ALB_E_INVAL: return "ALB_E_INVAL";
+    case ALB_E_NOMEM: return "ALB_E_NOMEM";
+    case ALB_E_DEVICE: return "ALB_E_DEVICE";
+    case ALB_E_RANGE: return "ALB_E_RANGE";
+    case ALB_E_OVERFLOW: return "ALB_E_OVERFLOW";
+    case ALB_E_UNSUPPORTED: return "ALB_E_UNSUPPORTED";
+  }
+  return "ALB_E_UNKNOWN";
+}
+
+const char *alb_last_error(void) { return g_err.c_str(); }
+
+alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, const int32_t *col,
+                            const int32_t *weights, uint32_t flags, alb_graph *out) {
+  if (!out) return fail(ALB_E_INVAL, "output handle pointer is NULL");
+  *out = nullptr;
+  if (flags & ~(uint32_t)(ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) return fail(ALB_E_INVAL, "unknown flags 0x%x", flags);
+  alb_status s = validate_csr(n, m, row_offsets, col, weights);
+  if (s != ALB_OK) return s;
+
+  std::vector<int32_t> soff, scol;
+  const int32_t *off = row_offsets, *cl = col, *w = weights;
+  int64_t mm = m;
+  if (flags & ALB_BUILD_SYMMETRIC) {
+    s = symmetrise(n, row_offsets, col, soff, scol);
+    if (s != ALB_OK) return s;
+    off = soff.data();
+    cl = scol.data();
+    mm = (int64_t)scol.size();
+    w = nullptr;
+  }
+  int32_t maxd = 0;
+  for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, off[v + 1] - off[v]);
+
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  alb_graph g = new (std::nothrow) alb_graph_s();
+  if (!g) return fail(ALB_E_NOMEM, "host allocation failed");
+  auto cleanup = [&](alb_status st) {
+    (void)hipFree(g->d_off);
+    (void)hipFree(g->d_col);
+    (void)hipFree(g->d_w);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+    return st;
+  };
+  g->n = n;
+  g->m = mm;
+  g->max_deg = maxd;
+  g->symmetric = (flags & (ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) != 0;
+  g->weighted = (w != nullptr);
+  g->device = dev;
+  int attr = 0;
+  hipError_t e;
+  if ((e = hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return cleanup(fail(ALB_E_DEVICE, "hipDeviceGetAttribute: %s", hipGetErrorString(e)));
+  if (hipDeviceGetAttribute(&attr, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess) g->coop = attr != 0;
+  if (hipDeviceGetAttribute(&attr, hipDeviceAttributeWallClockRate, dev) == hipSuccess && attr > 0)
+    g->clock_khz = (uint64_t)attr;
+  size_t bytes = 0;
+  if ((e = dalloc(&g->d_off, (size_t)n + 1, bytes)) != hipSuccess ||
+      (e = dalloc(&g->d_col, (size_t)mm, bytes)) != hipSuccess ||
+      (w && (e = dalloc(&g->d_w, (size_t)mm, bytes)) != hipSuccess))
+    return cleanup(fail(e == hipErrorOutOfMemory ? ALB_E_NOMEM : ALB_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e)));
+  g->graph_bytes = bytes;
+  if ((e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess)
+    return cleanup(fail(ALB_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
+  if ((e = hipMemcpy(g->d_off, off, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+      (mm && (e = hipMemcpy(g->d_col, cl, sizeof(int32_t) * (size_t)mm, hipMemcpyHostToDevice)) != hipSuccess) ||
+      (w && mm && (e = hipMemcpy(g->d_w, w, sizeof(int32_t) * (size_t)mm, hipMemcpyHostToDevice)) != hipSuccess))
+    return cleanup(fail(ALB_E_DEVICE, "hipMemcpy: %s", hipGetErrorString(e)));
+  *out = g;
+  return ALB_OK;
+}
+
+alb_status alb_graph_destroy(alb_graph g) {
+  if (!g) return ALB_OK;
+  (void)hipSetDevice(g->device);
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  for (Workspace *w : g->pool) {
+    w->release();
+    delete w;
+  }
+  (void)hipFree(g->d_off);
+  (void)hipFree(g->d_col);
+  (void)hipFree(g->d_w);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+  return ALB_OK;
+}
+
+alb_status alb_graph_info(alb_graph g, int32_t *n, int64_t *m, int32_t *max_out_degree, size_t *device_bytes) {
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (n) *n = g->n;
+  if (m) *m = g->m;
+  if (max_out_degree) *max_out_degree = g->max_deg;
+  if (device_bytes) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    size_t b = g->graph_bytes;
+    for (Workspace *w : g->pool) b += w->bytes;
+    *device_bytes = b;
+  }
+  return ALB_OK;
+}
+
+alb_status alb_bfs(alb_graph g, int32_t source, int32_t *level, const alb_options *opt, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (!level) return fail(ALB_E_INVAL, "level is NULL");
+  if (source < 0 || source >= g->n) return fail(ALB_E_INVAL, "source %d out of range [0, %d)", source, g->n);
+  Job job;
+  job.op = OP_BFS;
+  job.source = source;
+  job.nfront0 = 1;
+  job.max_rounds = g->n + 1;
+  s = traverse(g, job, level, sizeof(int32_t), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_sssp(alb_graph g, int32_t source, int32_t *dist, const alb_options *opt, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (!dist) return fail(ALB_E_INVAL, "dist is NULL");
+  if (!g->weighted) return fail(ALB_E_INVAL, "alb_sssp needs a graph created with weights");
+  if (source < 0 || source >= g->n) return fail(ALB_E_INVAL, "source %d out of range [0, %d)", source, g->n);
+  Job job;
+  job.op = OP_SSSP;
+  job.source = source;
+  job.nfront0 = 1;
+  job.max_rounds = g->n + 1;
+  s = traverse(g, job, dist, sizeof(int32_t), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_cc(alb_graph g, int32_t *label, const alb_options *opt, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (!label) return fail(ALB_E_INVAL, "label is NULL");
+  if (!g->symmetric) return fail(ALB_E_INVAL, "alb_cc needs a symmetric graph (ALB_SYMMETRIC or ALB_BUILD_SYMMETRIC)");
+  Job job;
+  job.op = OP_CC;
+  job.identity_first = true;
+  job.nfront0 = (uint32_t)g->n;
+  job.max_rounds = g->n + 1;
+  s = traverse(g, job, label, sizeof(int32_t), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_pagerank(alb_graph g, float damping, int32_t iterations, float *rank, const alb_options *opt,
+                        alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (!rank) return fail(ALB_E_INVAL, "rank is NULL");
+  if (!(damping > 0.0f && damping < 1.0f)) return fail(ALB_E_INVAL, "damping must be in (0, 1)");
+  if (iterations < 0) return fail(ALB_E_INVAL, "iterations must be >= 0");
+  Job job;
+  job.op = OP_PR;
+  job.all_rounds = true;
+  job.nfront0 = (uint32_t)g->n;
+  job.max_rounds = iterations;
+  job.damping = damping;
+  s = traverse(g, job, rank, sizeof(float), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_trace_round(alb_graph g, const int32_t *frontier, int64_t nf, const alb_options *user, int8_t *bins,
+                           int32_t *work, int64_t *nwork, int64_t *prefix, int32_t *edge_hits, int32_t *edge_thread,
+                           int32_t *next, int64_t *nnext, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (nf < 1 || nf > g->n) return fail(ALB_E_INVAL, "nf must be in [1, n]");
+  if (!frontier || !bins || !work || !nwork || !prefix || !edge_hits || !edge_thread || !nnext)
+    return fail(ALB_E_INVAL, "a required pointer is NULL");
+  std::vector<int32_t> hoff((size_t)g->n + 1);
+  HIP_TRY(hipSetDevice(g->device));
+  HIP_TRY(hipMemcpy(hoff.data(), g->d_off, sizeof(int32_t) * hoff.size(), hipMemcpyDeviceToHost));
+  int64_t sumdeg = 0;
+  for (int64_t i = 0; i < nf; ++i) {
+    if (frontier[i] < 0 || frontier[i] >= g->n) return fail(ALB_E_INVAL, "frontier[%lld] out of range", (long long)i);
+    sumdeg += hoff[frontier[i] + 1] - hoff[frontier[i]];
+  }
+  if (sumdeg >= 0xfffffffeLL) return fail(ALB_E_INVAL, "frontier has too many edges for one traced round");
+  alb_options o;
+  s = resolve_options(user, o);
+  if (s != ALB_OK) return s;
+  o.out_on_device = 0;
+  o.worklist_capacity = 0;
+  size_t mm = (size_t)std::max<int64_t>(g->m, 1);
+  int32_t *d_hits = nullptr, *d_thread = nullptr;
+  int8_t *d_bins = nullptr;
+  size_t scratch = 0;
+  auto free_all = [&] {
+    (void)hipFree(d_hits);
+    (void)hipFree(d_thread);
+    (void)hipFree(d_bins);
+  };
+  hipError_t e;
+  if ((e = dalloc(&d_hits, mm, scratch)) != hipSuccess || (e = dalloc(&d_thread, mm, scratch)) != hipSuccess ||
+      (e = dalloc(&d_bins, (size_t)nf, scratch)) != hipSuccess) {
+    free_all();
+    return fail(ALB_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+  }
+  Job job;
+  job.op = OP_RECORD;
+  job.nfront0 = (uint32_t)nf;
+  job.max_rounds = 1;
+  job.h_frontier = frontier;
+  job.d_hits = d_hits;
+  job.d_thread = d_thread;
+  job.d_bins = d_bins;
+  job.qcap_min = (uint32_t)std::max<int64_t>(sumdeg, nf);
+  hipStream_t stream = o.stream ? (hipStream_t)o.stream : g->stream;
+  if ((e = hipMemsetAsync(d_hits, 0, sizeof(int32_t) * mm, stream)) != hipSuccess ||
+      (e = hipMemsetAsync(d_thread, 0xff, sizeof(int32_t) * mm, stream)) != hipSuccess) {
+    free_all();
+    return fail(ALB_E_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  WsGuard guard{nullptr, nullptr};
+  RunOut ro;
+  s = run_job(g, job, o, nullptr, stats, guard, ro);
+  if (s != ALB_OK) {
+    free_all();
+    zero_stats(stats);
+    return s;
+  }
+  Workspace *ws = ro.ws;
+  const Ctl &c = *ws->h_ctl;
+  const uint32_t vh = (uint32_t)(c.huge[0] >> 32), ehuge = (uint32_t)c.huge[0];
+  const uint32_t nn = std::min(c.qcount[1], ro.qcap);
+  std::vector<uint32_t> hp(vh);
+  bool ok = true;
+  ok = ok && hipMemcpy(bins, d_bins, (size_t)nf, hipMemcpyDeviceToHost) == hipSuccess;
+  ok = ok && (vh == 0 || hipMemcpy(work, ws->work, sizeof(int32_t) * vh, hipMemcpyDeviceToHost) == hipSuccess);
+  ok = ok && (vh == 0 || hipMemcpy(hp.data(), ws->prefix, sizeof(uint32_t) * vh, hipMemcpyDeviceToHost) == hipSuccess);
+  ok = ok && (g->m == 0 || hipMemcpy(edge_hits, d_hits, sizeof(int32_t) * g->m, hipMemcpyDeviceToHost) == hipSuccess);
+  ok = ok && (g->m == 0 || hipMemcpy(edge_thread, d_thread, sizeof(int32_t) * g->m, hipMemcpyDeviceToHost) == hipSuccess);
+  ok = ok && (!next || nn == 0 || hipMemcpy(next, ws->q1, sizeof(int32_t) * nn, hipMemcpyDeviceToHost) == hipSuccess);
+  free_all();
+  if (!ok) {
+    zero_stats(stats);
+    return fail(ALB_E_DEVICE, "copy-out of the traced round failed");
+  }
+  *nwork = vh;
+  for (uint32_t j = 0; j < vh; ++j) prefix[j] = hp[j];
+  prefix[vh] = ehuge;
+  *nnext = nn;
+  return ALB_OK;
+}
+
+}  // extern "C"

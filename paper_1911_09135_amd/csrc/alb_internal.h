@@ -1,0 +1,72 @@
+// Internal interface between the host runtime (alb_api.cpp) and the device
+// kernels (alb_kernels.hip).  Plain structs of device pointers and sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace alb {
+
+constexpr int32_t kInf = 0x7fffffff;
+
+// Per-call control block in device memory.  Counters rotate by round so that
+// one round can clear the counter two rounds ahead without a separate launch.
+struct Ctl {
+  uint32_t qcount[3];             // worklist sizes: round r reads [r % 3], pushes into [(r + 1) % 3]
+  uint32_t overflow;              // first round in which a worklist overflowed (0xffffffff: none)
+  unsigned long long huge[2];     // round r: (count << 32) | edge total of the huge worklist, [r & 1]
+  unsigned long long bar_count;   // grid barrier arrivals (monotone within a launch)
+  uint32_t abort;                 // a barrier wait timed out; every workgroup leaves
+  uint32_t rounds;                // rounds completed (written by workgroup 0)
+  unsigned long long st_frontier; // statistics, summed over rounds
+  unsigned long long st_edges_twc;
+  unsigned long long st_edges_lb;
+  unsigned long long st_huge_v;
+  unsigned long long st_pushes;
+  double dangling[2];             // PageRank: rank mass without out-edges, iteration it in [it & 1]
+};
+
+enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4 };
+
+// Everything a traversal kernel reads.  Passed by value.
+struct Args {
+  const int32_t *off;  // n + 1
+  const int32_t *col;  // m
+  const int32_t *w;    // m (SSSP)
+  int32_t n;
+  uint32_t qcap;        // capacity of each worklist and of work / prefix
+  int32_t *q0;          // worklists (double buffered)
+  int32_t *q1;
+  int32_t *work;        // huge worklist (Algorithm 1 `work`)
+  uint32_t *prefix;     // its exclusive degree prefix (`prefixWork`)
+  int32_t *stamp;       // dedup stamps (round of the last push), or null
+  Ctl *ctl;
+  int64_t threshold;    // huge iff degree >= threshold (and degree >= 1)
+  int32_t c_wave;       // TWC cutoffs
+  int32_t c_wg;
+  int32_t identity_first;  // round 0 works on every vertex (no worklist)
+  int32_t all_rounds;      // every round works on every vertex (PageRank)
+  int32_t max_rounds;
+  int32_t round;           // host-loop mode: the round this launch runs
+  uint64_t timeout_ticks;  // barrier wait limit in wall-clock ticks
+  // operator state
+  int32_t *labels;      // BFS level / SSSP dist / CC label
+  float *rank;          // PageRank
+  float *acc;
+  float damping;
+  int32_t *hits;        // trace operator
+  int32_t *thread_of;
+  int8_t *bins;
+};
+
+// Host-callable launchers (alb_kernels.hip).  All return the launch status.
+hipError_t launch_init(OpKind op, const Args &a, int32_t source, uint32_t nfront0, hipStream_t s);
+hipError_t launch_twc(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
+hipError_t launch_lb(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
+hipError_t launch_pr_update(int wg, int grid, const Args &a, hipStream_t s);
+hipError_t launch_persistent(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
+// Workgroups of `wg` threads that fit on one CU for the persistent kernel of `op`.
+hipError_t persistent_occupancy(OpKind op, int wg, int *blocks_per_cu);
+bool supported_wg(int wg);
+
+}  // namespace alb

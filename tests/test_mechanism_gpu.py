@@ -1,0 +1,125 @@
+"""One traced round on the GPU against the oracle's Algorithm 1 / Algorithm 2
+rules: bins, the huge worklist and its prefix, the cyclic thread of every huge
+edge, TWC locality, each frontier edge processed exactly once, and the
+wave-aggregated pushes."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def alb():
+    from paper_1911_09135_amd import alb as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def hubgraph():
+    hubs = {0: 30000, 17: 4096, 99: 4095, 1234: 700, 5000: 64, 5001: 63, 5002: 65, 7000: 255, 7001: 256, 7002: 257}
+    return gg.hub_graph(40000, hubs, 3, seed=11)
+
+
+def check_round(alb, g, dg, frontier, **opts):
+    r = alb.trace_round(dg, frontier, off=g.off, **opts)
+    st = r["stats"]
+    T = st["launched_threads"]
+    t = st["huge_threshold"]
+    wg = opts.get("wg_size", 256)
+    c_wave = opts.get("wave_cutoff", 64)
+    c_wg = opts.get("wg_cutoff", wg)
+    bins_ref, work_ref = oracle.inspect(frontier, g.off, t, c_wave, c_wg)
+    # Algorithm 1: the same bin for every entry and the same huge set
+    assert np.array_equal(r["bins"], bins_ref)
+    work = r["work"]
+    assert np.array_equal(np.sort(work), np.sort(work_ref))
+    # prefixWork: exclusive scan of the huge degrees in the device's worklist order
+    assert np.array_equal(r["prefix"], oracle.prefix_work(work, g.off))
+    # every edge of the frontier processed exactly once, no other edge touched
+    deg = g.degrees()
+    expect_hits = np.zeros(g.m, np.int32)
+    for v in frontier:
+        expect_hits[g.off[v]:g.off[v + 1]] += 1
+    assert np.array_equal(r["edge_hits"], expect_hits)
+    # Algorithm 2, cyclic distribution: huge edge k on global thread k mod T
+    src, pos, thr = oracle.lb_edges(work, r["prefix"], g.off, T)
+    assert np.array_equal(r["edge_thread"][pos], thr.astype(np.int32))
+    assert np.array_equal(src, np.repeat(work, deg[work]))
+    # TWC: every other edge stays inside the workgroup that owns the vertex's chunk;
+    # wavefront-bin vertices inside one wavefront, workgroup-bin vertices in one workgroup
+    G = T // wg
+    for i, v in enumerate(frontier):
+        b = r["bins"][i]
+        if b == 3 or deg[v] == 0:
+            continue
+        th = r["edge_thread"][g.off[v]:g.off[v + 1]]
+        wg_expected = (i // wg) % G
+        assert np.all(th // wg == wg_expected), (i, v, b)
+        if b == 1:
+            assert len(np.unique(th // 64)) == 1
+    # pushes: every processed edge pushed its destination once
+    dsts = np.concatenate([g.col[g.off[v]:g.off[v + 1]] for v in frontier]) if len(frontier) else np.zeros(0)
+    assert np.array_equal(np.sort(r["next"]), np.sort(dsts))
+    assert st["edges_examined"] == int(deg[frontier].sum())
+    assert st["huge_vertices"] == len(work_ref)
+    assert st["huge_edges"] == int(deg[work_ref].sum())
+    return r
+
+
+@pytest.mark.parametrize("launch", ["host", "persistent"])
+@pytest.mark.parametrize("wg", [64, 256, 1024])
+def test_trace_matrix(alb, hubgraph, launch, wg):
+    g = hubgraph
+    dg = alb.Graph(g.off, g.col)
+    rng = np.random.default_rng(wg)
+    fronts = [
+        np.array([0], np.int32),                                     # one huge vertex (the first-round case)
+        np.arange(g.n, dtype=np.int32),                              # everything, many chunks
+        rng.choice(g.n, 12345, replace=False).astype(np.int32),      # ragged tail
+        np.array([5000, 5001, 5002, 7000, 7001, 7002, 17, 99], np.int32),
+    ]
+    for fr in fronts:
+        for thr in [0, 1, 64, 65, 256, 4096, 30000, 30001, None]:
+            check_round(alb, g, dg, fr, threshold=thr, wg_size=wg, launch=launch)
+        check_round(alb, g, dg, fr, mode="twc", wg_size=wg, launch=launch)
+        check_round(alb, g, dg, fr, mode="lb_all", wg_size=wg, launch=launch)
+    dg.close()
+
+
+def test_trace_small_grid_many_sweeps(alb, hubgraph):
+    """T = 64 * 2 threads: each thread walks hundreds of cyclic sweeps."""
+    g = hubgraph
+    dg = alb.Graph(g.off, g.col)
+    fr = np.array([0, 17, 99, 1234, 3], np.int32)
+    for launch in ("host", "persistent"):
+        r = check_round(alb, g, dg, fr, threshold=64, wg_size=64, grid_wgs=2, launch=launch)
+        assert r["stats"]["launched_threads"] == 128
+    dg.close()
+
+
+def test_trace_cutoffs(alb, hubgraph):
+    g = hubgraph
+    dg = alb.Graph(g.off, g.col)
+    fr = np.arange(0, g.n, 3, dtype=np.int32)
+    check_round(alb, g, dg, fr, threshold=5000, wave_cutoff=8, wg_cutoff=100)
+    check_round(alb, g, dg, fr, threshold=5000, wave_cutoff=1, wg_cutoff=2)
+    check_round(alb, g, dg, fr, mode="twc", wave_cutoff=32, wg_cutoff=32)
+    dg.close()
+
+
+def test_two_sources_per_wave_at_default_threshold(alb):
+    """With threshold >= 64 a wavefront's 64 consecutive huge edges belong to at
+    most two sources (Section 4.1): checked on the traced thread assignment."""
+    g = gg.hub_graph(20000, {i * 37: 64 + 13 * i for i in range(60)}, 1, seed=5)
+    dg = alb.Graph(g.off, g.col)
+    fr = np.array([i * 37 for i in range(60)], np.int32)
+    r = check_round(alb, g, dg, fr, threshold=64)
+    src, pos, thr = oracle.lb_edges(r["work"], r["prefix"], g.off, r["stats"]["launched_threads"])
+    waves = thr // 64
+    for w in np.unique(waves):
+        assert len(np.unique(src[waves == w])) <= 2
+    dg.close()
