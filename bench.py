@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--launch", default="auto")
     ap.add_argument("--sweep", action="store_true", help="also sweep the threshold over powers of two")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only-alb", action="store_true", help="skip the TWC-only comparison (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -81,6 +84,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 18  # int32 elements
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(args.steps, 1)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                          "launches": max(args.steps, 1)}))
+        return
 
     import graphgen as gg
     from paper_1911_09135_amd import alb
@@ -107,8 +121,11 @@ def main():
     dist = out.cpu().numpy()
     reached = dist < alb.INF
     m_reached = int(g.degrees()[reached].sum())
-    twc_sec, twc_stats = measure(dict(base_opts, mode="twc"), "twc_only")
-    twc_ok = np.array_equal(out.cpu().numpy(), dist)
+    if args.only_alb:
+        twc_sec, twc_stats, twc_ok = sec, stats, None
+    else:
+        twc_sec, twc_stats = measure(dict(base_opts, mode="twc"), "twc_only")
+        twc_ok = bool(np.array_equal(out.cpu().numpy(), dist))
 
     # roofline of the traversal kernel: algorithmic bytes of each launch over the
     # launch's own device time (HIP events recorded on the kernel's stream)
@@ -156,7 +173,7 @@ def main():
                    "launched_threads": stats[-1]["launched_threads"], "rounds": stats[-1]["rounds"],
                    "kernel_launches": stats[-1]["kernel_launches"]},
         "twc_only": {"value": round(args.steps * m_reached / twc_sec / 1e9, 3),
-                     "ms_per_step": round(1e3 * twc_sec / args.steps, 4), "same_result": bool(twc_ok),
+                     "ms_per_step": round(1e3 * twc_sec / args.steps, 4), "same_result": twc_ok,
                      "kernel_ms": round(float(np.mean([s["kernel_ms"] for s in twc_stats])), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

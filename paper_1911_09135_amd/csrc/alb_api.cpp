@@ -1,6 +1,6 @@
 // Host runtime behind include/alb.h: argument validation, the device-resident
 // graph, cached per-call workspaces and the round drivers (host loop or one
-// persistent cooperative launch).
+// persistent launch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,7 +8,10 @@
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <string>
@@ -49,7 +52,8 @@ struct Workspace {
   bool busy = false;
   int32_t *q0 = nullptr, *q1 = nullptr, *work = nullptr, *stamp = nullptr, *labels = nullptr;
   uint32_t *prefix = nullptr;
-  float *rank = nullptr, *acc = nullptr;
+  float *rank = nullptr;
+  unsigned long long *acc = nullptr;
   Ctl *ctl = nullptr;
   Ctl *h_ctl = nullptr;  // pinned host mirror
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -82,7 +86,6 @@ struct alb_graph_s {
   bool weighted = false;
   int device = 0;
   int cus = 0;
-  bool coop = false;
   uint64_t clock_khz = 100000;
   int32_t *d_off = nullptr, *d_col = nullptr, *d_w = nullptr;
   hipStream_t stream = nullptr;
@@ -322,6 +325,38 @@ alb_status resolve_options(const alb_options *user, alb_options &o) {
 // The round driver shared by every traversal
 // --------------------------------------------------------------------------
 
+// Longest wait at a grid barrier before the persistent launch gives up
+// (ALB_BARRIER_TIMEOUT_MS, default 30 s).  Every wave leaves in bounded time.
+uint64_t barrier_timeout_ms() {
+  const char *e = getenv("ALB_BARRIER_TIMEOUT_MS");
+  if (e) {
+    long long v = atoll(e);
+    if (v > 0) return (uint64_t)v;
+  }
+  return 30000;
+}
+
+// Upper bound on co-resident workgroups of the persistent kernel (op, wg):
+// the occupancy calculator's per-CU figure times the CU count.  The
+// persistent launch uses this as its grid; membership inside the launch
+// decides how many workgroups actually take part.
+std::mutex g_res_mu;
+std::map<std::tuple<int, int, int>, int> g_res;
+
+alb_status resident_workgroups(alb_graph g, OpKind op, int wg, int *out) {
+  const auto key = std::make_tuple(g->device, (int)op, wg);
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  auto it = g_res.find(key);
+  if (it == g_res.end()) {
+    int per_cu = 0;
+    HIP_TRY(persistent_occupancy(op, wg, &per_cu));
+    if (per_cu < 1) return fail(ALB_E_DEVICE, "persistent kernel does not fit on a CU with wg_size %d", wg);
+    it = g_res.emplace(key, per_cu * g->cus).first;
+  }
+  *out = it->second;
+  return ALB_OK;
+}
+
 struct Job {
   OpKind op;
   int32_t source = -1;        // BFS / SSSP
@@ -355,26 +390,27 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   ro.stream = stream;
   const int wg = o.wg_size;
 
-  int per_cu = 0;
-  HIP_TRY(persistent_occupancy(job.op, wg, &per_cu));
-  if (per_cu < 1) return fail(ALB_E_DEVICE, "persistent kernel does not fit on a CU with wg_size %d", wg);
-  const int resident = per_cu * g->cus;
+  int resident = 0;
+  alb_status rs = resident_workgroups(g, job.op, wg, &resident);
+  if (rs != ALB_OK) return rs;
   int launch = o.launch;
-  if (launch == ALB_LAUNCH_AUTO) launch = g->coop ? ALB_LAUNCH_PERSISTENT : ALB_LAUNCH_HOST_LOOP;
-  if (launch == ALB_LAUNCH_PERSISTENT && !g->coop)
-    return fail(ALB_E_UNSUPPORTED, "device does not support cooperative launches");
+  if (launch == ALB_LAUNCH_AUTO) launch = ALB_LAUNCH_PERSISTENT;
   const int grid = o.grid_wgs > 0 ? o.grid_wgs : resident;
-  if (launch == ALB_LAUNCH_PERSISTENT && grid > resident)
-    return fail(ALB_E_INVAL, "grid_wgs %d exceeds the %d co-resident workgroups", grid, resident);
-  const int64_t T = (int64_t)grid * wg;
+  if (grid > resident)
+    return fail(ALB_E_INVAL, "grid_wgs %d exceeds the %d workgroups the device can hold", grid, resident);
+  // T: the host loop launches `grid` workgroups; the persistent launch learns
+  // its member count on the device (reported after the run)
+  int64_t T = (int64_t)grid * wg;
 
   int64_t threshold;
   if (o.mode == ALB_MODE_TWC_ONLY)
     threshold = INT64_MAX;
   else if (o.mode == ALB_MODE_LB_ALL)
     threshold = 0;
+  else if (o.huge_threshold >= 0)
+    threshold = o.huge_threshold;
   else
-    threshold = o.huge_threshold < 0 ? T : o.huge_threshold;
+    threshold = launch == ALB_LAUNCH_PERSISTENT ? -1 : T;  // the launched thread count
 
   bool dedup = false;
   if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);
@@ -418,7 +454,8 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.all_rounds = job.all_rounds;
   a.max_rounds = job.max_rounds;
   a.round = 0;
-  a.timeout_ticks = g->clock_khz * 1000ull * 30ull;  // 30 s per barrier wait
+  a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
+  a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);  // 10 us without a new member
   a.labels = nullptr;
   if (job.op == OP_BFS || job.op == OP_SSSP || job.op == OP_CC)
     a.labels = dev_out ? (int32_t *)dev_out : ws->labels;
@@ -477,10 +514,30 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   const Ctl &c = *ws->h_ctl;
-  if (c.abort) return fail(ALB_E_DEVICE, "a grid barrier wait timed out; the device run was abandoned");
+  if (c.abort)
+    return fail(ALB_E_DEVICE,
+                "a grid barrier wait timed out in round %u (%llu of %llu arrivals seen, %u members); the device "
+                "run was abandoned",
+                c.diag_round, c.diag_seen, c.diag_target, c.n_members);
+  if (launch == ALB_LAUNCH_PERSISTENT && launches) {
+    T = (int64_t)c.n_members * wg;
+    threshold = c.threshold_used;
+  }
   if (c.overflow != 0xffffffffu)
     return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", a.qcap, c.overflow);
-  if (launch == ALB_LAUNCH_PERSISTENT) rounds = (int)c.rounds;
+  if (launch == ALB_LAUNCH_PERSISTENT) {
+    rounds = (int)c.rounds;
+    if (getenv("ALB_TIMELINE")) {  // profiling aid: per-round phase times on stderr
+      const double us = 1000.0 / (double)g->clock_khz;
+      fprintf(stderr, "[alb] op %d members %u threshold %lld\n", (int)job.op, c.n_members, (long long)threshold);
+      for (int r = 0; r < std::min(rounds, kTimeline); ++r) {
+        const unsigned long long *t = &c.tl[4 * r];
+        fprintf(stderr, "[alb] round %2d  |F| %9u  huge %7u  twc %8.1f us  lb %8.1f us\n", r,
+                (unsigned)(t[3] & 0xffffffffu), (unsigned)(t[3] >> 32), (double)(t[1] - t[0]) * us,
+                (double)(t[2] - t[1]) * us);
+      }
+    }
+  }
   if (!job.all_rounds && job.max_rounds > 1 && rounds >= job.max_rounds && c.qcount[rounds % 3] != 0)
     return fail(ALB_E_DEVICE, "no convergence within %d rounds", job.max_rounds);
 
@@ -598,7 +655,6 @@ alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, co
   hipError_t e;
   if ((e = hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return cleanup(fail(ALB_E_DEVICE, "hipDeviceGetAttribute: %s", hipGetErrorString(e)));
-  if (hipDeviceGetAttribute(&attr, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess) g->coop = attr != 0;
   if (hipDeviceGetAttribute(&attr, hipDeviceAttributeWallClockRate, dev) == hipSuccess && attr > 0)
     g->clock_khz = (uint64_t)attr;
   size_t bytes = 0;

@@ -8,23 +8,45 @@
 namespace alb {
 
 constexpr int32_t kInf = 0x7fffffff;
+// PageRank sums: an fp32 contribution c is added as round(c * 2^60) to a
+// 64-bit integer.  Integer addition is exact and associative, so the sum of a
+// vertex's in-contributions does not depend on the order of the atomics, and
+// the rounding is 2^-61 per term.  Every partial sum is at most the total rank
+// mass (1), far below 2^64 / 2^60.
+constexpr double kFixScale = 1152921504606846976.0;     // 2^60
+constexpr double kFixInv = 1.0 / 1152921504606846976.0;  // 2^-60
 
 // Per-call control block in device memory.  Counters rotate by round so that
 // one round can clear the counter two rounds ahead without a separate launch.
+// The grid-barrier word, which waiting workgroups poll, sits on its own
+// 256-byte line, away from the worklist counters that pushes update.
 struct Ctl {
   uint32_t qcount[3];             // worklist sizes: round r reads [r % 3], pushes into [(r + 1) % 3]
   uint32_t overflow;              // first round in which a worklist overflowed (0xffffffff: none)
   unsigned long long huge[2];     // round r: (count << 32) | edge total of the huge worklist, [r & 1]
-  unsigned long long bar_count;   // grid barrier arrivals (monotone within a launch)
-  uint32_t abort;                 // a barrier wait timed out; every workgroup leaves
   uint32_t rounds;                // rounds completed (written by workgroup 0)
-  unsigned long long st_frontier; // statistics, summed over rounds
+  uint32_t pad0;
+  unsigned long long dangling[2]; // PageRank: rank mass without out-edges (fixed point), iteration it in [it & 1]
+  alignas(256) unsigned long long bar_count;  // grid barrier arrivals (monotone within a launch)
+  uint32_t abort;                 // a barrier wait timed out; every workgroup leaves
+  uint32_t diag_round;            // round of the wait that timed out
+  unsigned long long diag_seen;   // arrivals it observed
+  unsigned long long diag_target; // arrivals it waited for
+  unsigned long long members;     // persistent launch: tickets taken (top bit: membership closed)
+  uint32_t n_members;             // member count, published when membership closes
+  uint32_t pad1;
+  long long threshold_used;       // huge threshold the persistent launch used
+  alignas(256) unsigned long long st_frontier;  // statistics, summed over rounds
   unsigned long long st_edges_twc;
   unsigned long long st_edges_lb;
   unsigned long long st_huge_v;
   unsigned long long st_pushes;
-  double dangling[2];             // PageRank: rank mass without out-edges, iteration it in [it & 1]
+  // per-round timeline of the persistent launch (first kTimeline rounds):
+  // wall-clock ticks at round start, after the inspection/TWC phase and after
+  // the execution phase, and (worklist size | huge count << 32)
+  unsigned long long tl[4 * 64];
 };
+constexpr int kTimeline = 64;
 
 enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4 };
 
@@ -41,7 +63,7 @@ struct Args {
   uint32_t *prefix;     // its exclusive degree prefix (`prefixWork`)
   int32_t *stamp;       // dedup stamps (round of the last push), or null
   Ctl *ctl;
-  int64_t threshold;    // huge iff degree >= threshold (and degree >= 1)
+  int64_t threshold;    // huge iff degree >= threshold (and degree >= 1); persistent: < 0 = launched threads
   int32_t c_wave;       // TWC cutoffs
   int32_t c_wg;
   int32_t identity_first;  // round 0 works on every vertex (no worklist)
@@ -49,10 +71,11 @@ struct Args {
   int32_t max_rounds;
   int32_t round;           // host-loop mode: the round this launch runs
   uint64_t timeout_ticks;  // barrier wait limit in wall-clock ticks
+  uint64_t join_window_ticks;  // persistent launch: close membership after this long without a new member
   // operator state
   int32_t *labels;      // BFS level / SSSP dist / CC label
-  float *rank;          // PageRank
-  float *acc;
+  float *rank;          // PageRank: fp32 ranks
+  unsigned long long *acc;  // exact sums of fp32 contributions in 64-bit fixed point (kFix)
   float damping;
   int32_t *hits;        // trace operator
   int32_t *thread_of;
@@ -65,7 +88,9 @@ hipError_t launch_twc(OpKind op, int wg, int grid, const Args &a, hipStream_t s)
 hipError_t launch_lb(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_pr_update(int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_persistent(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
-// Workgroups of `wg` threads that fit on one CU for the persistent kernel of `op`.
+// Workgroups of `wg` threads that fit on one CU for the persistent kernel of
+// `op`, by the runtime's occupancy calculator (an upper bound: the launch
+// itself finds out how many are co-resident).
 hipError_t persistent_occupancy(OpKind op, int wg, int *blocks_per_cu);
 bool supported_wg(int wg);
 

@@ -32,6 +32,7 @@ namespace alb {
 namespace {
 
 constexpr int kWave = 64;
+constexpr uint32_t kPushBuf = 512;  // per-wavefront LDS staging of next-worklist pushes
 
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -70,7 +71,7 @@ struct OpBFS {  // level[dst] = level[src] + 1 on first visit
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
   int32_t *level;
   __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return level[v]; }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t) const {
+  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t, int32_t) const {
     if (level[dst] != kInf) return false;
     int32_t expected = kInf;
     return __hip_atomic_compare_exchange_strong(&level[dst], &expected, sv + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -84,7 +85,7 @@ struct OpSSSP {  // relaxation: dist[dst] = min(dist[dst], dist[src] + w)
   int32_t *dist;
   const int32_t *w;
   __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return dist[v]; }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t pos, int32_t dst, int32_t) const {
+  __device__ __forceinline__ bool apply(val_t sv, int32_t pos, int32_t dst, int32_t, int32_t) const {
     const int32_t nd = sv + w[pos];
     if (nd >= dist[dst]) return false;  // a stale (larger) cached value only costs an atomic
     const int32_t old = __hip_atomic_fetch_min(&dist[dst], nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -97,21 +98,24 @@ struct OpCC {  // min-label propagation
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
   int32_t *lab;
   __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return lab[v]; }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t) const {
+  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t, int32_t) const {
     if (sv >= lab[dst]) return false;
     const int32_t old = __hip_atomic_fetch_min(&lab[dst], sv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return sv < old;
   }
 };
 
-struct OpPR {  // acc[dst] += rank[src] / outdeg(src)
-  using val_t = float;
+// fp32 value -> 64-bit fixed point (round to nearest)
+__device__ __forceinline__ unsigned long long to_fix(float x) { return __double2ull_rn((double)x * kFixScale); }
+
+struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact fixed-point sum
+  using val_t = unsigned long long;
   static constexpr bool kPush = false, kNeedSrc = false, kRecord = false, kPR = true;
   const float *rank;
-  float *acc;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t deg) const { return rank[v] / (float)deg; }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t) const {
-    unsafeAtomicAdd(&acc[dst], sv);
+  unsigned long long *acc;
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t deg) const { return to_fix(rank[v] / (float)deg); }
+  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t, int32_t) const {
+    add_relaxed(&acc[dst], sv);
     return false;
   }
 };
@@ -122,9 +126,9 @@ struct OpRecord {  // counts each processed edge and the thread that took it; pu
   int32_t *hits;
   int32_t *thread_of;
   __device__ __forceinline__ val_t load_src(int32_t, int32_t) const { return 0; }
-  __device__ __forceinline__ bool apply(val_t, int32_t pos, int32_t, int32_t) const {
+  __device__ __forceinline__ bool apply(val_t, int32_t pos, int32_t, int32_t, int32_t gt) const {
     __hip_atomic_fetch_add(&hits[pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    thread_of[pos] = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    thread_of[pos] = gt;
     return true;
   }
 };
@@ -148,7 +152,7 @@ OpRecord make_op<OpRecord>(const Args &a) { return OpRecord{a.hits, a.thread_of}
 
 struct Acc {
   unsigned long long frontier = 0, edges_twc = 0, edges_lb = 0, huge_v = 0, pushes = 0;
-  double dangling = 0.0;
+  unsigned long long dangling = 0;  // fixed point
 };
 
 template <int B, class Op>
@@ -159,10 +163,28 @@ struct Smem {
   int32_t src[Op::kNeedSrc ? B : 1];
   int32_t wsum[B / kWave];
   unsigned long long ured[B / kWave][5];
-  double dred[B / kWave];
+  unsigned long long dred[B / kWave];
   int32_t owner, obeg, odeg, ov;  // workgroup-bin broadcast
   V osv;
   int32_t flag;
+  int32_t pbuf[B / kWave][kPushBuf];  // per-wavefront push staging
+};
+
+// Next-worklist pushes of one wavefront, staged in LDS and written out in
+// batches: one global reservation per batch instead of one per ballot.
+// The workgroup's index and the workgroup count used for work distribution:
+// the hardware ones for one-phase launches, the membership ticket and the
+// member count inside the persistent launch.
+struct Grid {
+  uint32_t id;
+  uint32_t n;
+};
+
+struct Pusher {
+  int32_t *buf;      // this wavefront's LDS staging area
+  uint32_t cnt;      // entries staged (wave-uniform)
+  int32_t *qn;       // next worklist
+  uint32_t *qn_cnt;  // its size counter
 };
 
 template <int B, class Op>
@@ -192,45 +214,52 @@ __device__ void flush_stats(Acc &acc, Smem<B, Op> &sm, Ctl *c) {
 }
 
 template <int B, class Op>
-__device__ void flush_dangling(Acc &acc, Smem<B, Op> &sm, double *dst) {
-  double x = acc.dangling;
+__device__ void flush_dangling(Acc &acc, Smem<B, Op> &sm, unsigned long long *dst) {
+  unsigned long long x = acc.dangling;
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
   if (lane_id() == 0) sm.dred[threadIdx.x / kWave] = x;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
+    unsigned long long t = 0;
     for (int j = 0; j < B / kWave; ++j) t += sm.dred[j];
-    if (t != 0.0) unsafeAtomicAdd(dst, t);
+    if (t != 0) add_relaxed(dst, t);
   }
   __syncthreads();
-  acc.dangling = 0.0;
+  acc.dangling = 0;
 }
 
 // ---------------------------------------------------------------------------
 // Wave-aggregated push and huge-worklist reservation.
 // ---------------------------------------------------------------------------
 
-// All lanes of the wavefront must call this (pred may be false).
-__device__ __forceinline__ void push_wave(bool pred, int32_t v, const Args &a, int round, int32_t *qn,
-                                          uint32_t *qn_cnt, Acc &acc) {
-  const unsigned long long m = __ballot(pred);
-  if (m == 0ull) return;
-  const uint32_t total = (uint32_t)__popcll(m);
-  const int leader = __ffsll((unsigned long long)m) - 1;
+// Write the staged entries to the next worklist (all lanes call this).
+__device__ __forceinline__ void flush_pushes(const Args &a, int round, Pusher &pu) {
+  if (pu.cnt == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   uint32_t base = 0;
-  if ((int)lane_id() == leader) {
-    base = add_relaxed(qn_cnt, total);
-    acc.pushes += total;
-  }
-  base = __shfl(base, leader);
-  if (pred) {
-    const uint32_t idx = base + bits_below(m);
+  if (lane_id() == 0) base = add_relaxed(pu.qn_cnt, pu.cnt);
+  base = __shfl(base, 0);
+  for (uint32_t j = lane_id(); j < pu.cnt; j += kWave) {
+    const uint32_t idx = base + j;
     if (idx < a.qcap)
-      qn[idx] = v;
+      pu.qn[idx] = pu.buf[j];
     else
       flag_overflow(a.ctl, round);
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  pu.cnt = 0;
+}
+
+// Stage v for every lane with pred (all lanes of the wavefront call this).
+__device__ __forceinline__ void push_wave(bool pred, int32_t v, const Args &a, int round, Pusher &pu, Acc &acc) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  const uint32_t total = (uint32_t)__popcll(m);
+  if (pu.cnt + total > kPushBuf) flush_pushes(a, round, pu);
+  if (pred) pu.buf[pu.cnt + bits_below(m)] = v;
+  pu.cnt += total;
+  if (lane_id() == 0) acc.pushes += total;
 }
 
 // Algorithm 1, "work.push(src)": append every huge lane's vertex to `work`
@@ -278,18 +307,21 @@ __device__ __forceinline__ void reserve_huge(bool huge, int32_t v, int32_t deg, 
 // Apply the operator along one edge (if act) and push; every lane calls it.
 template <class Op>
 __device__ __forceinline__ void edge(bool act, int32_t pos, typename Op::val_t sv, int32_t src, const Op &op,
-                                     const Args &a, int round, int32_t *qn, uint32_t *qn_cnt, Acc &acc) {
+                                     const Args &a, int round, Pusher &pu, Acc &acc, int32_t gt) {
   bool p = false;
   int32_t dst = 0;
   if (act) {
     dst = a.col[pos];
-    p = op.apply(sv, pos, dst, src);
+    p = op.apply(sv, pos, dst, src, gt);
     if constexpr (Op::kPush) {
+      // dedup: push once per round; a stamp equal to this round can only have
+      // been written this round, so the plain load is a safe filter
       if (p && a.stamp)
-        p = __hip_atomic_exchange(&a.stamp[dst], round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != round;
+        p = a.stamp[dst] != round &&
+            __hip_atomic_exchange(&a.stamp[dst], round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != round;
     }
   }
-  if constexpr (Op::kPush) push_wave(p, dst, a, round, qn, qn_cnt, acc);
+  if constexpr (Op::kPush) push_wave(p, dst, a, round, pu, acc);
 }
 
 template <int B>
@@ -320,13 +352,15 @@ __device__ __forceinline__ void block_exscan(int32_t x, int32_t &excl, int32_t &
 // Phase 1: inspection (Algorithm 1) fused with the TWC bins.
 // ---------------------------------------------------------------------------
 template <int B, class Op>
-__device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, int round, const int32_t *F, uint32_t nF,
-                          int32_t *qn, uint32_t *qn_cnt, unsigned long long *hctr, Acc &acc) {
+__device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, int round, const int32_t *F,
+                          uint32_t nF, int32_t *qn, uint32_t *qn_cnt, unsigned long long *hctr, Acc &acc) {
   using V = typename Op::val_t;
   const int tid = threadIdx.x;
   const uint32_t lane = lane_id();
-  const uint32_t stride = gridDim.x * B;
-  for (uint32_t base = blockIdx.x * B; base < nF; base += stride) {
+  const uint32_t stride = gr.n * B;
+  const int32_t gt = (int32_t)(gr.id * B + tid);
+  Pusher pu{sm.pbuf[tid / kWave], 0u, qn, qn_cnt};
+  for (uint32_t base = gr.id * B; base < nF; base += stride) {
     const uint32_t i = base + tid;
     int32_t v = -1, beg = 0, deg = 0;
     if (i < nF) {
@@ -341,7 +375,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, int roun
       if (i < nF) a.bins[i] = (int8_t)(huge ? 3 : deg >= a.c_wg ? 2 : deg >= a.c_wave ? 1 : 0);
     }
     if constexpr (Op::kPR) {
-      if (v >= 0 && deg == 0) acc.dangling += (double)a.rank[v];
+      if (v >= 0 && deg == 0) acc.dangling += to_fix(a.rank[v]);
     }
     if (huge) deg = 0;
     acc.frontier += (v >= 0);
@@ -369,7 +403,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, int roun
       const V os = sm.osv;
       for (int32_t j0 = 0; j0 < od; j0 += B) {
         const int32_t j = j0 + tid;
-        edge<Op>(j < od, ob + j, os, ov, op, a, round, qn, qn_cnt, acc);
+        edge<Op>(j < od, ob + j, os, ov, op, a, round, pu, acc, gt);
       }
     }
 
@@ -383,7 +417,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, int roun
       if ((int)lane == ld) deg = 0;
       for (int32_t j0 = 0; j0 < od; j0 += kWave) {
         const int32_t j = j0 + (int32_t)lane;
-        edge<Op>(j < od, ob + j, os, ov, op, a, round, qn, qn_cnt, acc);
+        edge<Op>(j < od, ob + j, os, ov, op, a, round, pu, acc, gt);
       }
     }
 
@@ -408,10 +442,11 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, int roun
         x = sm.sv[tid];
         if constexpr (Op::kNeedSrc) s = sm.src[tid];
       }
-      edge<Op>(act, p, x, s, op, a, round, qn, qn_cnt, acc);
+      edge<Op>(act, p, x, s, op, a, round, pu, acc, gt);
       __syncthreads();
     }
   }
+  if constexpr (Op::kPush) flush_pushes(a, round, pu);
 }
 
 // Largest j in [lo, vh) with prefix[j] <= k, given prefix[lo] <= k:
@@ -438,22 +473,23 @@ __device__ __forceinline__ uint32_t owner_from(const uint32_t *prefix, uint32_t 
 // Phase 2: execution (Algorithm 2) with the cyclic distribution.
 // ---------------------------------------------------------------------------
 template <int B, class Op>
-__device__ void phase_lb(const Args &a, const Op &op, int round, unsigned long long hc, int32_t *qn,
-                         uint32_t *qn_cnt, Acc &acc) {
+__device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, int round, unsigned long long hc,
+                         int32_t *qn, uint32_t *qn_cnt, Acc &acc) {
   using V = typename Op::val_t;
   const uint32_t vh = (uint32_t)(hc >> 32);
   const uint32_t e = (uint32_t)hc;
   if (vh == 0) return;
   // an overflowed reservation leaves prefix inconsistent with the degrees: skip
   if (ld_relaxed(&a.ctl->overflow) <= (uint32_t)round) return;
-  const uint64_t T = (uint64_t)gridDim.x * B;
+  const uint64_t T = (uint64_t)gr.n * B;
   const uint32_t lane = lane_id();
-  const uint64_t g = (uint64_t)blockIdx.x * B + threadIdx.x;
+  const uint64_t g = (uint64_t)gr.id * B + threadIdx.x;
   uint32_t s = 0;  // owner of the wavefront's first edge; never decreases
   uint32_t c_s = 0xffffffffu;
   int32_t c_src = 0, c_beg = 0;
   uint32_t c_p = 0;
   V c_sv = V(0);
+  Pusher pu{sm.pbuf[threadIdx.x / kWave], 0u, qn, qn_cnt};
   for (uint64_t k0 = g - lane; k0 < e; k0 += T) {
     s = owner_from(a.prefix, vh, s, (uint32_t)k0);
     const uint64_t k = k0 + lane;
@@ -471,37 +507,39 @@ __device__ void phase_lb(const Args &a, const Op &op, int round, unsigned long l
       }
     }
     acc.edges_lb += act;
-    edge<Op>(act, c_beg + (int32_t)((uint32_t)k - c_p), c_sv, c_src, op, a, round, qn, qn_cnt, acc);
+    edge<Op>(act, c_beg + (int32_t)((uint32_t)k - c_p), c_sv, c_src, op, a, round, pu, acc, (int32_t)g);
   }
+  if constexpr (Op::kPush) flush_pushes(a, round, pu);
 }
 
-// PageRank update: r'(v) = (1-d)/n + d * (acc(v) + D/n); acc cleared.
+// PageRank update: r'(v) = (1-d)/n + d * (acc(v) + D/n), rounded to fp32; acc cleared.
 template <int B>
-__device__ void phase_pr_update(const Args &a, double dangling) {
-  const float d = a.damping;
+__device__ void phase_pr_update(const Args &a, Grid gr, unsigned long long dangling_fix) {
+  const double d = (double)a.damping;
   const double N = (double)a.n;
-  const float base = (float)((1.0 - (double)d) / N + (double)d * dangling / N);
-  for (uint32_t v = blockIdx.x * B + threadIdx.x; v < (uint32_t)a.n; v += gridDim.x * B) {
-    const float x = a.acc[v];
-    a.rank[v] = base + d * x;
-    a.acc[v] = 0.0f;
+  const double base = (1.0 - d) / N + d * ((double)dangling_fix * kFixInv) / N;
+  for (uint32_t v = gr.id * B + threadIdx.x; v < (uint32_t)a.n; v += gr.n * B) {
+    const double x = (double)a.acc[v] * kFixInv;
+    a.rank[v] = (float)(base + d * x);
+    a.acc[v] = 0ull;
   }
 }
 
-// Grid-wide barrier over a monotone arrival counter.  Every thread fences its
-// own writes at agent scope first; thread 0 arrives with a release RMW and
-// spins with relaxed loads (plus s_sleep) until all workgroups have arrived,
-// then an agent-scope acquire fence.  A wait longer than timeout_ticks sets
-// ctl->abort, which makes every workgroup leave at its next barrier.
+// Grid-wide barrier over a monotone arrival counter.  After the workgroup
+// barrier, thread 0 alone releases the workgroup's writes at agent scope
+// (L2 write-back across the 8 XCDs), arrives with one RMW and spins with
+// relaxed loads and s_sleep until every workgroup has arrived, then acquires
+// (L1/L2 invalidate) before the workgroup barrier lets the others on.  A wait
+// longer than timeout_ticks sets ctl->abort, which makes every workgroup
+// leave at its next barrier.
 template <class S>
-__device__ bool grid_barrier(const Args &a, S &sm) {
-  __threadfence();
+__device__ bool grid_barrier(const Args &a, S &sm, Grid gr, int round) {
   __syncthreads();
   if (threadIdx.x == 0) {
     Ctl *c = a.ctl;
-    const unsigned long long nb = gridDim.x;
-    const unsigned long long arrived =
-        __hip_atomic_fetch_add(&c->bar_count, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long nb = gr.n;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned long long arrived = add_relaxed(&c->bar_count, 1ull);
     const unsigned long long target = (arrived / nb + 1ull) * nb;
     int ok = 1;
     const uint64_t t0 = (uint64_t)wall_clock64();
@@ -511,17 +549,19 @@ __device__ bool grid_barrier(const Args &a, S &sm) {
         break;
       }
       if ((uint64_t)wall_clock64() - t0 > a.timeout_ticks) {
+        st_relaxed(&c->diag_seen, ld_relaxed(&c->bar_count));
+        st_relaxed(&c->diag_target, target);
+        st_relaxed(&c->diag_round, (uint32_t)round);
         st_relaxed(&c->abort, 1u);
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_s_sleep(4);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     sm.flag = ok;
   }
   __syncthreads();
-  __threadfence();
   return sm.flag != 0;
 }
 
@@ -541,7 +581,7 @@ __device__ __forceinline__ uint32_t round_size(const Args &a, int r) {
 __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
   st_relaxed(&a.ctl->qcount[(r + 2) % 3], 0u);
   st_relaxed(&a.ctl->huge[(r + 1) & 1], 0ull);
-  st_relaxed(&a.ctl->dangling[(r + 1) & 1], 0.0);
+  st_relaxed(&a.ctl->dangling[(r + 1) & 1], 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,7 +596,7 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     if (a.stamp) a.stamp[v] = -1;
     if (op == OP_PR) {
       a.rank[v] = r0;
-      a.acc[v] = 0.0f;
+      a.acc[v] = 0ull;
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -571,8 +611,13 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     c->abort = 0;
     c->rounds = 0;
     c->st_frontier = c->st_edges_twc = c->st_edges_lb = c->st_huge_v = c->st_pushes = 0;
-    c->dangling[0] = 0.0;
-    c->dangling[1] = 0.0;
+    c->dangling[0] = 0;
+    c->dangling[1] = 0;
+    c->members = 0;
+    c->n_members = 0;
+    c->diag_seen = c->diag_target = 0;
+    c->diag_round = 0;
+    c->threshold_used = a.threshold;
     if (source >= 0 && op != OP_RECORD) a.q0[0] = source;
   }
 }
@@ -584,7 +629,8 @@ __global__ __launch_bounds__(B) void k_twc(Args a, Op op) {
   const int r = a.round;
   const uint32_t nF = round_size(a, r);
   if (blockIdx.x == 0 && threadIdx.x == 0) clear_ahead(a, r);
-  phase_twc<B, Op>(a, op, sm, r, round_frontier(a, r), nF, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
+  const Grid gr{blockIdx.x, gridDim.x};
+  phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
                    &a.ctl->huge[r & 1], acc);
   if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
   flush_stats<B, Op>(acc, sm, a.ctl);
@@ -596,42 +642,109 @@ __global__ __launch_bounds__(B) void k_lb(Args a, Op op) {
   Acc acc;
   const int r = a.round;
   const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
-  phase_lb<B, Op>(a, op, r, hc, round_next(a, r), &a.ctl->qcount[(r + 1) % 3], acc);
+  phase_lb<B, Op>(a, op, sm, Grid{blockIdx.x, gridDim.x}, r, hc, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
+                  acc);
   flush_stats<B, Op>(acc, sm, a.ctl);
 }
 
 template <int B>
 __global__ __launch_bounds__(B) void k_pr_update(Args a) {
-  phase_pr_update<B>(a, ld_relaxed(&a.ctl->dangling[a.round & 1]));
+  phase_pr_update<B>(a, Grid{blockIdx.x, gridDim.x}, ld_relaxed(&a.ctl->dangling[a.round & 1]));
   if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->rounds, (uint32_t)a.round + 1u);
+}
+
+// Membership of the persistent launch.  The grid may be larger than what the
+// device can hold at once, so co-residency is not assumed: every workgroup
+// takes a ticket from ctl->members when it starts; the holder of ticket 0
+// closes membership (sets the top bit) once all workgroups have joined or
+// no new one has joined for join_window_ticks, and publishes the member
+// count.  A workgroup whose ticket shows the closed bit is not a member and
+// leaves at once.  Members are running when they join and never leave before
+// the end, so every barrier among them completes.  Returns false for a
+// non-member; *gr gets (ticket, member count).
+template <class S>
+__device__ bool join_members(const Args &a, S &sm, Grid *gr) {
+  constexpr unsigned long long kClosed = 1ull << 63;
+  if (threadIdx.x == 0) {
+    Ctl *c = a.ctl;
+    const unsigned long long t = add_relaxed(&c->members, 1ull);
+    uint32_t member = (t & kClosed) ? 0u : 1u;
+    if (member && t == 0) {
+      unsigned long long seen = 1;
+      uint64_t t_last = (uint64_t)wall_clock64();
+      for (;;) {
+        const unsigned long long cur = ld_relaxed(&c->members);
+        if (cur >= (unsigned long long)gridDim.x) break;
+        const uint64_t now = (uint64_t)wall_clock64();
+        if (cur != seen) {
+          seen = cur;
+          t_last = now;
+        } else if (now - t_last > a.join_window_ticks) {
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      const unsigned long long prev = __hip_atomic_fetch_or(&c->members, kClosed, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+      st_relaxed(&c->n_members, (uint32_t)prev);
+    }
+    uint32_t n = 0;
+    if (member) {
+      while ((n = ld_relaxed(&c->n_members)) == 0) __builtin_amdgcn_s_sleep(1);
+      if ((uint32_t)t >= n) member = 0;  // cannot happen: tickets below the closing count are members
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    sm.flag = (int32_t)member;
+    sm.owner = (int32_t)t;
+    sm.obeg = (int32_t)n;
+  }
+  __syncthreads();
+  const bool member = sm.flag != 0;
+  gr->id = (uint32_t)sm.owner;
+  gr->n = (uint32_t)sm.obeg;
+  __syncthreads();
+  return member;
 }
 
 template <int B, class Op>
 __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
   __shared__ Smem<B, Op> sm;
   Acc acc;
+  Grid gr;
+  if (!join_members(a, sm, &gr)) return;
+  if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // default: the launched thread count
   int r = 0;
   for (; r < a.max_rounds; ++r) {
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;  // set in an earlier round: seen by all alike
     const uint32_t nF = round_size(a, r);
     if (nF == 0) break;
-    if (blockIdx.x == 0 && threadIdx.x == 0) clear_ahead(a, r);
+    const bool tl = gr.id == 0 && threadIdx.x == 0 && r < kTimeline;
+    if (gr.id == 0 && threadIdx.x == 0) clear_ahead(a, r);
+    if (tl) a.ctl->tl[4 * r] = (unsigned long long)wall_clock64();
     int32_t *qn = round_next(a, r);
     uint32_t *qn_cnt = &a.ctl->qcount[(r + 1) % 3];
-    phase_twc<B, Op>(a, op, sm, r, round_frontier(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], acc);
+    phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], acc);
     if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
-    if (!grid_barrier(a, sm)) break;
+    if (!grid_barrier(a, sm, gr, r)) break;
     const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
-    if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
-      phase_lb<B, Op>(a, op, r, hc, qn, qn_cnt, acc);
-      if (!grid_barrier(a, sm)) break;
+    if (tl) {
+      a.ctl->tl[4 * r + 1] = (unsigned long long)wall_clock64();
+      a.ctl->tl[4 * r + 3] = (unsigned long long)nF | ((hc >> 32) << 32);
     }
+    if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
+      phase_lb<B, Op>(a, op, sm, gr, r, hc, qn, qn_cnt, acc);
+      if (!grid_barrier(a, sm, gr, r)) break;
+    }
+    if (tl) a.ctl->tl[4 * r + 2] = (unsigned long long)wall_clock64();
     if constexpr (Op::kPR) {
-      phase_pr_update<B>(a, ld_relaxed(&a.ctl->dangling[r & 1]));
-      if (!grid_barrier(a, sm)) break;
+      phase_pr_update<B>(a, gr, ld_relaxed(&a.ctl->dangling[r & 1]));
+      if (!grid_barrier(a, sm, gr, r)) break;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->rounds, (uint32_t)r);
+  if (gr.id == 0 && threadIdx.x == 0) {
+    st_relaxed(&a.ctl->rounds, (uint32_t)r);
+    st_relaxed(&a.ctl->threshold_used, (long long)a.threshold);
+  }
   flush_stats<B, Op>(acc, sm, a.ctl);
 }
 
@@ -651,10 +764,8 @@ hipError_t lb_t(int grid, const Args &a, hipStream_t s) {
 }
 template <int B, class Op>
 hipError_t persistent_t(int grid, const Args &a, hipStream_t s) {
-  Args aa = a;
-  Op op = make_op<Op>(a);
-  void *params[] = {(void *)&aa, (void *)&op};
-  return hipLaunchCooperativeKernel((const void *)k_persistent<B, Op>, dim3(grid), dim3(B), params, 0, s);
+  hipLaunchKernelGGL((k_persistent<B, Op>), dim3(grid), dim3(B), 0, s, a, make_op<Op>(a));
+  return hipGetLastError();
 }
 template <int B, class Op>
 hipError_t occupancy_t(int *blocks) {

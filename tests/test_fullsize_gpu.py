@@ -1,0 +1,107 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+  SSSP on RMAT scale 22 (4.19M vertices, ~65M edges, weights U[1,100]) from
+  the highest-degree vertex: every distance equal to Dijkstra's.
+  Zipf(1.9) out-degree graph, n = 2^24, degrees capped at 4,194,304 (~372M
+  edges): BFS levels equal to the queue BFS, CC labels equal to union-find,
+  PageRank (50 iterations) within L1 1e-5 of the fp64 oracle.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print("[%s] %s" % (time.strftime("%H:%M:%S"), msg), flush=True)
+
+
+@pytest.fixture(scope="module")
+def alb():
+    from paper_1911_09135_amd import alb as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def rmat22w():
+    t = time.time()
+    g = gg.workload("rmat22w")
+    log("rmat22w generated in %.1fs: m=%d" % (time.time() - t, g.m))
+    return g
+
+
+@pytest.fixture(scope="module")
+def zipf24():
+    t = time.time()
+    g = gg.workload("zipf24")
+    log("zipf24 generated in %.1fs: m=%d" % (time.time() - t, g.m))
+    return g
+
+
+def test_sssp_rmat22_full(alb, rmat22w):
+    g = rmat22w
+    s = g.max_degree_vertex()
+    t = time.time()
+    ref = oracle.sssp(g, s)
+    log("oracle dijkstra %.1fs" % (time.time() - t))
+    dg = alb.Graph(g.off, g.col, g.w)
+    for c in [dict(), dict(threshold=4096), dict(threshold=256), dict(mode="twc"), dict(mode="lb_all"),
+              dict(threshold=4096, launch="host")]:
+        d, st = alb.sssp(dg, s, **c)
+        assert np.array_equal(d, ref), c
+        log("sssp %s ok: rounds %d, %.2f ms" % (c, st["rounds"], st["device_ms"]))
+    dg.close()
+
+
+def test_bfs_zipf24_full(alb, zipf24):
+    g = zipf24
+    s = g.max_degree_vertex()
+    t = time.time()
+    ref = oracle.bfs(g, s)
+    log("oracle bfs %.1fs" % (time.time() - t))
+    dg = alb.Graph(g.off, g.col)
+    for c in [dict(), dict(threshold=4096), dict(mode="twc"), dict(threshold=4096, launch="host")]:
+        lv, st = alb.bfs(dg, s, **c)
+        assert np.array_equal(lv, ref), c
+        log("bfs %s ok: rounds %d, huge %d, %.2f ms" % (c, st["rounds"], st["huge_vertices"], st["device_ms"]))
+    dg.close()
+
+
+def test_cc_zipf24_full(alb, zipf24):
+    g = zipf24
+    t = time.time()
+    ref = oracle.cc(g)
+    log("oracle cc %.1fs" % (time.time() - t))
+    t = time.time()
+    dg = alb.Graph(g.off, g.col, None, build_symmetric=True)
+    log("symmetrised on the host in %.1fs: m=%d" % (time.time() - t, dg.m))
+    for c in [dict(), dict(threshold=4096)]:
+        lab, st = alb.cc(dg, **c)
+        assert np.array_equal(lab, ref), c
+        log("cc %s ok: rounds %d, %.2f ms" % (c, st["rounds"], st["device_ms"]))
+    dg.close()
+
+
+def test_pagerank_zipf24_full(alb, zipf24):
+    g = zipf24
+    t = time.time()
+    ref = oracle.pagerank(g, 0.85, 50, threads=min(16, os.cpu_count() or 1))
+    log("oracle pagerank %.1fs" % (time.time() - t))
+    dg = alb.Graph(g.off, g.col)
+    x0 = None
+    for c in [dict(), dict(threshold=4096), dict(mode="twc")]:
+        x, st = alb.pagerank(dg, 0.85, 50, **c)
+        err = float(np.abs(x.astype(np.float64) - ref).sum())
+        assert err <= 1e-5, (c, err)
+        if x0 is None:
+            x0 = x
+        assert np.array_equal(x, x0)
+        log("pagerank %s ok: L1 %.2e, %.2f ms" % (c, err, st["device_ms"]))
+    dg.close()

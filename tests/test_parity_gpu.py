@@ -144,6 +144,19 @@ def test_pagerank_matrix(alb, name):
     assert np.all(x == np.float32(1.0 / g.n))
 
 
+@pytest.mark.parametrize("name", ["rmat14", "hubs", "star3000"])
+def test_pagerank_bitwise_reproducible(alb, name):
+    """Sums are exact fixed point, so every configuration gives the same bits."""
+    g = graph(name)
+    dg = device_graph(alb, name)
+    first = None
+    for c in configs(int(g.degrees().max())):
+        x, _ = alb.pagerank(dg, 0.85, 50, **c)
+        if first is None:
+            first = x
+        assert np.array_equal(x, first), (name, c)
+
+
 def test_cc_disjoint_components(alb):
     g = gg.disjoint_copies(gg.star(700), 9)
     dg = alb.Graph(g.off, g.col, None, symmetric=True)
