@@ -48,12 +48,13 @@ alb_status fail(alb_status s, const char *fmt, ...) {
 
 struct Workspace {
   uint32_t qcap = 0;
+  uint32_t hint_cap = 0;
   int32_t n = 0;
   bool busy = false;
-  int32_t *q0 = nullptr, *q1 = nullptr, *work = nullptr, *stamp = nullptr, *labels = nullptr;
-  uint32_t *prefix = nullptr;
+  int32_t *q0 = nullptr, *q1 = nullptr, *hint = nullptr, *labels = nullptr;
+  int4 *huge_rec = nullptr;
+  unsigned long long *bar = nullptr, *word = nullptr, *acc = nullptr;
   float *rank = nullptr;
-  unsigned long long *acc = nullptr;
   Ctl *ctl = nullptr;
   Ctl *h_ctl = nullptr;  // pinned host mirror
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -62,9 +63,10 @@ struct Workspace {
   void release() {
     (void)hipFree(q0);
     (void)hipFree(q1);
-    (void)hipFree(work);
-    (void)hipFree(prefix);
-    (void)hipFree(stamp);
+    (void)hipFree(huge_rec);
+    (void)hipFree(hint);
+    (void)hipFree(bar);
+    (void)hipFree(word);
     (void)hipFree(labels);
     (void)hipFree(rank);
     (void)hipFree(acc);
@@ -198,7 +200,7 @@ alb_status symmetrise(int32_t n, const int32_t *off, const int32_t *col, std::ve
 
 struct Needs {
   uint32_t qcap;
-  bool stamp, labels, pr;
+  uint32_t hint_cap;
 };
 
 template <class T>
@@ -212,11 +214,13 @@ hipError_t dalloc(T **p, size_t count, size_t &bytes) {
 alb_status ws_fill(Workspace *w, int32_t n, const Needs &nd) {
   w->n = n;
   w->qcap = nd.qcap;
+  w->hint_cap = nd.hint_cap;
   HIP_TRY(dalloc(&w->q0, nd.qcap, w->bytes));
   HIP_TRY(dalloc(&w->q1, nd.qcap, w->bytes));
-  HIP_TRY(dalloc(&w->work, nd.qcap, w->bytes));
-  HIP_TRY(dalloc(&w->prefix, nd.qcap, w->bytes));
-  HIP_TRY(dalloc(&w->stamp, (size_t)n, w->bytes));
+  HIP_TRY(dalloc(&w->huge_rec, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->hint, nd.hint_cap, w->bytes));
+  HIP_TRY(dalloc(&w->bar, kBarWords, w->bytes));
+  HIP_TRY(dalloc(&w->word, (size_t)n, w->bytes));
   HIP_TRY(dalloc(&w->labels, (size_t)n, w->bytes));
   HIP_TRY(dalloc(&w->rank, (size_t)n, w->bytes));
   HIP_TRY(dalloc(&w->acc, (size_t)n, w->bytes));
@@ -229,7 +233,7 @@ alb_status ws_fill(Workspace *w, int32_t n, const Needs &nd) {
 alb_status ws_acquire(alb_graph g, const Needs &nd, Workspace **out) {
   std::lock_guard<std::mutex> lk(g->mu);
   for (Workspace *w : g->pool)
-    if (!w->busy && w->qcap >= nd.qcap) {
+    if (!w->busy && w->qcap >= nd.qcap && w->hint_cap >= nd.hint_cap) {
       w->busy = true;
       *out = w;
       return ALB_OK;
@@ -425,7 +429,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   qcap = std::max<uint64_t>(qcap, 1);
   if (qcap > 0xfffffffeULL) qcap = 0xfffffffeULL;
 
-  Needs nd{(uint32_t)qcap, dedup, true, job.op == OP_PR};
+  Needs nd{(uint32_t)qcap, (uint32_t)(((uint64_t)g->m >> kHintMinShift) + 2)};
   Workspace *ws = nullptr;
   alb_status s = ws_acquire(g, nd, &ws);
   if (s != ALB_OK) return s;
@@ -443,22 +447,26 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.qcap = (uint32_t)qcap;  // the workspace may be larger; honour the requested capacity
   a.q0 = ws->q0;
   a.q1 = ws->q1;
-  a.work = ws->work;
-  a.prefix = ws->prefix;
-  a.stamp = dedup ? ws->stamp : nullptr;
+  a.huge_rec = ws->huge_rec;
+  a.hint = ws->hint;
+  a.hint_cap = ws->hint_cap;
+  a.bar = ws->bar;
   a.ctl = ws->ctl;
   a.threshold = threshold;
   a.c_wave = o.wave_cutoff;
   a.c_wg = o.wg_cutoff;
+  a.dedup = dedup ? 1 : 0;
   a.identity_first = job.identity_first;
   a.all_rounds = job.all_rounds;
   a.max_rounds = job.max_rounds;
   a.round = 0;
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
   a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);  // 10 us without a new member
-  a.labels = nullptr;
-  if (job.op == OP_BFS || job.op == OP_SSSP || job.op == OP_CC)
-    a.labels = dev_out ? (int32_t *)dev_out : ws->labels;
+  if (job.op == OP_BFS) a.level = dev_out ? (int32_t *)dev_out : ws->labels;
+  if (job.op == OP_SSSP || job.op == OP_CC) {
+    a.word = ws->word;
+    a.out = dev_out ? (int32_t *)dev_out : ws->labels;
+  }
   if (job.op == OP_PR) {
     a.rank = dev_out ? (float *)dev_out : ws->rank;
     a.acc = ws->acc;
@@ -467,7 +475,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.hits = job.d_hits;
   a.thread_of = job.d_thread;
   a.bins = job.d_bins;
-  ro.d_labels = a.labels;
+  ro.d_labels = job.op == OP_BFS ? a.level : a.out;
   ro.d_rank = a.rank;
 
   if (job.h_frontier && job.nfront0)
@@ -510,6 +518,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
       rounds = r + 1;
     }
   }
+  if (job.op == OP_SSSP || job.op == OP_CC) HIP_TRY(launch_finish(a, stream));
   HIP_TRY(hipEventRecord(ws->ev[2], stream));
   HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -837,11 +846,10 @@ alb_status alb_trace_round(alb_graph g, const int32_t *frontier, int64_t nf, con
   const Ctl &c = *ws->h_ctl;
   const uint32_t vh = (uint32_t)(c.huge[0] >> 32), ehuge = (uint32_t)c.huge[0];
   const uint32_t nn = std::min(c.qcount[1], ro.qcap);
-  std::vector<uint32_t> hp(vh);
+  std::vector<int4> hr(vh);
   bool ok = true;
   ok = ok && hipMemcpy(bins, d_bins, (size_t)nf, hipMemcpyDeviceToHost) == hipSuccess;
-  ok = ok && (vh == 0 || hipMemcpy(work, ws->work, sizeof(int32_t) * vh, hipMemcpyDeviceToHost) == hipSuccess);
-  ok = ok && (vh == 0 || hipMemcpy(hp.data(), ws->prefix, sizeof(uint32_t) * vh, hipMemcpyDeviceToHost) == hipSuccess);
+  ok = ok && (vh == 0 || hipMemcpy(hr.data(), ws->huge_rec, sizeof(int4) * vh, hipMemcpyDeviceToHost) == hipSuccess);
   ok = ok && (g->m == 0 || hipMemcpy(edge_hits, d_hits, sizeof(int32_t) * g->m, hipMemcpyDeviceToHost) == hipSuccess);
   ok = ok && (g->m == 0 || hipMemcpy(edge_thread, d_thread, sizeof(int32_t) * g->m, hipMemcpyDeviceToHost) == hipSuccess);
   ok = ok && (!next || nn == 0 || hipMemcpy(next, ws->q1, sizeof(int32_t) * nn, hipMemcpyDeviceToHost) == hipSuccess);
@@ -851,7 +859,10 @@ alb_status alb_trace_round(alb_graph g, const int32_t *frontier, int64_t nf, con
     return fail(ALB_E_DEVICE, "copy-out of the traced round failed");
   }
   *nwork = vh;
-  for (uint32_t j = 0; j < vh; ++j) prefix[j] = hp[j];
+  for (uint32_t j = 0; j < vh; ++j) {
+    work[j] = hr[j].z;
+    prefix[j] = (uint32_t)hr[j].x;
+  }
   prefix[vh] = ehuge;
   *nnext = nn;
   return ALB_OK;

@@ -16,10 +16,24 @@ constexpr int32_t kInf = 0x7fffffff;
 constexpr double kFixScale = 1152921504606846976.0;     // 2^60
 constexpr double kFixInv = 1.0 / 1152921504606846976.0;  // 2^-60
 
+// Grid barrier: workgroups arrive on one of several group counters (kBarGroup
+// workgroups each); the last of a group arrives on the root counter; the last
+// root arrival bumps the generation word that every workgroup polls.  Each
+// word sits on its own 256-byte line of the barrier buffer.
+constexpr int kBarGroup = 32;
+constexpr int kBarMaxGroups = 1024;
+constexpr int kBarStride = 32;  // uint64 words per line
+constexpr int kBarRoot = 0, kBarGen = kBarStride, kBarGroups = 2 * kBarStride;
+constexpr size_t kBarWords = (size_t)kBarGroups + (size_t)kBarStride * kBarMaxGroups;
+
+// Huge-worklist chunk index: edge index k of the round's huge edges lies in
+// chunk k >> hint_shift; hint[c] holds the huge-list slot that owns the first
+// edge of chunk c.  The shift is at least kHintMinShift.
+constexpr int kHintMinShift = 10;
+constexpr int kHintMaxShift = 20;
+
 // Per-call control block in device memory.  Counters rotate by round so that
 // one round can clear the counter two rounds ahead without a separate launch.
-// The grid-barrier word, which waiting workgroups poll, sits on its own
-// 256-byte line, away from the worklist counters that pushes update.
 struct Ctl {
   uint32_t qcount[3];             // worklist sizes: round r reads [r % 3], pushes into [(r + 1) % 3]
   uint32_t overflow;              // first round in which a worklist overflowed (0xffffffff: none)
@@ -27,11 +41,10 @@ struct Ctl {
   uint32_t rounds;                // rounds completed (written by workgroup 0)
   uint32_t pad0;
   unsigned long long dangling[2]; // PageRank: rank mass without out-edges (fixed point), iteration it in [it & 1]
-  alignas(256) unsigned long long bar_count;  // grid barrier arrivals (monotone within a launch)
-  uint32_t abort;                 // a barrier wait timed out; every workgroup leaves
+  alignas(256) uint32_t abort;    // a barrier wait timed out; every workgroup leaves
   uint32_t diag_round;            // round of the wait that timed out
-  unsigned long long diag_seen;   // arrivals it observed
-  unsigned long long diag_target; // arrivals it waited for
+  unsigned long long diag_seen;   // generation it observed
+  unsigned long long diag_target; // generation it waited for
   unsigned long long members;     // persistent launch: tickets taken (top bit: membership closed)
   uint32_t n_members;             // member count, published when membership closes
   uint32_t pad1;
@@ -56,16 +69,18 @@ struct Args {
   const int32_t *col;  // m
   const int32_t *w;    // m (SSSP)
   int32_t n;
-  uint32_t qcap;        // capacity of each worklist and of work / prefix
+  uint32_t qcap;        // capacity of each worklist and of the huge list
   int32_t *q0;          // worklists (double buffered)
   int32_t *q1;
-  int32_t *work;        // huge worklist (Algorithm 1 `work`)
-  uint32_t *prefix;     // its exclusive degree prefix (`prefixWork`)
-  int32_t *stamp;       // dedup stamps (round of the last push), or null
+  int4 *huge_rec;       // huge list (Algorithm 1 `work`): per slot {prefixWork entry, CSR start, vertex, source value}
+  int32_t *hint;        // chunk index of the huge edges
+  uint32_t hint_cap;
+  unsigned long long *bar;  // grid barrier words (kBarWords)
   Ctl *ctl;
   int64_t threshold;    // huge iff degree >= threshold (and degree >= 1); persistent: < 0 = launched threads
   int32_t c_wave;       // TWC cutoffs
   int32_t c_wg;
+  int32_t dedup;        // SSSP / CC: push a vertex at most once per round
   int32_t identity_first;  // round 0 works on every vertex (no worklist)
   int32_t all_rounds;      // every round works on every vertex (PageRank)
   int32_t max_rounds;
@@ -73,7 +88,9 @@ struct Args {
   uint64_t timeout_ticks;  // barrier wait limit in wall-clock ticks
   uint64_t join_window_ticks;  // persistent launch: close membership after this long without a new member
   // operator state
-  int32_t *labels;      // BFS level / SSSP dist / CC label
+  int32_t *level;       // BFS levels
+  unsigned long long *word;  // SSSP / CC: (label << 32) | tag, tag = 1 + last round that lowered it
+  int32_t *out;         // SSSP / CC: int32 labels written by the finishing kernel
   float *rank;          // PageRank: fp32 ranks
   unsigned long long *acc;  // exact sums of fp32 contributions in 64-bit fixed point (kFix)
   float damping;
@@ -88,6 +105,8 @@ hipError_t launch_twc(OpKind op, int wg, int grid, const Args &a, hipStream_t s)
 hipError_t launch_lb(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_pr_update(int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_persistent(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
+// SSSP / CC: out[v] = word[v] >> 32.
+hipError_t launch_finish(const Args &a, hipStream_t s);
 // Workgroups of `wg` threads that fit on one CU for the persistent kernel of
 // `op`, by the runtime's occupancy calculator (an upper bound: the launch
 // itself finds out how many are co-resident).

@@ -5,26 +5,28 @@
 //
 //   phase 1  inspection + TWC (Algorithm 1, Section 3 "TWC").  Each workgroup
 //            takes B consecutive entries of F.  A vertex whose out-degree is
-//            >= threshold is appended to the huge worklist `work`; its degree is
-//            added to `prefixWork` in the same wave-aggregated atomic, so the
+//            >= threshold is appended to the huge list; its degree is added
+//            to prefixWork in the same wave-aggregated 64-bit atomic, so the
 //            exclusive prefix of the huge degrees (Section 4.1 "Search") is
 //            known once the phase ends.  Every other vertex is processed at
 //            once by the workgroup, wavefront or thread bin of its degree.
-//   phase 2  execution (Algorithm 2), only when `work` is non-empty
-//            (Section 4.3).  Huge edge k goes to global thread k mod T (the
-//            cyclic distribution, Section 4.1), so the 64 lanes of a wavefront
-//            take 64 consecutive edges and read consecutive col / weight
-//            entries.  The source of each edge is the last prefix entry <= k,
-//            found once per wavefront-iteration; a second search runs only
-//            for lanes past the first source's range.
+//   phase 2  execution (Algorithm 2), only when the huge list is non-empty
+//            (Section 4.3).  Huge edge k goes to thread k mod T (the cyclic
+//            distribution, Section 4.1), so the 64 lanes of a wavefront take
+//            64 consecutive edges and read consecutive col / weight entries.
+//            The source of edge k is the last prefixWork entry <= k.  The
+//            search starts from a chunk index written when the huge list is
+//            reserved (the slot owning the first edge of every 2^s-edge
+//            chunk), so it costs one or two probes instead of log2(v) levels.
 //
-// The operator (BFS, SSSP, CC, PageRank, or a recorder for tests) is a
-// template parameter.  Pushes to the next worklist are wave-aggregated: one
-// atomic per wavefront, lane offsets from a ballot and mbcnt.
+// Each lane keeps kU edges in flight: loads of all of them are issued before
+// any operator decision, which hides the random-access latency of the
+// destination labels.  The operator (BFS, SSSP, CC, PageRank, or a recorder
+// for tests) is a template parameter.  Pushes to the next worklist are
+// staged per wavefront in LDS and reserved in batches.
 //
 // Rounds are driven either from the host (one launch per phase) or inside one
-// cooperative persistent launch whose phases are separated by a grid-wide
-// barrier with agent-scope release/acquire fences (8 XCDs, separate L2s).
+// persistent launch whose phases are separated by a grid-wide barrier.
 
 #include "alb_internal.h"
 
@@ -32,6 +34,7 @@ namespace alb {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kU = 4;               // edges in flight per lane
 constexpr uint32_t kPushBuf = 512;  // per-wavefront LDS staging of next-worklist pushes
 
 __device__ __forceinline__ uint32_t lane_id() {
@@ -61,73 +64,121 @@ __device__ __forceinline__ void flag_overflow(Ctl *c, int round) {
   __hip_atomic_fetch_min(&c->overflow, (uint32_t)round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// fp32 value -> 64-bit fixed point (round to nearest)
+__device__ __forceinline__ unsigned long long to_fix(float x) { return __double2ull_rn((double)x * kFixScale); }
+
+template <class V>
+__device__ __forceinline__ int32_t to_bits(V x) {
+  return __builtin_bit_cast(int32_t, x);
+}
+template <class V>
+__device__ __forceinline__ V from_bits(int32_t x) {
+  return __builtin_bit_cast(V, x);
+}
+
 // ---------------------------------------------------------------------------
-// Operators.  apply() runs the operator along one edge and returns true when
-// the destination must be pushed to the next worklist.
+// Operators.  The work along one edge is split into prepare() (issue the loads
+// it needs) and commit() (decide, update the destination, and say whether the
+// destination goes to the next worklist), so that a lane can have kU edges'
+// loads in flight before the first decision.
 // ---------------------------------------------------------------------------
 
 struct OpBFS {  // level[dst] = level[src] + 1 on first visit
   using val_t = int32_t;
+  struct pre_t {
+    int32_t cur;
+  };
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
   int32_t *level;
   __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return level[v]; }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t, int32_t) const {
-    if (level[dst] != kInf) return false;
+  __device__ __forceinline__ pre_t prepare(int32_t, int32_t dst, val_t) const { return {level[dst]}; }
+  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
+                                         uint32_t) const {
+    if (p.cur != kInf) return false;
     int32_t expected = kInf;
     return __hip_atomic_compare_exchange_strong(&level[dst], &expected, sv + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 
+// SSSP and CC keep one 64-bit word per vertex: (label << 32) | tag, where tag
+// is 1 + the round that last lowered the label.  A relaxation in round r
+// offers (candidate << 32) | (r + 1) to an atomic minimum: it lowers the word
+// exactly when the candidate is smaller (an equal candidate never changes the
+// word, its tag being no smaller), and the old word says both whether the
+// label dropped and whether it had already dropped this round, in which case
+// the vertex is already on the next worklist.  One random atomic per
+// relaxation serves as both the update and the push deduplication.
+__device__ __forceinline__ bool lower_word(unsigned long long *word, int32_t cand, unsigned long long cur,
+                                           uint32_t tag, int32_t dedup) {
+  if (cand >= (int32_t)(cur >> 32)) return false;  // a stale (larger) cached word only costs an atomic
+  const unsigned long long old = __hip_atomic_fetch_min(word, ((unsigned long long)(uint32_t)cand << 32) | tag,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return cand < (int32_t)(old >> 32) && (!dedup || (uint32_t)old != tag);
+}
+
 struct OpSSSP {  // relaxation: dist[dst] = min(dist[dst], dist[src] + w)
   using val_t = int32_t;
+  struct pre_t {
+    int32_t cand;
+    unsigned long long cur;
+  };
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
-  int32_t *dist;
+  unsigned long long *word;
   const int32_t *w;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return dist[v]; }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t pos, int32_t dst, int32_t, int32_t) const {
-    const int32_t nd = sv + w[pos];
-    if (nd >= dist[dst]) return false;  // a stale (larger) cached value only costs an atomic
-    const int32_t old = __hip_atomic_fetch_min(&dist[dst], nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return nd < old;
+  int32_t dedup;
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return (int32_t)(word[v] >> 32); }
+  __device__ __forceinline__ pre_t prepare(int32_t pos, int32_t dst, val_t sv) const {
+    return {sv + w[pos], word[dst]};
+  }
+  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t, int32_t, int32_t,
+                                         uint32_t tag) const {
+    return lower_word(&word[dst], p.cand, p.cur, tag, dedup);
   }
 };
 
 struct OpCC {  // min-label propagation
   using val_t = int32_t;
+  struct pre_t {
+    unsigned long long cur;
+  };
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
-  int32_t *lab;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return lab[v]; }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t, int32_t) const {
-    if (sv >= lab[dst]) return false;
-    const int32_t old = __hip_atomic_fetch_min(&lab[dst], sv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return sv < old;
+  unsigned long long *word;
+  int32_t dedup;
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return (int32_t)(word[v] >> 32); }
+  __device__ __forceinline__ pre_t prepare(int32_t, int32_t dst, val_t) const { return {word[dst]}; }
+  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
+                                         uint32_t tag) const {
+    return lower_word(&word[dst], sv, p.cur, tag, dedup);
   }
 };
 
-// fp32 value -> 64-bit fixed point (round to nearest)
-__device__ __forceinline__ unsigned long long to_fix(float x) { return __double2ull_rn((double)x * kFixScale); }
-
 struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact fixed-point sum
-  using val_t = unsigned long long;
+  using val_t = float;
+  struct pre_t {};
   static constexpr bool kPush = false, kNeedSrc = false, kRecord = false, kPR = true;
   const float *rank;
   unsigned long long *acc;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t deg) const { return to_fix(rank[v] / (float)deg); }
-  __device__ __forceinline__ bool apply(val_t sv, int32_t, int32_t dst, int32_t, int32_t) const {
-    add_relaxed(&acc[dst], sv);
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t deg) const { return rank[v] / (float)deg; }
+  __device__ __forceinline__ pre_t prepare(int32_t, int32_t, val_t) const { return {}; }
+  __device__ __forceinline__ bool commit(const pre_t &, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
+                                         uint32_t) const {
+    add_relaxed(&acc[dst], to_fix(sv));
     return false;
   }
 };
 
 struct OpRecord {  // counts each processed edge and the thread that took it; pushes every destination
   using val_t = int32_t;
+  struct pre_t {};
   static constexpr bool kPush = true, kNeedSrc = true, kRecord = true, kPR = false;
   int32_t *hits;
   int32_t *thread_of;
   __device__ __forceinline__ val_t load_src(int32_t, int32_t) const { return 0; }
-  __device__ __forceinline__ bool apply(val_t, int32_t pos, int32_t, int32_t, int32_t gt) const {
-    __hip_atomic_fetch_add(&hits[pos], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __device__ __forceinline__ pre_t prepare(int32_t, int32_t, val_t) const { return {}; }
+  __device__ __forceinline__ bool commit(const pre_t &, int32_t pos, int32_t, val_t, int32_t, int32_t gt,
+                                         uint32_t) const {
+    add_relaxed(&hits[pos], 1);
     thread_of[pos] = gt;
     return true;
   }
@@ -136,18 +187,18 @@ struct OpRecord {  // counts each processed edge and the thread that took it; pu
 template <class Op>
 Op make_op(const Args &a);
 template <>
-OpBFS make_op<OpBFS>(const Args &a) { return OpBFS{a.labels}; }
+OpBFS make_op<OpBFS>(const Args &a) { return OpBFS{a.level}; }
 template <>
-OpSSSP make_op<OpSSSP>(const Args &a) { return OpSSSP{a.labels, a.w}; }
+OpSSSP make_op<OpSSSP>(const Args &a) { return OpSSSP{a.word, a.w, a.dedup}; }
 template <>
-OpCC make_op<OpCC>(const Args &a) { return OpCC{a.labels}; }
+OpCC make_op<OpCC>(const Args &a) { return OpCC{a.word, a.dedup}; }
 template <>
 OpPR make_op<OpPR>(const Args &a) { return OpPR{a.rank, a.acc}; }
 template <>
 OpRecord make_op<OpRecord>(const Args &a) { return OpRecord{a.hits, a.thread_of}; }
 
 // ---------------------------------------------------------------------------
-// Per-thread statistics and shared memory.
+// Per-thread statistics, shared memory, work-distribution grid, push staging.
 // ---------------------------------------------------------------------------
 
 struct Acc {
@@ -158,9 +209,9 @@ struct Acc {
 template <int B, class Op>
 struct Smem {
   using V = typename Op::val_t;
-  int32_t pos[B];  // thread-bin gather: CSR position, source value and source of each staged edge
-  V sv[B];
-  int32_t src[Op::kNeedSrc ? B : 1];
+  int32_t pos[kU * B];  // thread-bin gather: CSR position, source value and source of each staged edge
+  V sv[kU * B];
+  int32_t src[Op::kNeedSrc ? kU * B : 1];
   int32_t wsum[B / kWave];
   unsigned long long ured[B / kWave][5];
   unsigned long long dred[B / kWave];
@@ -170,8 +221,6 @@ struct Smem {
   int32_t pbuf[B / kWave][kPushBuf];  // per-wavefront push staging
 };
 
-// Next-worklist pushes of one wavefront, staged in LDS and written out in
-// batches: one global reservation per batch instead of one per ballot.
 // The workgroup's index and the workgroup count used for work distribution:
 // the hardware ones for one-phase launches, the membership ticket and the
 // member count inside the persistent launch.
@@ -180,6 +229,8 @@ struct Grid {
   uint32_t n;
 };
 
+// Next-worklist pushes of one wavefront, staged in LDS and written out in
+// batches: one global reservation per batch instead of one per ballot.
 struct Pusher {
   int32_t *buf;      // this wavefront's LDS staging area
   uint32_t cnt;      // entries staged (wave-uniform)
@@ -229,10 +280,6 @@ __device__ void flush_dangling(Acc &acc, Smem<B, Op> &sm, unsigned long long *ds
   acc.dangling = 0;
 }
 
-// ---------------------------------------------------------------------------
-// Wave-aggregated push and huge-worklist reservation.
-// ---------------------------------------------------------------------------
-
 // Write the staged entries to the next worklist (all lanes call this).
 __device__ __forceinline__ void flush_pushes(const Args &a, int round, Pusher &pu) {
   if (pu.cnt == 0) return;
@@ -262,13 +309,25 @@ __device__ __forceinline__ void push_wave(bool pred, int32_t v, const Args &a, i
   if (lane_id() == 0) acc.pushes += total;
 }
 
-// Algorithm 1, "work.push(src)": append every huge lane's vertex to `work`
-// and its degree to the running edge total with ONE 64-bit atomic per
-// wavefront on (count << 32 | edges).  Slot j receives prefix[j] = the edges
-// of all earlier slots, i.e. the exclusive scan of the huge degrees in
-// worklist order.  All lanes of the wavefront must call this.
-__device__ __forceinline__ void reserve_huge(bool huge, int32_t v, int32_t deg, const Args &a, int round,
-                                             unsigned long long *ctr, Acc &acc) {
+// log2 of the chunk size of the huge-edge index for a threshold t: the
+// largest power of two not above t, clamped, so that a chunk holds at most
+// two segment starts when t >= 2^kHintMinShift.
+__device__ __forceinline__ uint32_t hint_shift(int64_t t) {
+  if (t < (1ll << kHintMinShift)) return kHintMinShift;
+  if (t >= (1ll << kHintMaxShift)) return kHintMaxShift;
+  return 63u - (uint32_t)__builtin_clzll((unsigned long long)t);
+}
+
+// Algorithm 1, "work.push(src)": append every huge lane's vertex to the huge
+// list and its degree to the running edge total with ONE 64-bit atomic per
+// wavefront on (count << 32 | edges).  Slot j receives the edges of all
+// earlier slots as its prefixWork entry, i.e. the exclusive scan of the huge
+// degrees in list order, with the vertex's CSR start and source value.  The
+// wavefront then writes the chunk index for every chunk whose first edge
+// falls in one of its new segments.  All lanes of the wavefront call this.
+__device__ __forceinline__ void reserve_huge(bool huge, int32_t v, int32_t beg, int32_t deg, int32_t sv_bits,
+                                             const Args &a, int round, unsigned long long *ctr, uint32_t hs,
+                                             Acc &acc) {
   const unsigned long long hm = __ballot(huge);
   if (hm == 0ull) return;
   const uint32_t lane = lane_id();
@@ -282,46 +341,66 @@ __device__ __forceinline__ void reserve_huge(bool huge, int32_t v, int32_t deg, 
   const unsigned long long tot_e = __shfl(incl, kWave - 1);
   const uint32_t tot_c = (uint32_t)__popcll(hm);
   unsigned long long base = 0;
+  int bad = 0;
   if (lane == kWave - 1) {
     if (tot_e >> 32) {
-      flag_overflow(a.ctl, round);
+      bad = 1;
     } else {
       base = add_relaxed(ctr, ((unsigned long long)tot_c << 32) | tot_e);
-      if ((unsigned long long)(uint32_t)base + tot_e > 0xffffffffull) flag_overflow(a.ctl, round);
+      if ((unsigned long long)(uint32_t)base + tot_e > 0xffffffffull) bad = 1;
       acc.huge_v += tot_c;
     }
+    if (bad) flag_overflow(a.ctl, round);
   }
   base = __shfl(base, kWave - 1);
+  bad = __shfl(bad, kWave - 1);
+  if (bad) return;  // the round is abandoned; nothing below may be trusted
+  uint32_t j = 0, p = 0;
   if (huge) {
-    const uint32_t j = (uint32_t)(base >> 32) + bits_below(hm);
-    const uint32_t p = (uint32_t)base + (uint32_t)(incl - mine);
-    if (j < a.qcap) {
-      a.work[j] = v;
-      a.prefix[j] = p;
-    } else {
+    j = (uint32_t)(base >> 32) + bits_below(hm);
+    p = (uint32_t)base + (uint32_t)(incl - mine);
+    if (j < a.qcap)
+      a.huge_rec[j] = make_int4((int32_t)p, beg, v, sv_bits);
+    else
       flag_overflow(a.ctl, round);
+  }
+  // chunk index: chunk c's first edge c << hs lies in [p, p + deg)
+  unsigned long long rem = hm;
+  while (rem) {
+    const int l = __ffsll(rem) - 1;
+    rem &= rem - 1;
+    const uint32_t jj = __shfl(j, l), pp = __shfl(p, l);
+    const uint32_t dd = (uint32_t)__shfl(deg, l);
+    const uint64_t c_lo = ((uint64_t)pp + (1ull << hs) - 1) >> hs;
+    const uint64_t c_hi = ((uint64_t)pp + dd - 1) >> hs;
+    for (uint64_t c = c_lo + lane; c <= c_hi; c += kWave) {
+      if (c < a.hint_cap)
+        a.hint[c] = (int32_t)jj;
+      else
+        flag_overflow(a.ctl, round);
     }
   }
 }
 
-// Apply the operator along one edge (if act) and push; every lane calls it.
+// Apply the operator along up to kU edges per lane and push; every lane of
+// the wavefront calls this (act[u] false for empty slots).
 template <class Op>
-__device__ __forceinline__ void edge(bool act, int32_t pos, typename Op::val_t sv, int32_t src, const Op &op,
-                                     const Args &a, int round, Pusher &pu, Acc &acc, int32_t gt) {
-  bool p = false;
-  int32_t dst = 0;
-  if (act) {
-    dst = a.col[pos];
-    p = op.apply(sv, pos, dst, src, gt);
-    if constexpr (Op::kPush) {
-      // dedup: push once per round; a stamp equal to this round can only have
-      // been written this round, so the plain load is a safe filter
-      if (p && a.stamp)
-        p = a.stamp[dst] != round &&
-            __hip_atomic_exchange(&a.stamp[dst], round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != round;
-    }
+__device__ __forceinline__ void edges(const bool (&act)[kU], const int32_t (&pos)[kU],
+                                      const typename Op::val_t (&sv)[kU], const int32_t (&src)[kU], const Op &op,
+                                      const Args &a, uint32_t tag, int round, Pusher &pu, Acc &acc, int32_t gt) {
+  int32_t dst[kU];
+  typename Op::pre_t pre[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) dst[u] = a.col[act[u] ? pos[u] : 0];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) pre[u] = op.prepare(act[u] ? pos[u] : 0, dst[u], sv[u]);
+  bool p[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) p[u] = act[u] && op.commit(pre[u], pos[u], dst[u], sv[u], src[u], gt, tag);
+  if constexpr (Op::kPush) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) push_wave(p[u], dst[u], a, round, pu, acc);
   }
-  if constexpr (Op::kPush) push_wave(p, dst, a, round, pu, acc);
 }
 
 template <int B>
@@ -353,12 +432,14 @@ __device__ __forceinline__ void block_exscan(int32_t x, int32_t &excl, int32_t &
 // ---------------------------------------------------------------------------
 template <int B, class Op>
 __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, int round, const int32_t *F,
-                          uint32_t nF, int32_t *qn, uint32_t *qn_cnt, unsigned long long *hctr, Acc &acc) {
+                          uint32_t nF, int32_t *qn, uint32_t *qn_cnt, unsigned long long *hctr, uint32_t hs,
+                          Acc &acc) {
   using V = typename Op::val_t;
   const int tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const uint32_t stride = gr.n * B;
   const int32_t gt = (int32_t)(gr.id * B + tid);
+  const uint32_t tag = (uint32_t)round + 1u;
   Pusher pu{sm.pbuf[tid / kWave], 0u, qn, qn_cnt};
   for (uint32_t base = gr.id * B; base < nF; base += stride) {
     const uint32_t i = base + tid;
@@ -368,9 +449,11 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       beg = a.off[v];
       deg = a.off[v + 1] - beg;
     }
-    // inspection: degree >= THRESHOLD goes to the huge worklist
+    V sv = V(0);
+    if (deg > 0) sv = op.load_src(v, deg);
+    // inspection: degree >= THRESHOLD goes to the huge list
     const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= a.threshold;
-    reserve_huge(huge, v, deg, a, round, hctr, acc);
+    reserve_huge(huge, v, beg, deg, to_bits(sv), a, round, hctr, hs, acc);
     if constexpr (Op::kRecord) {
       if (i < nF) a.bins[i] = (int8_t)(huge ? 3 : deg >= a.c_wg ? 2 : deg >= a.c_wave ? 1 : 0);
     }
@@ -380,8 +463,6 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
     if (huge) deg = 0;
     acc.frontier += (v >= 0);
     acc.edges_twc += (unsigned long long)deg;
-    V sv = V(0);
-    if (deg > 0) sv = op.load_src(v, deg);
 
     // workgroup bin: the whole workgroup strides one vertex's edges
     for (;;) {
@@ -401,9 +482,19 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       __syncthreads();
       const int32_t ob = sm.obeg, od = sm.odeg, ov = sm.ov;
       const V os = sm.osv;
-      for (int32_t j0 = 0; j0 < od; j0 += B) {
-        const int32_t j = j0 + tid;
-        edge<Op>(j < od, ob + j, os, ov, op, a, round, pu, acc, gt);
+      for (int32_t j0 = 0; j0 < od; j0 += kU * B) {
+        bool act[kU];
+        int32_t pos[kU], src[kU];
+        V s[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int32_t j = j0 + u * B + tid;
+          act[u] = j < od;
+          pos[u] = ob + j;
+          s[u] = os;
+          src[u] = ov;
+        }
+        edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       }
     }
 
@@ -411,62 +502,77 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
     for (;;) {
       const unsigned long long mm = __ballot(deg > 0 && deg >= a.c_wave);
       if (mm == 0ull) break;
-      const int ld = __ffsll((unsigned long long)mm) - 1;
+      const int ld = __ffsll(mm) - 1;
       const int32_t ob = __shfl(beg, ld), od = __shfl(deg, ld), ov = __shfl(v, ld);
       const V os = __shfl(sv, ld);
       if ((int)lane == ld) deg = 0;
-      for (int32_t j0 = 0; j0 < od; j0 += kWave) {
-        const int32_t j = j0 + (int32_t)lane;
-        edge<Op>(j < od, ob + j, os, ov, op, a, round, pu, acc, gt);
+      for (int32_t j0 = 0; j0 < od; j0 += kU * kWave) {
+        bool act[kU];
+        int32_t pos[kU], src[kU];
+        V s[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int32_t j = j0 + u * kWave + (int32_t)lane;
+          act[u] = j < od;
+          pos[u] = ob + j;
+          s[u] = os;
+          src[u] = ov;
+        }
+        edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       }
     }
 
     // thread bin: fine-grained gather of the remaining short lists through LDS,
-    // B edges at a time, so that the workgroup's lanes stay busy
+    // kU * B edges at a time, so that the workgroup's lanes stay busy
     int32_t rank, total;
     block_exscan<B>(deg, rank, total, sm.wsum);
-    for (int32_t done = 0; done < total; done += B) {
-      const int32_t lo = max(rank, done), hi = min(rank + deg, done + B);
+    for (int32_t done = 0; done < total; done += kU * B) {
+      const int32_t lo = max(rank, done), hi = min(rank + deg, done + kU * B);
       for (int32_t e = lo; e < hi; ++e) {
         sm.pos[e - done] = beg + (e - rank);
         sm.sv[e - done] = sv;
         if constexpr (Op::kNeedSrc) sm.src[e - done] = v;
       }
       __syncthreads();
-      const int32_t cnt = min(B, total - done);
-      const bool act = tid < cnt;
-      int32_t p = 0, s = 0;
-      V x = V(0);
-      if (act) {
-        p = sm.pos[tid];
-        x = sm.sv[tid];
-        if constexpr (Op::kNeedSrc) s = sm.src[tid];
+      const int32_t cnt = min(kU * B, total - done);
+      bool act[kU];
+      int32_t pos[kU], src[kU];
+      V s[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int32_t idx = u * B + tid;
+        act[u] = idx < cnt;
+        pos[u] = act[u] ? sm.pos[idx] : 0;
+        s[u] = act[u] ? sm.sv[idx] : V(0);
+        src[u] = 0;
+        if constexpr (Op::kNeedSrc) src[u] = act[u] ? sm.src[idx] : 0;
       }
-      edge<Op>(act, p, x, s, op, a, round, pu, acc, gt);
+      edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       __syncthreads();
     }
   }
   if constexpr (Op::kPush) flush_pushes(a, round, pu);
 }
 
-// Largest j in [lo, vh) with prefix[j] <= k, given prefix[lo] <= k:
-// exponential search forward from lo, then bisection.
-__device__ __forceinline__ uint32_t owner_from(const uint32_t *prefix, uint32_t vh, uint32_t lo, uint32_t k) {
-  uint64_t j = lo, step = 1, hi = (uint64_t)lo + 1;
-  while (hi < vh && prefix[hi] <= k) {
-    j = hi;
+// The huge-list slot whose edge range holds huge edge k: the last slot j with
+// prefixWork[j] <= k.  The chunk index gives a slot at or before the answer;
+// an exponential search forward from it, then bisection, finds the answer.
+__device__ __forceinline__ uint32_t owner_of(const Args &a, uint32_t vh, uint32_t hs, uint32_t k) {
+  uint64_t lo = (uint32_t)a.hint[k >> hs], step = 1, hi = lo + 1;
+  while (hi < vh && (uint32_t)a.huge_rec[hi].x <= k) {
+    lo = hi;
     step <<= 1;
-    hi = j + step;
+    hi = lo + step;
   }
   if (hi > vh) hi = vh;
-  while (hi - j > 1) {
-    const uint64_t mid = j + ((hi - j) >> 1);
-    if (prefix[mid] <= k)
-      j = mid;
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if ((uint32_t)a.huge_rec[mid].x <= k)
+      lo = mid;
     else
       hi = mid;
   }
-  return (uint32_t)j;
+  return (uint32_t)lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -474,40 +580,39 @@ __device__ __forceinline__ uint32_t owner_from(const uint32_t *prefix, uint32_t 
 // ---------------------------------------------------------------------------
 template <int B, class Op>
 __device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, int round, unsigned long long hc,
-                         int32_t *qn, uint32_t *qn_cnt, Acc &acc) {
+                         int32_t *qn, uint32_t *qn_cnt, uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
   const uint32_t vh = (uint32_t)(hc >> 32);
   const uint32_t e = (uint32_t)hc;
   if (vh == 0) return;
-  // an overflowed reservation leaves prefix inconsistent with the degrees: skip
+  // an overflowed reservation leaves the huge list inconsistent: skip
   if (ld_relaxed(&a.ctl->overflow) <= (uint32_t)round) return;
   const uint64_t T = (uint64_t)gr.n * B;
   const uint32_t lane = lane_id();
   const uint64_t g = (uint64_t)gr.id * B + threadIdx.x;
-  uint32_t s = 0;  // owner of the wavefront's first edge; never decreases
-  uint32_t c_s = 0xffffffffu;
-  int32_t c_src = 0, c_beg = 0;
-  uint32_t c_p = 0;
-  V c_sv = V(0);
+  const uint32_t tag = (uint32_t)round + 1u;
   Pusher pu{sm.pbuf[threadIdx.x / kWave], 0u, qn, qn_cnt};
-  for (uint64_t k0 = g - lane; k0 < e; k0 += T) {
-    s = owner_from(a.prefix, vh, s, (uint32_t)k0);
-    const uint64_t k = k0 + lane;
-    const bool act = k < e;
-    if (act) {
-      uint32_t ss = s;
-      const uint32_t nxt = (s + 1 < vh) ? a.prefix[s + 1] : e;
-      if ((uint32_t)k >= nxt) ss = owner_from(a.prefix, vh, s + 1, (uint32_t)k);
-      if (ss != c_s) {
-        c_s = ss;
-        c_src = a.work[ss];
-        c_beg = a.off[c_src];
-        c_p = a.prefix[ss];
-        c_sv = op.load_src(c_src, a.off[c_src + 1] - c_beg);
+  // thread g takes huge edges g, g + T, g + 2T, ...; kU of them per pass
+  for (uint64_t k0 = g - lane; k0 < e; k0 += kU * T) {
+    bool act[kU];
+    int32_t pos[kU], src[kU];
+    V s[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint64_t k = k0 + lane + (uint64_t)u * T;
+      act[u] = k < e;
+      pos[u] = 0;
+      src[u] = 0;
+      s[u] = V(0);
+      if (act[u]) {
+        const int4 r = a.huge_rec[owner_of(a, vh, hs, (uint32_t)k)];
+        pos[u] = r.y + (int32_t)((uint32_t)k - (uint32_t)r.x);
+        src[u] = r.z;
+        s[u] = from_bits<V>(r.w);
       }
+      acc.edges_lb += act[u];
     }
-    acc.edges_lb += act;
-    edge<Op>(act, c_beg + (int32_t)((uint32_t)k - c_p), c_sv, c_src, op, a, round, pu, acc, (int32_t)g);
+    edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, (int32_t)g);
   }
   if constexpr (Op::kPush) flush_pushes(a, round, pu);
 }
@@ -525,43 +630,54 @@ __device__ void phase_pr_update(const Args &a, Grid gr, unsigned long long dangl
   }
 }
 
-// Grid-wide barrier over a monotone arrival counter.  After the workgroup
-// barrier, thread 0 alone releases the workgroup's writes at agent scope
-// (L2 write-back across the 8 XCDs), arrives with one RMW and spins with
-// relaxed loads and s_sleep until every workgroup has arrived, then acquires
-// (L1/L2 invalidate) before the workgroup barrier lets the others on.  A wait
-// longer than timeout_ticks sets ctl->abort, which makes every workgroup
-// leave at its next barrier.
+// Grid-wide barrier among the members of the persistent launch.  After the
+// workgroup barrier, thread 0 alone releases the workgroup's writes at agent
+// scope (L2 write-back across the 8 XCDs) and arrives on its group counter;
+// the last of a group arrives on the root counter, and the last root arrival
+// publishes the next generation.  Thread 0 polls the generation with relaxed
+// loads and s_sleep, then acquires (L1/L2 invalidate) before the workgroup
+// barrier lets the other waves on.  The counters only grow, so nothing is
+// reset between barriers.  A wait longer than timeout_ticks sets ctl->abort,
+// which makes every workgroup leave at its next barrier.
 template <class S>
-__device__ bool grid_barrier(const Args &a, S &sm, Grid gr, int round) {
+__device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round) {
   __syncthreads();
   if (threadIdx.x == 0) {
+    unsigned long long *b = a.bar;
     Ctl *c = a.ctl;
-    const unsigned long long nb = gr.n;
+    const uint32_t grp = gr.id / kBarGroup;
+    const uint32_t ngrp = (gr.n + kBarGroup - 1) / kBarGroup;
+    const uint32_t gsz = min((uint32_t)kBarGroup, gr.n - grp * kBarGroup);
+    const unsigned long long target = epoch + 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned long long arrived = add_relaxed(&c->bar_count, 1ull);
-    const unsigned long long target = (arrived / nb + 1ull) * nb;
+    const unsigned long long o1 = add_relaxed(&b[kBarGroups + (size_t)kBarStride * grp], 1ull);
+    if ((o1 + 1) % gsz == 0) {
+      const unsigned long long o2 = add_relaxed(&b[kBarRoot], 1ull);
+      if ((o2 + 1) % ngrp == 0) st_relaxed(&b[kBarGen], target);
+    }
     int ok = 1;
     const uint64_t t0 = (uint64_t)wall_clock64();
-    while (ld_relaxed(&c->bar_count) < target) {
+    unsigned long long seen;
+    while ((seen = ld_relaxed(&b[kBarGen])) < target) {
       if (ld_relaxed(&c->abort)) {
         ok = 0;
         break;
       }
       if ((uint64_t)wall_clock64() - t0 > a.timeout_ticks) {
-        st_relaxed(&c->diag_seen, ld_relaxed(&c->bar_count));
+        st_relaxed(&c->diag_seen, seen);
         st_relaxed(&c->diag_target, target);
         st_relaxed(&c->diag_round, (uint32_t)round);
         st_relaxed(&c->abort, 1u);
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(4);
+      __builtin_amdgcn_s_sleep(2);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     sm.flag = ok;
   }
   __syncthreads();
+  ++epoch;
   return sm.flag != 0;
 }
 
@@ -582,75 +698,6 @@ __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
   st_relaxed(&a.ctl->qcount[(r + 2) % 3], 0u);
   st_relaxed(&a.ctl->huge[(r + 1) & 1], 0ull);
   st_relaxed(&a.ctl->dangling[(r + 1) & 1], 0ull);
-}
-
-// ---------------------------------------------------------------------------
-// Kernels.
-// ---------------------------------------------------------------------------
-
-__global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
-  const uint32_t stride = gridDim.x * blockDim.x;
-  const float r0 = 1.0f / (float)a.n;
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)a.n; v += stride) {
-    if (a.labels) a.labels[v] = (op == OP_CC) ? (int32_t)v : ((int32_t)v == source ? 0 : kInf);
-    if (a.stamp) a.stamp[v] = -1;
-    if (op == OP_PR) {
-      a.rank[v] = r0;
-      a.acc[v] = 0ull;
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Ctl *c = a.ctl;
-    c->qcount[0] = nfront0;
-    c->qcount[1] = 0;
-    c->qcount[2] = 0;
-    c->overflow = 0xffffffffu;
-    c->huge[0] = 0;
-    c->huge[1] = 0;
-    c->bar_count = 0;
-    c->abort = 0;
-    c->rounds = 0;
-    c->st_frontier = c->st_edges_twc = c->st_edges_lb = c->st_huge_v = c->st_pushes = 0;
-    c->dangling[0] = 0;
-    c->dangling[1] = 0;
-    c->members = 0;
-    c->n_members = 0;
-    c->diag_seen = c->diag_target = 0;
-    c->diag_round = 0;
-    c->threshold_used = a.threshold;
-    if (source >= 0 && op != OP_RECORD) a.q0[0] = source;
-  }
-}
-
-template <int B, class Op>
-__global__ __launch_bounds__(B) void k_twc(Args a, Op op) {
-  __shared__ Smem<B, Op> sm;
-  Acc acc;
-  const int r = a.round;
-  const uint32_t nF = round_size(a, r);
-  if (blockIdx.x == 0 && threadIdx.x == 0) clear_ahead(a, r);
-  const Grid gr{blockIdx.x, gridDim.x};
-  phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
-                   &a.ctl->huge[r & 1], acc);
-  if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
-  flush_stats<B, Op>(acc, sm, a.ctl);
-}
-
-template <int B, class Op>
-__global__ __launch_bounds__(B) void k_lb(Args a, Op op) {
-  __shared__ Smem<B, Op> sm;
-  Acc acc;
-  const int r = a.round;
-  const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
-  phase_lb<B, Op>(a, op, sm, Grid{blockIdx.x, gridDim.x}, r, hc, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
-                  acc);
-  flush_stats<B, Op>(acc, sm, a.ctl);
-}
-
-template <int B>
-__global__ __launch_bounds__(B) void k_pr_update(Args a) {
-  phase_pr_update<B>(a, Grid{blockIdx.x, gridDim.x}, ld_relaxed(&a.ctl->dangling[a.round & 1]));
-  if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->rounds, (uint32_t)a.round + 1u);
 }
 
 // Membership of the persistent launch.  The grid may be larger than what the
@@ -684,8 +731,8 @@ __device__ bool join_members(const Args &a, S &sm, Grid *gr) {
         }
         __builtin_amdgcn_s_sleep(1);
       }
-      const unsigned long long prev = __hip_atomic_fetch_or(&c->members, kClosed, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long prev =
+          __hip_atomic_fetch_or(&c->members, kClosed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       st_relaxed(&c->n_members, (uint32_t)prev);
     }
     uint32_t n = 0;
@@ -706,6 +753,83 @@ __device__ bool join_members(const Args &a, S &sm, Grid *gr) {
   return member;
 }
 
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+
+__global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const float r0 = 1.0f / (float)a.n;
+  for (uint32_t v = t; v < (uint32_t)a.n; v += stride) {
+    if (op == OP_BFS) a.level[v] = ((int32_t)v == source) ? 0 : kInf;
+    if (op == OP_SSSP) a.word[v] = (unsigned long long)(uint32_t)((int32_t)v == source ? 0 : kInf) << 32;
+    if (op == OP_CC) a.word[v] = (unsigned long long)v << 32;
+    if (op == OP_PR) {
+      a.rank[v] = r0;
+      a.acc[v] = 0ull;
+    }
+  }
+  for (size_t i = t; i < kBarWords; i += stride) a.bar[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl *c = a.ctl;
+    c->qcount[0] = nfront0;
+    c->qcount[1] = 0;
+    c->qcount[2] = 0;
+    c->overflow = 0xffffffffu;
+    c->huge[0] = 0;
+    c->huge[1] = 0;
+    c->abort = 0;
+    c->rounds = 0;
+    c->st_frontier = c->st_edges_twc = c->st_edges_lb = c->st_huge_v = c->st_pushes = 0;
+    c->dangling[0] = 0;
+    c->dangling[1] = 0;
+    c->members = 0;
+    c->n_members = 0;
+    c->diag_seen = c->diag_target = 0;
+    c->diag_round = 0;
+    c->threshold_used = a.threshold;
+    if (source >= 0 && op != OP_RECORD) a.q0[0] = source;
+  }
+}
+
+__global__ void k_finish(Args a) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)a.n; v += stride)
+    a.out[v] = (int32_t)(a.word[v] >> 32);
+}
+
+template <int B, class Op>
+__global__ __launch_bounds__(B) void k_twc(Args a, Op op) {
+  __shared__ Smem<B, Op> sm;
+  Acc acc;
+  const int r = a.round;
+  const uint32_t nF = round_size(a, r);
+  if (blockIdx.x == 0 && threadIdx.x == 0) clear_ahead(a, r);
+  const Grid gr{blockIdx.x, gridDim.x};
+  phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
+                   &a.ctl->huge[r & 1], hint_shift(a.threshold), acc);
+  if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
+  flush_stats<B, Op>(acc, sm, a.ctl);
+}
+
+template <int B, class Op>
+__global__ __launch_bounds__(B) void k_lb(Args a, Op op) {
+  __shared__ Smem<B, Op> sm;
+  Acc acc;
+  const int r = a.round;
+  const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
+  phase_lb<B, Op>(a, op, sm, Grid{blockIdx.x, gridDim.x}, r, hc, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
+                  hint_shift(a.threshold), acc);
+  flush_stats<B, Op>(acc, sm, a.ctl);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_pr_update(Args a) {
+  phase_pr_update<B>(a, Grid{blockIdx.x, gridDim.x}, ld_relaxed(&a.ctl->dangling[a.round & 1]));
+  if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->rounds, (uint32_t)a.round + 1u);
+}
+
 template <int B, class Op>
 __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
   __shared__ Smem<B, Op> sm;
@@ -713,6 +837,8 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
   Grid gr;
   if (!join_members(a, sm, &gr)) return;
   if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // default: the launched thread count
+  const uint32_t hs = hint_shift(a.threshold);
+  unsigned long long epoch = 0;
   int r = 0;
   for (; r < a.max_rounds; ++r) {
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;  // set in an earlier round: seen by all alike
@@ -723,22 +849,22 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
     if (tl) a.ctl->tl[4 * r] = (unsigned long long)wall_clock64();
     int32_t *qn = round_next(a, r);
     uint32_t *qn_cnt = &a.ctl->qcount[(r + 1) % 3];
-    phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], acc);
+    phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], hs, acc);
     if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
-    if (!grid_barrier(a, sm, gr, r)) break;
+    if (!grid_barrier(a, sm, gr, epoch, r)) break;
     const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
     if (tl) {
       a.ctl->tl[4 * r + 1] = (unsigned long long)wall_clock64();
       a.ctl->tl[4 * r + 3] = (unsigned long long)nF | ((hc >> 32) << 32);
     }
     if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
-      phase_lb<B, Op>(a, op, sm, gr, r, hc, qn, qn_cnt, acc);
-      if (!grid_barrier(a, sm, gr, r)) break;
+      phase_lb<B, Op>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+      if (!grid_barrier(a, sm, gr, epoch, r)) break;
     }
     if (tl) a.ctl->tl[4 * r + 2] = (unsigned long long)wall_clock64();
     if constexpr (Op::kPR) {
       phase_pr_update<B>(a, gr, ld_relaxed(&a.ctl->dangling[r & 1]));
-      if (!grid_barrier(a, sm, gr, r)) break;
+      if (!grid_barrier(a, sm, gr, epoch, r)) break;
     }
   }
   if (gr.id == 0 && threadIdx.x == 0) {
@@ -753,24 +879,32 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
 // ---------------------------------------------------------------------------
 
 template <int B, class Op>
-hipError_t twc_t(int grid, const Args &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_twc<B, Op>), dim3(grid), dim3(B), 0, s, a, make_op<Op>(a));
-  return hipGetLastError();
-}
+struct TwcF {
+  static hipError_t run(int grid, const Args *a, hipStream_t s) {
+    hipLaunchKernelGGL((k_twc<B, Op>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
+    return hipGetLastError();
+  }
+};
 template <int B, class Op>
-hipError_t lb_t(int grid, const Args &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_lb<B, Op>), dim3(grid), dim3(B), 0, s, a, make_op<Op>(a));
-  return hipGetLastError();
-}
+struct LbF {
+  static hipError_t run(int grid, const Args *a, hipStream_t s) {
+    hipLaunchKernelGGL((k_lb<B, Op>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
+    return hipGetLastError();
+  }
+};
 template <int B, class Op>
-hipError_t persistent_t(int grid, const Args &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_persistent<B, Op>), dim3(grid), dim3(B), 0, s, a, make_op<Op>(a));
-  return hipGetLastError();
-}
+struct PersistentF {
+  static hipError_t run(int grid, const Args *a, hipStream_t s) {
+    hipLaunchKernelGGL((k_persistent<B, Op>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
+    return hipGetLastError();
+  }
+};
 template <int B, class Op>
-hipError_t occupancy_t(int *blocks) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_persistent<B, Op>, B, 0);
-}
+struct OccF {
+  static hipError_t run(int *blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_persistent<B, Op>, B, 0);
+  }
+};
 
 template <template <int, class> class F, int B, typename... Xs>
 hipError_t by_op(OpKind op, Xs... xs) {
@@ -794,23 +928,6 @@ hipError_t by_wg(OpKind op, int wg, Xs... xs) {
   return hipErrorInvalidValue;
 }
 
-template <int B, class Op>
-struct TwcF {
-  static hipError_t run(int grid, const Args *a, hipStream_t s) { return twc_t<B, Op>(grid, *a, s); }
-};
-template <int B, class Op>
-struct LbF {
-  static hipError_t run(int grid, const Args *a, hipStream_t s) { return lb_t<B, Op>(grid, *a, s); }
-};
-template <int B, class Op>
-struct PersistentF {
-  static hipError_t run(int grid, const Args *a, hipStream_t s) { return persistent_t<B, Op>(grid, *a, s); }
-};
-template <int B, class Op>
-struct OccF {
-  static hipError_t run(int *blocks) { return occupancy_t<B, Op>(blocks); }
-};
-
 }  // namespace
 
 bool supported_wg(int wg) { return wg == 64 || wg == 256 || wg == 1024; }
@@ -819,8 +936,17 @@ hipError_t launch_init(OpKind op, const Args &a, int32_t source, uint32_t nfront
   const int threads = 256;
   int blocks = (int)(((int64_t)a.n + threads - 1) / threads);
   if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
+  if (blocks < 128) blocks = 128;
   hipLaunchKernelGGL(k_init, dim3(blocks), dim3(threads), 0, s, a, (int)op, source, nfront0);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const Args &a, hipStream_t s) {
+  const int threads = 256;
+  int blocks = (int)(((int64_t)a.n + threads - 1) / threads);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -113,9 +113,22 @@ def test_sssp_matrix(alb, name):
         assert np.array_equal(d, ref), (name, c)
         if c.get("mode") == "twc":
             assert st["huge_vertices"] == 0
-    for dedup in (False, True):
-        d, _ = alb.sssp(dg, s, dedup=dedup, threshold=64)
-        assert np.array_equal(d, ref), (name, dedup)
+    d, _ = alb.sssp(dg, s, dedup=True, threshold=64)
+    assert np.array_equal(d, ref), name
+    check_no_dedup(alb, lambda **o: alb.sssp(dg, s, **o)[0], ref, g)
+
+
+def check_no_dedup(alb, run, ref, g):
+    """Without deduplication a vertex can be pushed once per improving edge,
+    so a round's worklist is bounded only by the edges examined: a big
+    capacity is given, and an exceeded one must be reported, never a wrong
+    answer."""
+    try:
+        got = run(dedup=False, threshold=64, worklist_capacity=64 * (g.n + g.m) + 64)
+    except alb.AlbError as e:
+        assert e.status == alb.ALB_E_OVERFLOW
+        return
+    assert np.array_equal(got, ref)
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
@@ -126,8 +139,7 @@ def test_cc_matrix(alb, name):
     for c in configs(dg.max_out_degree):
         lab, _ = alb.cc(dg, **c)
         assert np.array_equal(lab, ref), (name, c)
-    lab, _ = alb.cc(dg, dedup=False, threshold=64)
-    assert np.array_equal(lab, ref)
+    check_no_dedup(alb, lambda **o: alb.cc(dg, **o)[0], ref, g)
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
@@ -155,6 +167,17 @@ def test_pagerank_bitwise_reproducible(alb, name):
         if first is None:
             first = x
         assert np.array_equal(x, first), (name, c)
+
+
+def test_no_dedup_bounded_in_degree(alb):
+    """In-degree at most one: pushes per round are bounded by n even without
+    deduplication, so the default capacity always suffices."""
+    for g in [graph("path300"), graph("cycle257")]:
+        dg = alb.Graph(g.off, g.col, g.w)
+        for launch in ("host", "persistent"):
+            d, _ = alb.sssp(dg, 0, dedup=False, threshold=1, launch=launch)
+            assert np.array_equal(d, oracle.sssp(g, 0))
+        dg.close()
 
 
 def test_cc_disjoint_components(alb):
