@@ -69,7 +69,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--threshold", type=int, default=None,
-                    help="huge-degree threshold for the ALB run (default: the launched thread count)")
+                    help="huge-degree threshold for the ALB run (default: the library's, 4 x workgroup size)")
     ap.add_argument("--launch", default="auto")
     ap.add_argument("--sweep", action="store_true", help="also sweep the threshold over powers of two")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -134,6 +134,12 @@ def main():
     achieved = float(np.mean([b / (k * 1e-3) for b, k in zip(bytes_per, kms)])) / 1e9
     traffic = measured_traffic()
 
+    paper_rule = None
+    if not args.only_alb:
+        s3, st3 = measure(dict(base_opts, mode="alb", threshold="launched"), "alb t=launched threads")
+        paper_rule = {"value": round(args.steps * m_reached / s3 / 1e9, 3), "ms_per_step": round(1e3 * s3 / args.steps, 4),
+                      "huge_threshold": st3[-1]["huge_threshold"], "huge_vertices": st3[-1]["huge_vertices"]}
+
     sweep = None
     if args.sweep:
         sweep = {}
@@ -175,6 +181,7 @@ def main():
         "twc_only": {"value": round(args.steps * m_reached / twc_sec / 1e9, 3),
                      "ms_per_step": round(1e3 * twc_sec / args.steps, 4), "same_result": twc_ok,
                      "kernel_ms": round(float(np.mean([s["kernel_ms"] for s in twc_stats])), 4)},
+        "alb_paper_threshold_rule": paper_rule,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,

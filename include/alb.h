@@ -58,11 +58,15 @@ typedef enum {
  *           paper's "D-IrGL (LB)" configuration, Section 5.1). */
 typedef enum { ALB_MODE_ALB = 0, ALB_MODE_TWC_ONLY = 1, ALB_MODE_LB_ALL = 2 } alb_mode;
 
-/* Round driver.  HOST_LOOP launches one kernel per phase and reads two
- * counters back per round.  PERSISTENT runs every round inside one
- * cooperative launch with grid-wide barriers between phases.  AUTO picks
- * PERSISTENT when the device supports cooperative launches. */
+/* Round driver.  HOST_LOOP launches one kernel per phase and reads the
+ * worklist counters back every round.  PERSISTENT runs every round inside one
+ * launch with grid-wide barriers between phases; the workgroups that are
+ * running when the launch starts take part and any other leaves at once, so
+ * no co-residency is assumed.  AUTO picks PERSISTENT. */
 typedef enum { ALB_LAUNCH_AUTO = 0, ALB_LAUNCH_HOST_LOOP = 1, ALB_LAUNCH_PERSISTENT = 2 } alb_launch;
+
+/* Special values of alb_options.huge_threshold. */
+enum { ALB_THRESHOLD_DEFAULT = -1, ALB_THRESHOLD_LAUNCHED = -2 };
 
 /* Graph creation flags. */
 enum {
@@ -73,7 +77,9 @@ enum {
 typedef struct {
   uint32_t struct_size;      /* sizeof(alb_options); set by alb_options_init */
   int32_t mode;              /* alb_mode */
-  int64_t huge_threshold;    /* ALB mode: < 0 = launched threads (Section 4.1 default) */
+  int64_t huge_threshold;    /* ALB mode: degree >= this is huge; ALB_THRESHOLD_DEFAULT (-1) = 4 * wg_size
+                                (the edges one workgroup covers in one pass), ALB_THRESHOLD_LAUNCHED (-2) =
+                                the launched thread count (the paper's rule, Section 5) */
   int32_t wg_size;           /* 0 = 256; one of 64, 256, 1024 */
   int32_t wave_cutoff;       /* TWC wavefront bin: degree >= this (0 = 64) */
   int32_t wg_cutoff;         /* TWC workgroup bin: degree >= this (0 = wg_size) */

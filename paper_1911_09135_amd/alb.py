@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC = 1, 2
+THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED = -1, -2  # 4 * wg_size; the launched thread count (the paper's rule)
 MODES = {"alb": 0, "twc": 1, "twc_only": 1, "lb_all": 2}
 LAUNCHES = {"auto": 0, "host": 1, "host_loop": 1, "persistent": 2}
 INF = np.iinfo(np.int32).max
@@ -110,7 +111,12 @@ def make_options(mode: str = "alb", threshold: Optional[int] = None, wg_size: in
     o = Options()
     _check(_lib.alb_options_init(ctypes.byref(o)), "alb_options_init")
     o.mode = MODES[mode]
-    o.huge_threshold = -1 if threshold is None else int(threshold)
+    if threshold is None:
+        o.huge_threshold = THRESHOLD_DEFAULT
+    elif threshold == "launched":
+        o.huge_threshold = THRESHOLD_LAUNCHED
+    else:
+        o.huge_threshold = int(threshold)
     o.wg_size = int(wg_size)
     o.wave_cutoff = int(wave_cutoff)
     o.wg_cutoff = int(wg_cutoff)

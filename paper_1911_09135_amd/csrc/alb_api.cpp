@@ -322,6 +322,8 @@ alb_status resolve_options(const alb_options *user, alb_options &o) {
   if (o.launch < ALB_LAUNCH_AUTO || o.launch > ALB_LAUNCH_PERSISTENT) return fail(ALB_E_INVAL, "bad launch %d", o.launch);
   if (o.grid_wgs < 0) return fail(ALB_E_INVAL, "grid_wgs must be >= 0");
   if (o.worklist_capacity < 0 || o.worklist_capacity > 0xfffffffeLL) return fail(ALB_E_INVAL, "bad worklist_capacity");
+  if (o.huge_threshold < 0 && o.huge_threshold != ALB_THRESHOLD_DEFAULT && o.huge_threshold != ALB_THRESHOLD_LAUNCHED)
+    return fail(ALB_E_INVAL, "bad huge_threshold %lld", (long long)o.huge_threshold);
   return ALB_OK;
 }
 
@@ -413,8 +415,10 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     threshold = 0;
   else if (o.huge_threshold >= 0)
     threshold = o.huge_threshold;
+  else if (o.huge_threshold == ALB_THRESHOLD_LAUNCHED)
+    threshold = launch == ALB_LAUNCH_PERSISTENT ? -1 : T;  // the launched thread count (known on the device)
   else
-    threshold = launch == ALB_LAUNCH_PERSISTENT ? -1 : T;  // the launched thread count
+    threshold = (int64_t)kEdgesPerLanePass * wg;  // one pass of the workgroup over a vertex's edges
 
   bool dedup = false;
   if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);

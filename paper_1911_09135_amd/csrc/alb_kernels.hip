@@ -34,7 +34,7 @@ namespace alb {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kU = 4;               // edges in flight per lane
+constexpr int kU = kEdgesPerLanePass;  // edges in flight per lane
 constexpr uint32_t kPushBuf = 512;  // per-wavefront LDS staging of next-worklist pushes
 
 __device__ __forceinline__ uint32_t lane_id() {
@@ -90,7 +90,7 @@ struct OpBFS {  // level[dst] = level[src] + 1 on first visit
   };
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
   int32_t *level;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return level[v]; }
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t, uint32_t, bool &) const { return level[v]; }
   __device__ __forceinline__ pre_t prepare(int32_t, int32_t dst, val_t) const { return {level[dst]}; }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
@@ -117,6 +117,15 @@ __device__ __forceinline__ bool lower_word(unsigned long long *word, int32_t can
   return cand < (int32_t)(old >> 32) && (!dedup || (uint32_t)old != tag);
 }
 
+// The label of an active vertex.  If its tag shows that it was lowered again
+// during the current round, it is already on the next worklist and will be
+// processed there with the newer label, so relaxing its edges now (with the
+// older, larger label) is skipped.
+__device__ __forceinline__ int32_t label_of_active(unsigned long long w, uint32_t tag, bool &skip) {
+  skip = (uint32_t)w == tag;
+  return (int32_t)(w >> 32);
+}
+
 struct OpSSSP {  // relaxation: dist[dst] = min(dist[dst], dist[src] + w)
   using val_t = int32_t;
   struct pre_t {
@@ -127,7 +136,9 @@ struct OpSSSP {  // relaxation: dist[dst] = min(dist[dst], dist[src] + w)
   unsigned long long *word;
   const int32_t *w;
   int32_t dedup;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return (int32_t)(word[v] >> 32); }
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t, uint32_t tag, bool &skip) const {
+    return label_of_active(word[v], tag, skip);
+  }
   __device__ __forceinline__ pre_t prepare(int32_t pos, int32_t dst, val_t sv) const {
     return {sv + w[pos], word[dst]};
   }
@@ -145,7 +156,9 @@ struct OpCC {  // min-label propagation
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
   unsigned long long *word;
   int32_t dedup;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t) const { return (int32_t)(word[v] >> 32); }
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t, uint32_t tag, bool &skip) const {
+    return label_of_active(word[v], tag, skip);
+  }
   __device__ __forceinline__ pre_t prepare(int32_t, int32_t dst, val_t) const { return {word[dst]}; }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
                                          uint32_t tag) const {
@@ -159,7 +172,9 @@ struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact 
   static constexpr bool kPush = false, kNeedSrc = false, kRecord = false, kPR = true;
   const float *rank;
   unsigned long long *acc;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t deg) const { return rank[v] / (float)deg; }
+  __device__ __forceinline__ val_t load_src(int32_t v, int32_t deg, uint32_t, bool &) const {
+    return rank[v] / (float)deg;
+  }
   __device__ __forceinline__ pre_t prepare(int32_t, int32_t, val_t) const { return {}; }
   __device__ __forceinline__ bool commit(const pre_t &, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
@@ -174,7 +189,7 @@ struct OpRecord {  // counts each processed edge and the thread that took it; pu
   static constexpr bool kPush = true, kNeedSrc = true, kRecord = true, kPR = false;
   int32_t *hits;
   int32_t *thread_of;
-  __device__ __forceinline__ val_t load_src(int32_t, int32_t) const { return 0; }
+  __device__ __forceinline__ val_t load_src(int32_t, int32_t, uint32_t, bool &) const { return 0; }
   __device__ __forceinline__ pre_t prepare(int32_t, int32_t, val_t) const { return {}; }
   __device__ __forceinline__ bool commit(const pre_t &, int32_t pos, int32_t, val_t, int32_t, int32_t gt,
                                          uint32_t) const {
@@ -450,7 +465,11 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       deg = a.off[v + 1] - beg;
     }
     V sv = V(0);
-    if (deg > 0) sv = op.load_src(v, deg);
+    if (deg > 0) {
+      bool skip = false;
+      sv = op.load_src(v, deg, tag, skip);
+      if (skip) deg = 0;
+    }
     // inspection: degree >= THRESHOLD goes to the huge list
     const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= a.threshold;
     reserve_huge(huge, v, beg, deg, to_bits(sv), a, round, hctr, hs, acc);
@@ -836,7 +855,7 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
   Acc acc;
   Grid gr;
   if (!join_members(a, sm, &gr)) return;
-  if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // default: the launched thread count
+  if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // the launched thread count (the paper's rule)
   const uint32_t hs = hint_shift(a.threshold);
   unsigned long long epoch = 0;
   int r = 0;
