@@ -143,9 +143,8 @@ def main():
     sweep = None
     if args.sweep:
         sweep = {}
-        for e in [0] + list(range(6, 21, 2)):
-            thr = 0 if e == 0 else 1 << e
-            s2, st2 = measure(dict(base_opts, mode="alb", threshold=thr), "alb t=%d" % thr)
+        for thr in [0] + [1 << e for e in range(6, 21, 2)] + ["adaptive"]:
+            s2, st2 = measure(dict(base_opts, mode="alb", threshold=thr), "alb t=%s" % thr)
             sweep[str(thr)] = round(args.steps * m_reached / s2 / 1e9, 3)
 
     cpu = None

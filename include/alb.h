@@ -65,8 +65,11 @@ typedef enum { ALB_MODE_ALB = 0, ALB_MODE_TWC_ONLY = 1, ALB_MODE_LB_ALL = 2 } al
  * no co-residency is assumed.  AUTO picks PERSISTENT. */
 typedef enum { ALB_LAUNCH_AUTO = 0, ALB_LAUNCH_HOST_LOOP = 1, ALB_LAUNCH_PERSISTENT = 2 } alb_launch;
 
-/* Special values of alb_options.huge_threshold. */
-enum { ALB_THRESHOLD_DEFAULT = -1, ALB_THRESHOLD_LAUNCHED = -2 };
+/* Special values of alb_options.huge_threshold.  ADAPTIVE uses 64 (a
+ * wavefront's worth of edges) in rounds whose worklist has fewer entries than
+ * launched threads, where the TWC phase cannot occupy every workgroup, and the
+ * DEFAULT value otherwise. */
+enum { ALB_THRESHOLD_DEFAULT = -1, ALB_THRESHOLD_LAUNCHED = -2, ALB_THRESHOLD_ADAPTIVE = -3 };
 
 /* Graph creation flags. */
 enum {

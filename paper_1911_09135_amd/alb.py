@@ -24,7 +24,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC = 1, 2
-THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED = -1, -2  # 4 * wg_size; the launched thread count (the paper's rule)
+# 4 * wg_size; the launched thread count (the paper's rule); 64 in rounds smaller than the grid, else default
+THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED, THRESHOLD_ADAPTIVE = -1, -2, -3
 MODES = {"alb": 0, "twc": 1, "twc_only": 1, "lb_all": 2}
 LAUNCHES = {"auto": 0, "host": 1, "host_loop": 1, "persistent": 2}
 INF = np.iinfo(np.int32).max
@@ -115,6 +116,8 @@ def make_options(mode: str = "alb", threshold: Optional[int] = None, wg_size: in
         o.huge_threshold = THRESHOLD_DEFAULT
     elif threshold == "launched":
         o.huge_threshold = THRESHOLD_LAUNCHED
+    elif threshold == "adaptive":
+        o.huge_threshold = THRESHOLD_ADAPTIVE
     else:
         o.huge_threshold = int(threshold)
     o.wg_size = int(wg_size)

@@ -322,7 +322,8 @@ alb_status resolve_options(const alb_options *user, alb_options &o) {
   if (o.launch < ALB_LAUNCH_AUTO || o.launch > ALB_LAUNCH_PERSISTENT) return fail(ALB_E_INVAL, "bad launch %d", o.launch);
   if (o.grid_wgs < 0) return fail(ALB_E_INVAL, "grid_wgs must be >= 0");
   if (o.worklist_capacity < 0 || o.worklist_capacity > 0xfffffffeLL) return fail(ALB_E_INVAL, "bad worklist_capacity");
-  if (o.huge_threshold < 0 && o.huge_threshold != ALB_THRESHOLD_DEFAULT && o.huge_threshold != ALB_THRESHOLD_LAUNCHED)
+  if (o.huge_threshold < 0 && o.huge_threshold != ALB_THRESHOLD_DEFAULT && o.huge_threshold != ALB_THRESHOLD_LAUNCHED &&
+      o.huge_threshold != ALB_THRESHOLD_ADAPTIVE)
     return fail(ALB_E_INVAL, "bad huge_threshold %lld", (long long)o.huge_threshold);
   return ALB_OK;
 }
@@ -419,6 +420,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     threshold = launch == ALB_LAUNCH_PERSISTENT ? -1 : T;  // the launched thread count (known on the device)
   else
     threshold = (int64_t)kEdgesPerLanePass * wg;  // one pass of the workgroup over a vertex's edges
+  const bool adaptive = o.mode == ALB_MODE_ALB && o.huge_threshold == ALB_THRESHOLD_ADAPTIVE;
 
   bool dedup = false;
   if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);
@@ -460,12 +462,14 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.c_wave = o.wave_cutoff;
   a.c_wg = o.wg_cutoff;
   a.dedup = dedup ? 1 : 0;
+  a.adaptive = adaptive ? 1 : 0;
   a.identity_first = job.identity_first;
   a.all_rounds = job.all_rounds;
   a.max_rounds = job.max_rounds;
   a.round = 0;
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
   a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);  // 10 us without a new member
+  a.profile = getenv("ALB_TIMELINE") ? 1 : 0;
   if (job.op == OP_BFS) a.level = dev_out ? (int32_t *)dev_out : ws->labels;
   if (job.op == OP_SSSP || job.op == OP_CC) {
     a.word = ws->word;
@@ -549,6 +553,10 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
                 (unsigned)(t[3] & 0xffffffffu), (unsigned)(t[3] >> 32), (double)(t[1] - t[0]) * us,
                 (double)(t[2] - t[1]) * us);
       }
+      static const char *names[kProfParts] = {"inspect", "wg-bin", "wave-bin", "thread-bin", "lb", "barrier"};
+      fprintf(stderr, "[alb] workgroup-time per part (us summed over %u members):", c.n_members);
+      for (int k = 0; k < kProfParts; ++k) fprintf(stderr, " %s %.0f", names[k], (double)c.prof[k] * us);
+      fprintf(stderr, "\n");
     }
   }
   if (!job.all_rounds && job.max_rounds > 1 && rounds >= job.max_rounds && c.qcount[rounds % 3] != 0)

@@ -33,6 +33,10 @@ constexpr size_t kBarWords = (size_t)kBarGroups + (size_t)kBarStride * kBarMaxGr
 // chunk k >> hint_shift; hint[c] holds the huge-list slot that owns the first
 // edge of chunk c.  The shift is at least kHintMinShift.
 constexpr int kHintMinShift = 10;
+// Adaptive threshold for rounds whose worklist cannot give every launched
+// thread an entry: any vertex of at least a wavefront's worth of edges goes to
+// the cyclic distribution, which keeps every workgroup busy.
+constexpr int kAdaptiveSmall = 64;
 constexpr int kHintMaxShift = 20;
 
 // Per-call control block in device memory.  Counters rotate by round so that
@@ -44,6 +48,7 @@ struct Ctl {
   uint32_t rounds;                // rounds completed (written by workgroup 0)
   uint32_t pad0;
   unsigned long long dangling[2]; // PageRank: rank mass without out-edges (fixed point), iteration it in [it & 1]
+  alignas(256) uint32_t chunk[3]; // next worklist chunk to claim in phase 1 of round r: [r % 3]
   alignas(256) uint32_t abort;    // a barrier wait timed out; every workgroup leaves
   uint32_t diag_round;            // round of the wait that timed out
   unsigned long long diag_seen;   // generation it observed
@@ -61,8 +66,12 @@ struct Ctl {
   // wall-clock ticks at round start, after the inspection/TWC phase and after
   // the execution phase, and (worklist size | huge count << 32)
   unsigned long long tl[4 * 64];
+  // with Args::profile: wall-clock ticks summed over workgroups, per part of
+  // the round (see kProf*)
+  unsigned long long prof[8];
 };
 constexpr int kTimeline = 64;
+enum { kProfInspect = 0, kProfWgBin, kProfWaveBin, kProfThreadBin, kProfLb, kProfBarrier, kProfParts };
 
 enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4 };
 
@@ -84,12 +93,14 @@ struct Args {
   int32_t c_wave;       // TWC cutoffs
   int32_t c_wg;
   int32_t dedup;        // SSSP / CC: push a vertex at most once per round
+  int32_t adaptive;     // per-round threshold: kAdaptiveSmall when the worklist has fewer entries than threads
   int32_t identity_first;  // round 0 works on every vertex (no worklist)
   int32_t all_rounds;      // every round works on every vertex (PageRank)
   int32_t max_rounds;
   int32_t round;           // host-loop mode: the round this launch runs
   uint64_t timeout_ticks;  // barrier wait limit in wall-clock ticks
   uint64_t join_window_ticks;  // persistent launch: close membership after this long without a new member
+  int32_t profile;         // accumulate Ctl::prof (profiling aid)
   // operator state
   int32_t *level;       // BFS levels
   unsigned long long *word;  // SSSP / CC: (label << 32) | tag, tag = 1 + last round that lowered it

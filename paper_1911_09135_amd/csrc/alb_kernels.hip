@@ -83,14 +83,18 @@ __device__ __forceinline__ V from_bits(int32_t x) {
 // loads in flight before the first decision.
 // ---------------------------------------------------------------------------
 
-struct OpBFS {  // level[dst] = level[src] + 1 on first visit
+// BFS: level[dst] = level[src] + 1 on first visit (compare-and-swap from INF).
+// Every active vertex of round r has level r, so no source level is read.
+struct OpBFS {
   using val_t = int32_t;
   struct pre_t {
     int32_t cur;
   };
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
   int32_t *level;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t, uint32_t, bool &) const { return level[v]; }
+  __device__ __forceinline__ val_t load_src(int32_t, int32_t, uint32_t tag, bool &) const {
+    return (int32_t)tag - 1;
+  }
   __device__ __forceinline__ pre_t prepare(int32_t, int32_t dst, val_t) const { return {level[dst]}; }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
@@ -219,7 +223,17 @@ OpRecord make_op<OpRecord>(const Args &a) { return OpRecord{a.hits, a.thread_of}
 struct Acc {
   unsigned long long frontier = 0, edges_twc = 0, edges_lb = 0, huge_v = 0, pushes = 0;
   unsigned long long dangling = 0;  // fixed point
+  unsigned long long prof[kProfParts] = {0, 0, 0, 0, 0, 0};
 };
+
+// Profiling aid: thread 0 of each workgroup adds the ticks since *t to part k.
+__device__ __forceinline__ void prof_mark(const Args &a, Acc &acc, int k, uint64_t &t) {
+  if (a.profile && threadIdx.x == 0) {
+    const uint64_t now = (uint64_t)wall_clock64();
+    acc.prof[k] += now - t;
+    t = now;
+  }
+}
 
 template <int B, class Op>
 struct Smem {
@@ -233,6 +247,7 @@ struct Smem {
   int32_t owner, obeg, odeg, ov;  // workgroup-bin broadcast
   V osv;
   int32_t flag;
+  uint32_t chunk;
   int32_t pbuf[B / kWave][kPushBuf];  // per-wavefront push staging
 };
 
@@ -274,6 +289,8 @@ __device__ void flush_stats(Acc &acc, Smem<B, Op> &sm, Ctl *c) {
     if (t[2]) add_relaxed(&c->st_edges_lb, t[2]);
     if (t[3]) add_relaxed(&c->st_huge_v, t[3]);
     if (t[4]) add_relaxed(&c->st_pushes, t[4]);
+    for (int k = 0; k < kProfParts; ++k)
+      if (acc.prof[k]) add_relaxed(&c->prof[k], acc.prof[k]);
   }
   __syncthreads();
   acc = Acc();
@@ -447,17 +464,26 @@ __device__ __forceinline__ void block_exscan(int32_t x, int32_t &excl, int32_t &
 // ---------------------------------------------------------------------------
 template <int B, class Op>
 __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, int round, const int32_t *F,
-                          uint32_t nF, int32_t *qn, uint32_t *qn_cnt, unsigned long long *hctr, uint32_t hs,
-                          Acc &acc) {
+                          uint32_t nF, int32_t *qn, uint32_t *qn_cnt, unsigned long long *hctr, int64_t threshold,
+                          uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
   const int tid = threadIdx.x;
   const uint32_t lane = lane_id();
-  const uint32_t stride = gr.n * B;
   const int32_t gt = (int32_t)(gr.id * B + tid);
   const uint32_t tag = (uint32_t)round + 1u;
+  uint32_t *chunk_ctr = &a.ctl->chunk[round % 3];
   Pusher pu{sm.pbuf[tid / kWave], 0u, qn, qn_cnt};
-  for (uint32_t base = gr.id * B; base < nF; base += stride) {
-    const uint32_t i = base + tid;
+  uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
+  // Workgroups claim B-entry chunks of the worklist one at a time, so a chunk
+  // that takes long does not hold up work queued behind it on the same
+  // workgroup.  (The loop body's workgroup barriers separate one claim's read
+  // of sm.chunk from the next claim's write.)
+  for (;;) {
+    if (tid == 0) sm.chunk = add_relaxed(chunk_ctr, 1u);
+    __syncthreads();
+    const uint64_t base = (uint64_t)sm.chunk * B;
+    if (base >= nF) break;
+    const uint32_t i = (uint32_t)base + tid;
     int32_t v = -1, beg = 0, deg = 0;
     if (i < nF) {
       v = F ? F[i] : (int32_t)i;
@@ -471,7 +497,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       if (skip) deg = 0;
     }
     // inspection: degree >= THRESHOLD goes to the huge list
-    const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= a.threshold;
+    const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= threshold;
     reserve_huge(huge, v, beg, deg, to_bits(sv), a, round, hctr, hs, acc);
     if constexpr (Op::kRecord) {
       if (i < nF) a.bins[i] = (int8_t)(huge ? 3 : deg >= a.c_wg ? 2 : deg >= a.c_wave ? 1 : 0);
@@ -482,6 +508,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
     if (huge) deg = 0;
     acc.frontier += (v >= 0);
     acc.edges_twc += (unsigned long long)deg;
+    prof_mark(a, acc, kProfInspect, pt);
 
     // workgroup bin: the whole workgroup strides one vertex's edges
     for (;;) {
@@ -517,6 +544,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       }
     }
 
+    prof_mark(a, acc, kProfWgBin, pt);
     // wavefront bin: one wavefront strides one vertex's edges
     for (;;) {
       const unsigned long long mm = __ballot(deg > 0 && deg >= a.c_wave);
@@ -541,6 +569,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       }
     }
 
+    prof_mark(a, acc, kProfWaveBin, pt);
     // thread bin: fine-grained gather of the remaining short lists through LDS,
     // kU * B edges at a time, so that the workgroup's lanes stay busy
     int32_t rank, total;
@@ -569,8 +598,10 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       __syncthreads();
     }
+    prof_mark(a, acc, kProfThreadBin, pt);
   }
   if constexpr (Op::kPush) flush_pushes(a, round, pu);
+  prof_mark(a, acc, kProfThreadBin, pt);
 }
 
 // The huge-list slot whose edge range holds huge edge k: the last slot j with
@@ -611,6 +642,7 @@ __device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, 
   const uint64_t g = (uint64_t)gr.id * B + threadIdx.x;
   const uint32_t tag = (uint32_t)round + 1u;
   Pusher pu{sm.pbuf[threadIdx.x / kWave], 0u, qn, qn_cnt};
+  uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
   // thread g takes huge edges g, g + T, g + 2T, ...; kU of them per pass
   for (uint64_t k0 = g - lane; k0 < e; k0 += kU * T) {
     bool act[kU];
@@ -634,6 +666,7 @@ __device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, 
     edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, (int32_t)g);
   }
   if constexpr (Op::kPush) flush_pushes(a, round, pu);
+  prof_mark(a, acc, kProfLb, pt);
 }
 
 // PageRank update: r'(v) = (1-d)/n + d * (acc(v) + D/n), rounded to fp32; acc cleared.
@@ -712,8 +745,16 @@ __device__ __forceinline__ uint32_t round_size(const Args &a, int r) {
   return c < a.qcap ? c : a.qcap;
 }
 
-// Clear the counters two rounds ahead (nobody reads or writes them this round).
+// The huge threshold of a round: the configured one, or with the adaptive rule
+// kAdaptiveSmall while the worklist has fewer entries than launched threads.
+__device__ __forceinline__ int64_t round_threshold(const Args &a, uint32_t nF, uint64_t T) {
+  if (a.adaptive && (uint64_t)nF < T) return kAdaptiveSmall;
+  return a.threshold;
+}
+
+// Clear the counters ahead (nobody reads or writes them this round).
 __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
+  st_relaxed(&a.ctl->chunk[(r + 1) % 3], 0u);
   st_relaxed(&a.ctl->qcount[(r + 2) % 3], 0u);
   st_relaxed(&a.ctl->huge[(r + 1) & 1], 0ull);
   st_relaxed(&a.ctl->dangling[(r + 1) & 1], 0ull);
@@ -795,6 +836,7 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     c->qcount[0] = nfront0;
     c->qcount[1] = 0;
     c->qcount[2] = 0;
+    c->chunk[0] = c->chunk[1] = c->chunk[2] = 0;
     c->overflow = 0xffffffffu;
     c->huge[0] = 0;
     c->huge[1] = 0;
@@ -808,6 +850,7 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     c->diag_seen = c->diag_target = 0;
     c->diag_round = 0;
     c->threshold_used = a.threshold;
+    for (int k = 0; k < kProfParts; ++k) c->prof[k] = 0;
     if (source >= 0 && op != OP_RECORD) a.q0[0] = source;
   }
 }
@@ -826,8 +869,9 @@ __global__ __launch_bounds__(B) void k_twc(Args a, Op op) {
   const uint32_t nF = round_size(a, r);
   if (blockIdx.x == 0 && threadIdx.x == 0) clear_ahead(a, r);
   const Grid gr{blockIdx.x, gridDim.x};
+  const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
   phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
-                   &a.ctl->huge[r & 1], hint_shift(a.threshold), acc);
+                   &a.ctl->huge[r & 1], thr, hint_shift(thr), acc);
   if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
   flush_stats<B, Op>(acc, sm, a.ctl);
 }
@@ -838,8 +882,9 @@ __global__ __launch_bounds__(B) void k_lb(Args a, Op op) {
   Acc acc;
   const int r = a.round;
   const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
+  const int64_t thr = round_threshold(a, round_size(a, r), (uint64_t)gridDim.x * B);
   phase_lb<B, Op>(a, op, sm, Grid{blockIdx.x, gridDim.x}, r, hc, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
-                  hint_shift(a.threshold), acc);
+                  hint_shift(thr), acc);
   flush_stats<B, Op>(acc, sm, a.ctl);
 }
 
@@ -856,7 +901,6 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
   Grid gr;
   if (!join_members(a, sm, &gr)) return;
   if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // the launched thread count (the paper's rule)
-  const uint32_t hs = hint_shift(a.threshold);
   unsigned long long epoch = 0;
   int r = 0;
   for (; r < a.max_rounds; ++r) {
@@ -868,9 +912,13 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
     if (tl) a.ctl->tl[4 * r] = (unsigned long long)wall_clock64();
     int32_t *qn = round_next(a, r);
     uint32_t *qn_cnt = &a.ctl->qcount[(r + 1) % 3];
-    phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], hs, acc);
+    const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
+    const uint32_t hs = hint_shift(thr);
+    phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], thr, hs, acc);
     if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
+    uint64_t pb = a.profile ? (uint64_t)wall_clock64() : 0;
     if (!grid_barrier(a, sm, gr, epoch, r)) break;
+    prof_mark(a, acc, kProfBarrier, pb);
     const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
     if (tl) {
       a.ctl->tl[4 * r + 1] = (unsigned long long)wall_clock64();
@@ -878,7 +926,9 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
     }
     if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
       phase_lb<B, Op>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+      pb = a.profile ? (uint64_t)wall_clock64() : 0;
       if (!grid_barrier(a, sm, gr, epoch, r)) break;
+      prof_mark(a, acc, kProfBarrier, pb);
     }
     if (tl) a.ctl->tl[4 * r + 2] = (unsigned long long)wall_clock64();
     if constexpr (Op::kPR) {

@@ -49,16 +49,18 @@ def check_round(alb, g, dg, frontier, **opts):
     src, pos, thr = oracle.lb_edges(work, r["prefix"], g.off, T)
     assert np.array_equal(r["edge_thread"][pos], thr.astype(np.int32))
     assert np.array_equal(src, np.repeat(work, deg[work]))
-    # TWC: every other edge stays inside the workgroup that owns the vertex's chunk;
-    # wavefront-bin vertices inside one wavefront, workgroup-bin vertices in one workgroup
-    G = T // wg
+    # TWC: every other edge stays inside one workgroup, the same for all the
+    # vertices of a B-entry chunk of the worklist (chunks are claimed
+    # dynamically); wavefront-bin vertices inside one wavefront
+    chunk_wg = {}
     for i, v in enumerate(frontier):
         b = r["bins"][i]
         if b == 3 or deg[v] == 0:
             continue
         th = r["edge_thread"][g.off[v]:g.off[v + 1]]
-        wg_expected = (i // wg) % G
-        assert np.all(th // wg == wg_expected), (i, v, b)
+        wgs = np.unique(th // wg)
+        assert len(wgs) == 1, (i, v, b)
+        assert chunk_wg.setdefault(i // wg, int(wgs[0])) == int(wgs[0]), (i, v)
         if b == 1:
             assert len(np.unique(th // 64)) == 1
     # pushes: every processed edge pushed its destination once

@@ -64,7 +64,7 @@ def device_graph(alb, name, symmetric=False):
 def configs(maxdeg):
     """The metamorphic matrix: every cell must give the oracle's answer."""
     out = []
-    for thr in [None, "launched", 0, 1, 63, 64, 65, 256, maxdeg, maxdeg + 1, "twc", "lb_all"]:
+    for thr in [None, "launched", "adaptive", 0, 1, 63, 64, 65, 256, maxdeg, maxdeg + 1, "twc", "lb_all"]:
         for wg in (64, 256, 1024):
             for launch in ("host", "persistent"):
                 if thr == "twc":
