@@ -121,6 +121,27 @@ alb_status alb_options_init(alb_options *opt);
 alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, const int32_t *col,
                             const int32_t *weights, uint32_t flags, alb_graph *out);
 
+/* A graph set: `count` CSR graphs held as one handle for batches of queries
+ * (alb_bfs_batch, alb_sssp_batch).  Member i is given by ns[i], ms[i],
+ * row_offsets[i], cols[i] and, if `weights` is not NULL, weights[i], each
+ * following the CSR conventions above; the members are stored one after the
+ * other as the disjoint union (member i's vertex v is vertex
+ * vertex_base(i) + v of the handle, see alb_graph_member_info).  The total
+ * vertex and edge counts must stay below 2^31 - 1 and 2^31.  The caller keeps
+ * the host arrays.  The single-query calls also accept the handle and then
+ * work on the union.  Member lists of different sizes, from the same graph
+ * repeated, or one member only are all allowed. */
+alb_status alb_graph_create_set(int32_t count, const int32_t *ns, const int64_t *ms,
+                                const int32_t *const *row_offsets, const int32_t *const *cols,
+                                const int32_t *const *weights, alb_graph *out);
+
+/* Members of a handle (1 for alb_graph_create). */
+alb_status alb_graph_members(alb_graph g, int32_t *count);
+
+/* Vertex count, edge count and first vertex id of member `member` inside the
+ * handle.  Output pointers may be NULL. */
+alb_status alb_graph_member_info(alb_graph g, int32_t member, int32_t *n, int64_t *m, int32_t *vertex_base);
+
 /* Release the device copy and every cached workspace.  NULL is a no-op. */
 alb_status alb_graph_destroy(alb_graph g);
 
@@ -148,6 +169,27 @@ alb_status alb_cc(alb_graph g, int32_t *label, const alb_options *opt, alb_stats
  * 0 < damping < 1, iterations >= 0. */
 alb_status alb_pagerank(alb_graph g, float damping, int32_t iterations, float *rank, const alb_options *opt,
                         alb_stats *stats);
+
+/* Batches: `count` (1 .. 65535) independent queries on the members of a
+ * graph set, run together in ONE persistent launch.  Query q searches member
+ * members[q] from its local vertex sources[q] and writes that member's n
+ * labels to levels[q] / dists[q] (host pointers, or device pointers with
+ * options.out_on_device).  Every round's worklist holds (query, vertex)
+ * pairs of all queries still running, so small queries share the chip instead
+ * of each leaving most of it idle, and the inspection of Algorithm 1 and the
+ * cyclic distribution of Algorithm 2 balance the union of their frontiers.
+ * thresholds: NULL = the option's rule for every query; else thresholds[q] >= 0
+ * is query q's huge threshold (mode ALB only), e.g. one tuned per graph.
+ * Results equal the single-query calls on the member alone.  The sum over the
+ * queries of their member's vertex counts (with dedup off: plus edge counts)
+ * and of their edge counts must each stay below 2^32 - 1 (ALB_E_INVAL
+ * otherwise; split the batch).  Options as for the single calls except
+ * launch: HOST_LOOP is ALB_E_UNSUPPORTED.  stats sum over the batch;
+ * stats->huge_threshold is -1 with per-query thresholds. */
+alb_status alb_bfs_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                         int32_t *const *levels, const int64_t *thresholds, const alb_options *opt, alb_stats *stats);
+alb_status alb_sssp_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                          int32_t *const *dists, const int64_t *thresholds, const alb_options *opt, alb_stats *stats);
 
 /* One round of the balancer on an explicit frontier, with an operator that
  * records instead of updating labels (for checking the distribution).  Host

@@ -82,6 +82,12 @@ _sig = {
     "alb_sssp": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_cc": ([_vp, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_pagerank": ([_vp, _f32, _i32, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_graph_create_set": ([_i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "alb_graph_members": ([_vp, ctypes.POINTER(_i32)], ctypes.c_int),
+    "alb_graph_member_info": ([_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
+                              ctypes.c_int),
+    "alb_bfs_batch": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_sssp_batch": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_trace_round": ([_vp, _vp, _i64, _POpt, _vp, _vp, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp,
                          ctypes.POINTER(_i64), _PSt], ctypes.c_int),
     "alb_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -196,6 +202,103 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class GraphSet(Graph):
+    """Several CSR graphs held as one handle for query batches
+    (alb_graph_create_set).  `graphs`: objects with .off, .col and, for SSSP,
+    .w (for example graphgen.Graph).  members[i] = (n, m, vertex_base)."""
+
+    def __init__(self, graphs, weighted: Optional[bool] = None):
+        graphs = list(graphs)
+        if weighted is None:
+            weighted = all(getattr(g, "w", None) is not None for g in graphs)
+        self._keep = []
+        offs, cols, ws, ns, ms = [], [], [], [], []
+        for g in graphs:
+            off, col = _i32arr(g.off), _i32arr(g.col)
+            w = _i32arr(g.w) if weighted else None
+            self._keep += [off, col, w]
+            ns.append(off.shape[0] - 1)
+            ms.append(int(g.col.shape[0]))
+            offs.append(off.ctypes.data)
+            cols.append(col.ctypes.data if col.size else None)
+            ws.append(w.ctypes.data if (w is not None and w.size) else None)
+        k = len(graphs)
+        P = _vp * max(k, 1)
+        ns_a = np.asarray(ns, np.int32)
+        ms_a = np.asarray(ms, np.int64)
+        offs_p, cols_p, ws_p = P(*offs), P(*cols), P(*ws)
+        h = _vp()
+        _check(_lib.alb_graph_create_set(k, ns_a.ctypes.data, ms_a.ctypes.data, ctypes.cast(offs_p, _vp),
+                                         ctypes.cast(cols_p, _vp), ctypes.cast(ws_p, _vp) if weighted else None,
+                                         ctypes.byref(h)), "alb_graph_create_set")
+        self._keep = None
+        self._h = h
+        n_, m_, md = _i32(), _i64(), _i32()
+        _check(_lib.alb_graph_info(h, ctypes.byref(n_), ctypes.byref(m_), ctypes.byref(md), None), "alb_graph_info")
+        self.n, self.m, self.max_out_degree = n_.value, m_.value, md.value
+        cnt = _i32()
+        _check(_lib.alb_graph_members(h, ctypes.byref(cnt)), "alb_graph_members")
+        self.members = []
+        for i in range(cnt.value):
+            a, b, c = _i32(), _i64(), _i32()
+            _check(_lib.alb_graph_member_info(h, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                   "alb_graph_member_info")
+            self.members.append((a.value, b.value, c.value))
+
+
+def _run_batch(fn, gs: GraphSet, members, sources, thresholds, outs, opts: dict):
+    members = np.ascontiguousarray(members, np.int32)
+    sources = np.ascontiguousarray(sources, np.int32)
+    if members.shape != sources.shape or members.ndim != 1:
+        raise ValueError("members and sources must be 1-D of one length")
+    q = members.shape[0]
+    dev = False
+    # a member id out of range is left for the library to report
+    size = [gs.members[int(mb)][0] if 0 <= mb < len(gs.members) else 1 for mb in members]
+    if outs is None:
+        outs = [np.empty(n, np.int32) for n in size]
+        ptrs = [o.ctypes.data for o in outs]
+    else:
+        outs = list(outs)
+        if len(outs) != q:
+            raise ValueError("one output per query")
+        dev = not isinstance(outs[0], np.ndarray)
+        ptrs = []
+        for o, n in zip(outs, size):
+            if dev:
+                if not o.is_cuda or not o.is_contiguous() or o.numel() != n or o.dtype.itemsize != 4:
+                    raise ValueError("device outputs must be contiguous 32-bit CUDA tensors of the member's n")
+                ptrs.append(o.data_ptr())
+            else:
+                if o.dtype != np.int32 or o.shape != (n,) or not o.flags.c_contiguous:
+                    raise ValueError("host outputs must be contiguous int32 arrays of the member's n")
+                ptrs.append(o.ctypes.data)
+    if dev and opts.get("stream") is None:
+        import torch
+
+        opts = dict(opts, stream=torch.cuda.current_stream())
+    thr = None if thresholds is None else np.ascontiguousarray(thresholds, np.int64)
+    if thr is not None and thr.shape != (q,):
+        raise ValueError("one threshold per query")
+    ptr_arr = (_vp * max(q, 1))(*ptrs)
+    o = make_options(out_on_device=dev, **opts)
+    st = Stats()
+    _check(fn(gs.handle, q, members.ctypes.data, sources.ctypes.data, ctypes.cast(ptr_arr, _vp),
+              None if thr is None else thr.ctypes.data, ctypes.byref(o), ctypes.byref(st)), fn.__name__)
+    return outs, st.as_dict()
+
+
+def bfs_batch(gs: GraphSet, members, sources, thresholds=None, outs=None, **opts):
+    """Query q: BFS levels of member members[q] from its vertex sources[q].
+    Returns (list of per-query level arrays, stats), all queries in one launch."""
+    return _run_batch(_lib.alb_bfs_batch, gs, members, sources, thresholds, outs, opts)
+
+
+def sssp_batch(gs: GraphSet, members, sources, thresholds=None, outs=None, **opts):
+    """Query q: SSSP distances of member members[q] from its vertex sources[q]."""
+    return _run_batch(_lib.alb_sssp_batch, gs, members, sources, thresholds, outs, opts)
 
 
 def _out_buffer(g: Graph, out, dtype):

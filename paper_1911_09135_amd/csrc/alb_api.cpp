@@ -78,6 +78,34 @@ struct Workspace {
   }
 };
 
+// Workspace of a batch of queries on a graph set: worklists of
+// (query << 32 | vertex) entries, one label per (query, vertex of its graph)
+// and the per-query tables.
+struct BatchWs {
+  long long lab_cap = 0;
+  uint32_t qcap = 0, hint_cap = 0;
+  int32_t nq_cap = 0;
+  bool busy = false;
+  unsigned long long *q0 = nullptr, *q1 = nullptr, *word = nullptr, *bar = nullptr;
+  int32_t *out32 = nullptr, *hint = nullptr, *qsrc = nullptr, *qn = nullptr;
+  int4 *huge_rec = nullptr;
+  long long *qoff = nullptr, *qthr = nullptr, *qlbase = nullptr;
+  int32_t **qout = nullptr;
+  Ctl *ctl = nullptr;
+  Ctl *h_ctl = nullptr;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  size_t bytes = 0;
+
+  void release() {
+    void *p[] = {q0, q1, word, bar, out32, hint, qsrc, qn, huge_rec, qoff, qthr, qlbase, qout, ctl};
+    for (void *x : p) (void)hipFree(x);
+    if (h_ctl) (void)hipHostFree(h_ctl);
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+    *this = BatchWs();
+  }
+};
+
 }  // namespace
 
 struct alb_graph_s {
@@ -94,6 +122,11 @@ struct alb_graph_s {
   size_t graph_bytes = 0;
   std::mutex mu;
   std::vector<Workspace *> pool;
+  std::vector<BatchWs *> batch_pool;
+  // members of a graph set (a plain graph is a set of one): vertex base in the
+  // set's numbering, vertex and edge counts
+  std::vector<int32_t> mem_vbase, mem_n;
+  std::vector<int64_t> mem_m;
 };
 
 namespace {
@@ -230,17 +263,19 @@ alb_status ws_fill(Workspace *w, int32_t n, const Needs &nd) {
   return ALB_OK;
 }
 
-alb_status ws_acquire(alb_graph g, const Needs &nd, Workspace **out) {
+// Take a free cached workspace that `fits`, else grow a free one or make a
+// new one with `fill`.
+template <class W, class Fits, class Fill>
+alb_status pool_acquire(alb_graph g, std::vector<W *> &pool, Fits fits, Fill fill, W **out) {
   std::lock_guard<std::mutex> lk(g->mu);
-  for (Workspace *w : g->pool)
-    if (!w->busy && w->qcap >= nd.qcap && w->hint_cap >= nd.hint_cap) {
+  for (W *w : pool)
+    if (!w->busy && fits(*w)) {
       w->busy = true;
       *out = w;
       return ALB_OK;
     }
-  // grow a free one that is too small, else make a new one
-  Workspace *w = nullptr;
-  for (Workspace *x : g->pool)
+  W *w = nullptr;
+  for (W *x : pool)
     if (!x->busy) {
       w = x;
       w->release();
@@ -248,37 +283,85 @@ alb_status ws_acquire(alb_graph g, const Needs &nd, Workspace **out) {
     }
   bool fresh = false;
   if (!w) {
-    w = new (std::nothrow) Workspace();
+    w = new (std::nothrow) W();
     if (!w) return fail(ALB_E_NOMEM, "host allocation failed");
     fresh = true;
   }
-  alb_status s = ws_fill(w, g->n, nd);
+  alb_status s = fill(w);
   if (s != ALB_OK) {
     std::string keep = g_err;
     w->release();
-    if (!fresh) g->pool.erase(std::find(g->pool.begin(), g->pool.end(), w));
+    if (!fresh) pool.erase(std::find(pool.begin(), pool.end(), w));
     delete w;
     g_err = keep;
     return s;
   }
-  if (fresh) g->pool.push_back(w);
+  if (fresh) pool.push_back(w);
   w->busy = true;
   *out = w;
   return ALB_OK;
 }
 
-void ws_release(alb_graph g, Workspace *w) {
+alb_status ws_acquire(alb_graph g, const Needs &nd, Workspace **out) {
+  return pool_acquire(
+      g, g->pool, [&](const Workspace &w) { return w.qcap >= nd.qcap && w.hint_cap >= nd.hint_cap; },
+      [&](Workspace *w) { return ws_fill(w, g->n, nd); }, out);
+}
+
+struct BatchNeeds {
+  long long labels;
+  uint32_t qcap, hint_cap;
+  int32_t nq;
+};
+
+alb_status bws_fill(BatchWs *w, const BatchNeeds &nd) {
+  w->lab_cap = nd.labels;
+  w->qcap = nd.qcap;
+  w->hint_cap = nd.hint_cap;
+  w->nq_cap = nd.nq;
+  HIP_TRY(dalloc(&w->q0, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->q1, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->huge_rec, nd.qcap, w->bytes));
+  HIP_TRY(dalloc(&w->hint, nd.hint_cap, w->bytes));
+  HIP_TRY(dalloc(&w->bar, kBarWords, w->bytes));
+  HIP_TRY(dalloc(&w->word, (size_t)nd.labels, w->bytes));
+  HIP_TRY(dalloc(&w->out32, (size_t)nd.labels, w->bytes));
+  HIP_TRY(dalloc(&w->qsrc, (size_t)nd.nq, w->bytes));
+  HIP_TRY(dalloc(&w->qn, (size_t)nd.nq, w->bytes));
+  HIP_TRY(dalloc(&w->qoff, (size_t)nd.nq, w->bytes));
+  HIP_TRY(dalloc(&w->qthr, (size_t)nd.nq, w->bytes));
+  HIP_TRY(dalloc(&w->qlbase, (size_t)nd.nq, w->bytes));
+  HIP_TRY(dalloc(&w->qout, (size_t)nd.nq, w->bytes));
+  HIP_TRY(dalloc(&w->ctl, 1, w->bytes));
+  HIP_TRY(hipHostMalloc((void **)&w->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  for (auto &e : w->ev) HIP_TRY(hipEventCreate(&e));
+  return ALB_OK;
+}
+
+alb_status bws_acquire(alb_graph g, const BatchNeeds &nd, BatchWs **out) {
+  return pool_acquire(
+      g, g->batch_pool,
+      [&](const BatchWs &w) {
+        return w.lab_cap >= nd.labels && w.qcap >= nd.qcap && w.hint_cap >= nd.hint_cap && w.nq_cap >= nd.nq;
+      },
+      [&](BatchWs *w) { return bws_fill(w, nd); }, out);
+}
+
+template <class W>
+void ws_release(alb_graph g, W *w) {
   std::lock_guard<std::mutex> lk(g->mu);
   w->busy = false;
 }
 
-struct WsGuard {
+template <class W>
+struct GuardOf {
   alb_graph g;
-  Workspace *w;
-  ~WsGuard() {
+  W *w;
+  ~GuardOf() {
     if (w) ws_release(g, w);
   }
 };
+using WsGuard = GuardOf<Workspace>;
 
 // --------------------------------------------------------------------------
 // Options
@@ -350,13 +433,13 @@ uint64_t barrier_timeout_ms() {
 std::mutex g_res_mu;
 std::map<std::tuple<int, int, int>, int> g_res;
 
-alb_status resident_workgroups(alb_graph g, OpKind op, int wg, int *out) {
-  const auto key = std::make_tuple(g->device, (int)op, wg);
+alb_status resident_workgroups(alb_graph g, OpKind op, int wg, int *out, bool batch = false) {
+  const auto key = std::make_tuple(g->device, (int)op + (batch ? 256 : 0), wg);
   std::lock_guard<std::mutex> lk(g_res_mu);
   auto it = g_res.find(key);
   if (it == g_res.end()) {
     int per_cu = 0;
-    HIP_TRY(persistent_occupancy(op, wg, &per_cu));
+    HIP_TRY(batch ? batch_occupancy(op, wg, &per_cu) : persistent_occupancy(op, wg, &per_cu));
     if (per_cu < 1) return fail(ALB_E_DEVICE, "persistent kernel does not fit on a CU with wg_size %d", wg);
     it = g_res.emplace(key, per_cu * g->cus).first;
   }
@@ -388,6 +471,46 @@ struct RunOut {
 
 void zero_stats(alb_stats *st) {
   if (st) std::memset(st, 0, sizeof *st);
+}
+
+alb_status abort_error(const Ctl &c) {
+  return fail(ALB_E_DEVICE,
+              "a grid barrier wait timed out in round %u (%llu of %llu arrivals seen, %u members); the device "
+              "run was abandoned",
+              c.diag_round, c.diag_seen, c.diag_target, c.n_members);
+}
+
+void print_timeline(const Ctl &c, int op, int rounds, long long threshold, uint64_t clock_khz) {
+  const double us = 1000.0 / (double)clock_khz;
+  fprintf(stderr, "[alb] op %d members %u threshold %lld\n", op, c.n_members, threshold);
+  for (int r = 0; r < std::min(rounds, kTimeline); ++r) {
+    const unsigned long long *t = &c.tl[4 * r];
+    fprintf(stderr, "[alb] round %2d  |F| %9u  huge %7u  twc %8.1f us  lb %8.1f us\n", r,
+            (unsigned)(t[3] & 0xffffffffu), (unsigned)(t[3] >> 32), (double)(t[1] - t[0]) * us,
+            (double)(t[2] - t[1]) * us);
+  }
+  static const char *names[kProfParts] = {"inspect", "wg-bin", "wave-bin", "thread-bin", "lb", "barrier"};
+  fprintf(stderr, "[alb] workgroup-time per part (us summed over %u members):", c.n_members);
+  for (int k = 0; k < kProfParts; ++k) fprintf(stderr, " %s %.0f", names[k], (double)c.prof[k] * us);
+  fprintf(stderr, "\n");
+}
+
+void fill_stats(alb_stats *st, const Ctl &c, int rounds, int launches, int64_t T, int64_t threshold, hipEvent_t e0,
+                hipEvent_t e1, hipEvent_t e2) {
+  float ms_all = 0.f, ms_k = 0.f;
+  (void)hipEventElapsedTime(&ms_all, e0, e2);
+  (void)hipEventElapsedTime(&ms_k, e1, e2);
+  st->rounds = rounds;
+  st->kernel_launches = launches;
+  st->launched_threads = T;
+  st->huge_threshold = threshold;
+  st->frontier_vertices = (int64_t)c.st_frontier;
+  st->edges_examined = (int64_t)(c.st_edges_twc + c.st_edges_lb);
+  st->huge_vertices = (int64_t)c.st_huge_v;
+  st->huge_edges = (int64_t)c.st_edges_lb;
+  st->pushes = (int64_t)c.st_pushes;
+  st->device_ms = ms_all;
+  st->kernel_ms = ms_k;
 }
 
 alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_out, alb_stats *st, WsGuard &guard,
@@ -531,11 +654,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   const Ctl &c = *ws->h_ctl;
-  if (c.abort)
-    return fail(ALB_E_DEVICE,
-                "a grid barrier wait timed out in round %u (%llu of %llu arrivals seen, %u members); the device "
-                "run was abandoned",
-                c.diag_round, c.diag_seen, c.diag_target, c.n_members);
+  if (c.abort) return abort_error(c);
   if (launch == ALB_LAUNCH_PERSISTENT && launches) {
     T = (int64_t)c.n_members * wg;
     threshold = c.threshold_used;
@@ -544,40 +663,13 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", a.qcap, c.overflow);
   if (launch == ALB_LAUNCH_PERSISTENT) {
     rounds = (int)c.rounds;
-    if (getenv("ALB_TIMELINE")) {  // profiling aid: per-round phase times on stderr
-      const double us = 1000.0 / (double)g->clock_khz;
-      fprintf(stderr, "[alb] op %d members %u threshold %lld\n", (int)job.op, c.n_members, (long long)threshold);
-      for (int r = 0; r < std::min(rounds, kTimeline); ++r) {
-        const unsigned long long *t = &c.tl[4 * r];
-        fprintf(stderr, "[alb] round %2d  |F| %9u  huge %7u  twc %8.1f us  lb %8.1f us\n", r,
-                (unsigned)(t[3] & 0xffffffffu), (unsigned)(t[3] >> 32), (double)(t[1] - t[0]) * us,
-                (double)(t[2] - t[1]) * us);
-      }
-      static const char *names[kProfParts] = {"inspect", "wg-bin", "wave-bin", "thread-bin", "lb", "barrier"};
-      fprintf(stderr, "[alb] workgroup-time per part (us summed over %u members):", c.n_members);
-      for (int k = 0; k < kProfParts; ++k) fprintf(stderr, " %s %.0f", names[k], (double)c.prof[k] * us);
-      fprintf(stderr, "\n");
-    }
+    if (getenv("ALB_TIMELINE"))  // profiling aid: per-round phase times on stderr
+      print_timeline(c, (int)job.op, rounds, (long long)threshold, g->clock_khz);
   }
   if (!job.all_rounds && job.max_rounds > 1 && rounds >= job.max_rounds && c.qcount[rounds % 3] != 0)
     return fail(ALB_E_DEVICE, "no convergence within %d rounds", job.max_rounds);
 
-  if (st) {
-    float ms_all = 0.f, ms_k = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms_all, ws->ev[0], ws->ev[2]));
-    HIP_TRY(hipEventElapsedTime(&ms_k, ws->ev[1], ws->ev[2]));
-    st->rounds = rounds;
-    st->kernel_launches = launches;
-    st->launched_threads = T;
-    st->huge_threshold = threshold;
-    st->frontier_vertices = (int64_t)c.st_frontier;
-    st->edges_examined = (int64_t)(c.st_edges_twc + c.st_edges_lb);
-    st->huge_vertices = (int64_t)c.st_huge_v;
-    st->huge_edges = (int64_t)c.st_edges_lb;
-    st->pushes = (int64_t)c.st_pushes;
-    st->device_ms = ms_all;
-    st->kernel_ms = ms_k;
-  }
+  if (st) fill_stats(st, c, rounds, launches, T, threshold, ws->ev[0], ws->ev[1], ws->ev[2]);
   return ALB_OK;
 }
 
@@ -600,6 +692,157 @@ alb_status traverse(alb_graph g, const Job &job, void *out, size_t elem, const a
     HIP_TRY(hipMemcpyAsync(out, src, elem * (size_t)g->n, hipMemcpyDeviceToHost, ro.stream));
     HIP_TRY(hipStreamSynchronize(ro.stream));
   }
+  return ALB_OK;
+}
+
+// A batch of BFS or SSSP queries on a graph set, all in one persistent launch.
+alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
+                     int32_t *const *outs, const int64_t *thresholds, const alb_options *user, alb_stats *st) {
+  if (!g) return fail(ALB_E_INVAL, "graph handle is NULL");
+  if (count < 1 || count > kMaxBatch) return fail(ALB_E_INVAL, "count %d not in [1, %d]", count, kMaxBatch);
+  if (!members || !sources || !outs) return fail(ALB_E_INVAL, "members, sources and outs must not be NULL");
+  if (op == OP_SSSP && !g->weighted) return fail(ALB_E_INVAL, "SSSP needs a graph set created with weights");
+  alb_options o;
+  alb_status s = resolve_options(user, o);
+  if (s != ALB_OK) return s;
+  if (o.launch == ALB_LAUNCH_HOST_LOOP) return fail(ALB_E_UNSUPPORTED, "batches run as one persistent launch only");
+  if (thresholds && o.mode != ALB_MODE_ALB) return fail(ALB_E_INVAL, "per-query thresholds need mode ALB");
+  const int32_t nmem = (int32_t)g->mem_n.size();
+  std::vector<long long> qoff(count), qthr(count), qlbase(count);
+  std::vector<int32_t> qsrc(count), qn(count);
+  std::vector<int32_t *> qout(count);
+  long long labels = 0, edges = 0, thr_min = LLONG_MAX;
+  int32_t max_n = 0;
+  for (int32_t q = 0; q < count; ++q) {
+    const int32_t mb = members[q];
+    if (mb < 0 || mb >= nmem) return fail(ALB_E_INVAL, "members[%d] = %d out of range [0, %d)", q, mb, nmem);
+    const int32_t n = g->mem_n[mb];
+    if (sources[q] < 0 || sources[q] >= n)
+      return fail(ALB_E_INVAL, "sources[%d] = %d out of range [0, %d)", q, sources[q], n);
+    if (!outs[q]) return fail(ALB_E_INVAL, "outs[%d] is NULL", q);
+    if (thresholds && thresholds[q] < 0) return fail(ALB_E_INVAL, "thresholds[%d] must be >= 0", q);
+    qlbase[q] = labels;
+    qoff[q] = labels - g->mem_vbase[mb];
+    qsrc[q] = g->mem_vbase[mb] + sources[q];
+    qn[q] = n;
+    qthr[q] = thresholds ? thresholds[q] : 0;
+    thr_min = std::min(thr_min, (long long)qthr[q]);
+    labels += n;
+    edges += g->mem_m[mb];
+    max_n = std::max(max_n, n);
+  }
+  // every (query, vertex) enters a round's worklist at most once with the
+  // per-round dedup, so one round holds at most `labels` entries and at most
+  // `edges` huge edges, which the 32-bit worklist positions must hold
+  const bool dedup = op == OP_BFS || o.dedup != 0;
+  uint64_t qcap = o.worklist_capacity > 0 ? (uint64_t)o.worklist_capacity
+                                          : (uint64_t)labels + (dedup ? 0 : (uint64_t)edges);
+  qcap = std::max<uint64_t>(qcap, (uint64_t)count);
+  if (qcap > 0xfffffffeULL || edges >= 0xffffffffLL)
+    return fail(ALB_E_INVAL, "batch too large for 32-bit worklist positions (%lld labels, %lld edges): split it",
+                labels, edges);
+
+  HIP_TRY(hipSetDevice(g->device));
+  const hipStream_t stream = o.stream ? (hipStream_t)o.stream : g->stream;
+  const int wg = o.wg_size;
+  int resident = 0;
+  s = resident_workgroups(g, op, wg, &resident, true);
+  if (s != ALB_OK) return s;
+  const int grid = o.grid_wgs > 0 ? o.grid_wgs : resident;
+  if (grid > resident)
+    return fail(ALB_E_INVAL, "grid_wgs %d exceeds the %d workgroups the device can hold", grid, resident);
+  int64_t threshold;
+  if (o.mode == ALB_MODE_TWC_ONLY)
+    threshold = INT64_MAX;
+  else if (o.mode == ALB_MODE_LB_ALL)
+    threshold = 0;
+  else if (o.huge_threshold >= 0)
+    threshold = o.huge_threshold;
+  else if (o.huge_threshold == ALB_THRESHOLD_LAUNCHED)
+    threshold = -1;
+  else
+    threshold = (int64_t)kEdgesPerLanePass * wg;
+
+  BatchNeeds nd{std::max<long long>(labels, 1), (uint32_t)qcap, (uint32_t)(((uint64_t)edges >> kHintMinShift) + 2),
+                count};
+  BatchWs *ws = nullptr;
+  s = bws_acquire(g, nd, &ws);
+  if (s != ALB_OK) return s;
+  GuardOf<BatchWs> guard{g, ws};
+  for (int32_t q = 0; q < count; ++q) qout[q] = o.out_on_device ? outs[q] : ws->out32 + qlbase[q];
+
+  HIP_TRY(hipMemcpyAsync(ws->qoff, qoff.data(), sizeof(long long) * count, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(ws->qthr, qthr.data(), sizeof(long long) * count, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(ws->qlbase, qlbase.data(), sizeof(long long) * count, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(ws->qsrc, qsrc.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(ws->qn, qn.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(ws->qout, qout.data(), sizeof(int32_t *) * count, hipMemcpyHostToDevice, stream));
+
+  Args a;
+  std::memset(&a, 0, sizeof a);
+  a.off = g->d_off;
+  a.col = g->d_col;
+  a.w = g->d_w;
+  a.n = g->n;
+  a.qcap = (uint32_t)qcap;
+  a.q0 = ws->q0;
+  a.q1 = ws->q1;
+  a.huge_rec = ws->huge_rec;
+  a.hint = ws->hint;
+  a.hint_cap = ws->hint_cap;
+  a.bar = ws->bar;
+  a.ctl = ws->ctl;
+  a.threshold = threshold;
+  a.c_wave = o.wave_cutoff;
+  a.c_wg = o.wg_cutoff;
+  a.dedup = dedup ? 1 : 0;
+  a.adaptive = (!thresholds && o.mode == ALB_MODE_ALB && o.huge_threshold == ALB_THRESHOLD_ADAPTIVE) ? 1 : 0;
+  a.max_rounds = max_n + 1;
+  a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
+  a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);
+  a.profile = getenv("ALB_TIMELINE") ? 1 : 0;
+  if (op == OP_BFS) a.level = (int32_t *)ws->word;
+  if (op == OP_SSSP) a.word = ws->word;
+  a.nq = count;
+  a.qoff = ws->qoff;
+  a.qthr = thresholds ? ws->qthr : nullptr;
+  a.qthr_min = thresholds ? thr_min : 0;
+  a.qlbase = ws->qlbase;
+  a.qsrc = ws->qsrc;
+  a.qn = ws->qn;
+  a.qout = ws->qout;
+  a.nlabels = labels;
+
+  HIP_TRY(hipEventRecord(ws->ev[0], stream));
+  HIP_TRY(launch_init_batch(op, a, stream));
+  HIP_TRY(hipEventRecord(ws->ev[1], stream));
+  HIP_TRY(launch_batch(op, wg, grid, a, stream));
+  HIP_TRY(launch_finish_batch(op, a, max_n, stream));
+  HIP_TRY(hipEventRecord(ws->ev[2], stream));
+  HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const Ctl &c = *ws->h_ctl;
+  if (c.abort) return abort_error(c);
+  if (c.overflow != 0xffffffffu)
+    return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", a.qcap, c.overflow);
+  const int rounds = (int)c.rounds;
+  if (getenv("ALB_TIMELINE")) print_timeline(c, (int)op, rounds, (long long)c.threshold_used, g->clock_khz);
+  if (rounds >= a.max_rounds && c.qcount[rounds % 3] != 0)
+    return fail(ALB_E_DEVICE, "no convergence within %d rounds", a.max_rounds);
+  if (!o.out_on_device) {
+    std::vector<int32_t> h;
+    try {
+      h.resize((size_t)labels);
+    } catch (const std::bad_alloc &) {
+      return fail(ALB_E_NOMEM, "host allocation failed");
+    }
+    HIP_TRY(hipMemcpy(h.data(), ws->out32, sizeof(int32_t) * (size_t)labels, hipMemcpyDeviceToHost));
+    for (int32_t q = 0; q < count; ++q)
+      std::memcpy(outs[q], h.data() + qlbase[q], sizeof(int32_t) * (size_t)qn[q]);
+  }
+  if (st)
+    fill_stats(st, c, rounds, 1, (int64_t)c.n_members * wg, thresholds ? -1 : (int64_t)c.threshold_used, ws->ev[0],
+               ws->ev[1], ws->ev[2]);
   return ALB_OK;
 }
 
@@ -632,28 +875,15 @@ const char *alb_status_str(alb_status s) {
 
 const char *alb_last_error(void) { return g_err.c_str(); }
 
-alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, const int32_t *col,
-                            const int32_t *weights, uint32_t flags, alb_graph *out) {
-  if (!out) return fail(ALB_E_INVAL, "output handle pointer is NULL");
-  *out = nullptr;
-  if (flags & ~(uint32_t)(ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) return fail(ALB_E_INVAL, "unknown flags 0x%x", flags);
-  alb_status s = validate_csr(n, m, row_offsets, col, weights);
-  if (s != ALB_OK) return s;
+}  // extern "C"
 
-  std::vector<int32_t> soff, scol;
-  const int32_t *off = row_offsets, *cl = col, *w = weights;
-  int64_t mm = m;
-  if (flags & ALB_BUILD_SYMMETRIC) {
-    s = symmetrise(n, row_offsets, col, soff, scol);
-    if (s != ALB_OK) return s;
-    off = soff.data();
-    cl = scol.data();
-    mm = (int64_t)scol.size();
-    w = nullptr;
-  }
+namespace {
+
+// Copy a validated host CSR to the device and make the handle.
+alb_status make_graph(int32_t n, int64_t mm, const int32_t *off, const int32_t *cl, const int32_t *w, bool symmetric,
+                      alb_graph *out) {
   int32_t maxd = 0;
   for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, off[v + 1] - off[v]);
-
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   alb_graph g = new (std::nothrow) alb_graph_s();
@@ -669,9 +899,12 @@ alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, co
   g->n = n;
   g->m = mm;
   g->max_deg = maxd;
-  g->symmetric = (flags & (ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) != 0;
+  g->symmetric = symmetric;
   g->weighted = (w != nullptr);
   g->device = dev;
+  g->mem_vbase.assign(1, 0);
+  g->mem_n.assign(1, n);
+  g->mem_m.assign(1, mm);
   int attr = 0;
   hipError_t e;
   if ((e = hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
@@ -694,11 +927,104 @@ alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, co
   return ALB_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, const int32_t *col,
+                            const int32_t *weights, uint32_t flags, alb_graph *out) {
+  if (!out) return fail(ALB_E_INVAL, "output handle pointer is NULL");
+  *out = nullptr;
+  if (flags & ~(uint32_t)(ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) return fail(ALB_E_INVAL, "unknown flags 0x%x", flags);
+  alb_status s = validate_csr(n, m, row_offsets, col, weights);
+  if (s != ALB_OK) return s;
+  std::vector<int32_t> soff, scol;
+  const int32_t *off = row_offsets, *cl = col, *w = weights;
+  int64_t mm = m;
+  if (flags & ALB_BUILD_SYMMETRIC) {
+    s = symmetrise(n, row_offsets, col, soff, scol);
+    if (s != ALB_OK) return s;
+    off = soff.data();
+    cl = scol.data();
+    mm = (int64_t)scol.size();
+    w = nullptr;
+  }
+  return make_graph(n, mm, off, cl, w, (flags & (ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) != 0, out);
+}
+
+alb_status alb_graph_create_set(int32_t count, const int32_t *ns, const int64_t *ms,
+                                const int32_t *const *row_offsets, const int32_t *const *cols,
+                                const int32_t *const *weights, alb_graph *out) {
+  if (!out) return fail(ALB_E_INVAL, "output handle pointer is NULL");
+  *out = nullptr;
+  if (count < 1 || !ns || !ms || !row_offsets || !cols) return fail(ALB_E_INVAL, "bad graph-set arguments");
+  int64_t tn = 0, tm = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    alb_status s = validate_csr(ns[i], ms[i], row_offsets[i], cols[i], weights ? weights[i] : nullptr);
+    if (s != ALB_OK) {
+      std::string d = g_err;
+      return fail(s, "member %d: %s", i, d.c_str());
+    }
+    if (weights && !weights[i] && ms[i] > 0) return fail(ALB_E_INVAL, "member %d has no weights", i);
+    tn += ns[i];
+    tm += ms[i];
+  }
+  if (tn >= ((int64_t)1 << 31) - 1 || tm >= ((int64_t)1 << 31))
+    return fail(ALB_E_INVAL, "graph set too large (%lld vertices, %lld edges)", (long long)tn, (long long)tm);
+  std::vector<int32_t> off, col, w;
+  std::vector<int32_t> vbase(count), nn(count);
+  std::vector<int64_t> mm(count);
+  try {
+    off.resize((size_t)tn + 1);
+    col.resize((size_t)tm);
+    if (weights) w.resize((size_t)tm);
+  } catch (const std::bad_alloc &) {
+    return fail(ALB_E_NOMEM, "host allocation failed");
+  }
+  int64_t vb = 0, eb = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    vbase[i] = (int32_t)vb;
+    nn[i] = ns[i];
+    mm[i] = ms[i];
+    for (int32_t v = 0; v < ns[i]; ++v) off[(size_t)(vb + v)] = (int32_t)(eb + row_offsets[i][v]);
+    for (int64_t p = 0; p < ms[i]; ++p) col[(size_t)(eb + p)] = (int32_t)(vb + cols[i][p]);
+    if (weights && ms[i]) std::memcpy(w.data() + eb, weights[i], sizeof(int32_t) * (size_t)ms[i]);
+    vb += ns[i];
+    eb += ms[i];
+  }
+  off[(size_t)tn] = (int32_t)tm;
+  alb_status s = make_graph((int32_t)tn, tm, off.data(), col.data(), weights ? w.data() : nullptr, false, out);
+  if (s != ALB_OK) return s;
+  (*out)->mem_vbase = vbase;
+  (*out)->mem_n = nn;
+  (*out)->mem_m = mm;
+  return ALB_OK;
+}
+
+alb_status alb_graph_members(alb_graph g, int32_t *count) {
+  if (!g || !count) return fail(ALB_E_INVAL, "NULL argument");
+  *count = (int32_t)g->mem_n.size();
+  return ALB_OK;
+}
+
+alb_status alb_graph_member_info(alb_graph g, int32_t member, int32_t *n, int64_t *m, int32_t *vertex_base) {
+  if (!g) return fail(ALB_E_INVAL, "graph handle is NULL");
+  if (member < 0 || member >= (int32_t)g->mem_n.size()) return fail(ALB_E_INVAL, "member %d out of range", member);
+  if (n) *n = g->mem_n[member];
+  if (m) *m = g->mem_m[member];
+  if (vertex_base) *vertex_base = g->mem_vbase[member];
+  return ALB_OK;
+}
+
 alb_status alb_graph_destroy(alb_graph g) {
   if (!g) return ALB_OK;
   (void)hipSetDevice(g->device);
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   for (Workspace *w : g->pool) {
+    w->release();
+    delete w;
+  }
+  for (BatchWs *w : g->batch_pool) {
     w->release();
     delete w;
   }
@@ -720,6 +1046,7 @@ alb_status alb_graph_info(alb_graph g, int32_t *n, int64_t *m, int32_t *max_out_
     std::lock_guard<std::mutex> lk(g->mu);
     size_t b = g->graph_bytes;
     for (Workspace *w : g->pool) b += w->bytes;
+    for (BatchWs *w : g->batch_pool) b += w->bytes;
     *device_bytes = b;
   }
   return ALB_OK;
@@ -878,6 +1205,22 @@ alb_status alb_trace_round(alb_graph g, const int32_t *frontier, int64_t nf, con
   prefix[vh] = ehuge;
   *nnext = nn;
   return ALB_OK;
+}
+
+alb_status alb_bfs_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                         int32_t *const *levels, const int64_t *thresholds, const alb_options *opt, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = run_batch(g, OP_BFS, count, members, sources, levels, thresholds, opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_sssp_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                          int32_t *const *dists, const int64_t *thresholds, const alb_options *opt, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = run_batch(g, OP_SSSP, count, members, sources, dists, thresholds, opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
 }
 
 }  // extern "C"

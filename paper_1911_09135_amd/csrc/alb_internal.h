@@ -38,6 +38,8 @@ constexpr int kHintMinShift = 10;
 // the cyclic distribution, which keeps every workgroup busy.
 constexpr int kAdaptiveSmall = 64;
 constexpr int kHintMaxShift = 20;
+// Queries in one batch launch (the output kernel puts one query on each grid row).
+constexpr int32_t kMaxBatch = 65535;
 
 // Per-call control block in device memory.  Counters rotate by round so that
 // one round can clear the counter two rounds ahead without a separate launch.
@@ -82,8 +84,8 @@ struct Args {
   const int32_t *w;    // m (SSSP)
   int32_t n;
   uint32_t qcap;        // capacity of each worklist and of the huge list
-  int32_t *q0;          // worklists (double buffered)
-  int32_t *q1;
+  void *q0;             // worklists (double buffered): int32 vertex ids, or (query << 32 | vertex) for a batch
+  void *q1;
   int4 *huge_rec;       // huge list (Algorithm 1 `work`): per slot {prefixWork entry, CSR start, vertex, source value}
   int32_t *hint;        // chunk index of the huge edges
   uint32_t hint_cap;
@@ -111,6 +113,16 @@ struct Args {
   int32_t *hits;        // trace operator
   int32_t *thread_of;
   int8_t *bins;
+  // batch of queries sharing one launch (one graph set, see alb_graph_create_set)
+  int32_t nq;
+  const long long *qoff;   // label index of (query q, vertex v) = qoff[q] + v
+  const long long *qthr;   // per-query huge thresholds, or null
+  long long qthr_min;      // smallest of them
+  const long long *qlbase; // first label index of query q
+  const int32_t *qsrc;     // source vertex of query q (graph-set vertex id)
+  const int32_t *qn;       // vertex count of query q's graph
+  int32_t *const *qout;    // output array of query q
+  long long nlabels;       // labels of all queries
 };
 
 // Host-callable launchers (alb_kernels.hip).  All return the launch status.
@@ -126,5 +138,10 @@ hipError_t launch_finish(const Args &a, hipStream_t s);
 // itself finds out how many are co-resident).
 hipError_t persistent_occupancy(OpKind op, int wg, int *blocks_per_cu);
 bool supported_wg(int wg);
+// Batches of BFS / SSSP queries on a graph set (Args::nq queries).
+hipError_t batch_occupancy(OpKind op, int wg, int *blocks_per_cu);
+hipError_t launch_init_batch(OpKind op, const Args &a, hipStream_t s);
+hipError_t launch_batch(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
+hipError_t launch_finish_batch(OpKind op, const Args &a, int32_t max_n, hipStream_t s);
 
 }  // namespace alb

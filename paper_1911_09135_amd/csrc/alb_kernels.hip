@@ -28,6 +28,8 @@
 // Rounds are driven either from the host (one launch per phase) or inside one
 // persistent launch whose phases are separated by a grid-wide barrier.
 
+#include <type_traits>
+
 #include "alb_internal.h"
 
 namespace alb {
@@ -83,6 +85,10 @@ __device__ __forceinline__ V from_bits(int32_t x) {
 // loads in flight before the first decision.
 // ---------------------------------------------------------------------------
 
+// Label indices (long long) address the label arrays: the vertex id for a
+// single query; query offset + vertex id for a batch of queries sharing one
+// launch.  Graph indices (CSR positions, vertex ids) are separate.
+
 // BFS: level[dst] = level[src] + 1 on first visit (compare-and-swap from INF).
 // Every active vertex of round r has level r, so no source level is read.
 struct OpBFS {
@@ -90,17 +96,17 @@ struct OpBFS {
   struct pre_t {
     int32_t cur;
   };
-  static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
+  static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false, kBatch = true;
   int32_t *level;
-  __device__ __forceinline__ val_t load_src(int32_t, int32_t, uint32_t tag, bool &) const {
+  __device__ __forceinline__ val_t load_src(long long, int32_t, uint32_t tag, bool &) const {
     return (int32_t)tag - 1;
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, int32_t dst, val_t) const { return {level[dst]}; }
-  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t) const { return {level[dl]}; }
+  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
     if (p.cur != kInf) return false;
     int32_t expected = kInf;
-    return __hip_atomic_compare_exchange_strong(&level[dst], &expected, sv + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+    return __hip_atomic_compare_exchange_strong(&level[dl], &expected, sv + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
   }
 };
@@ -136,19 +142,19 @@ struct OpSSSP {  // relaxation: dist[dst] = min(dist[dst], dist[src] + w)
     int32_t cand;
     unsigned long long cur;
   };
-  static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
+  static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false, kBatch = true;
   unsigned long long *word;
   const int32_t *w;
   int32_t dedup;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t, uint32_t tag, bool &skip) const {
-    return label_of_active(word[v], tag, skip);
+  __device__ __forceinline__ val_t load_src(long long sl, int32_t, uint32_t tag, bool &skip) const {
+    return label_of_active(word[sl], tag, skip);
   }
-  __device__ __forceinline__ pre_t prepare(int32_t pos, int32_t dst, val_t sv) const {
-    return {sv + w[pos], word[dst]};
+  __device__ __forceinline__ pre_t prepare(int32_t pos, long long dl, val_t sv) const {
+    return {sv + w[pos], word[dl]};
   }
-  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t, int32_t, int32_t,
+  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t, int32_t, int32_t,
                                          uint32_t tag) const {
-    return lower_word(&word[dst], p.cand, p.cur, tag, dedup);
+    return lower_word(&word[dl], p.cand, p.cur, tag, dedup);
   }
 };
 
@@ -157,32 +163,32 @@ struct OpCC {  // min-label propagation
   struct pre_t {
     unsigned long long cur;
   };
-  static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false;
+  static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false, kBatch = false;
   unsigned long long *word;
   int32_t dedup;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t, uint32_t tag, bool &skip) const {
-    return label_of_active(word[v], tag, skip);
+  __device__ __forceinline__ val_t load_src(long long sl, int32_t, uint32_t tag, bool &skip) const {
+    return label_of_active(word[sl], tag, skip);
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, int32_t dst, val_t) const { return {word[dst]}; }
-  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t) const { return {word[dl]}; }
+  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t tag) const {
-    return lower_word(&word[dst], sv, p.cur, tag, dedup);
+    return lower_word(&word[dl], sv, p.cur, tag, dedup);
   }
 };
 
 struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact fixed-point sum
   using val_t = float;
   struct pre_t {};
-  static constexpr bool kPush = false, kNeedSrc = false, kRecord = false, kPR = true;
+  static constexpr bool kPush = false, kNeedSrc = false, kRecord = false, kPR = true, kBatch = false;
   const float *rank;
   unsigned long long *acc;
-  __device__ __forceinline__ val_t load_src(int32_t v, int32_t deg, uint32_t, bool &) const {
-    return rank[v] / (float)deg;
+  __device__ __forceinline__ val_t load_src(long long sl, int32_t deg, uint32_t, bool &) const {
+    return rank[sl] / (float)deg;
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, int32_t, val_t) const { return {}; }
-  __device__ __forceinline__ bool commit(const pre_t &, int32_t, int32_t dst, val_t sv, int32_t, int32_t,
+  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t) const { return {}; }
+  __device__ __forceinline__ bool commit(const pre_t &, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
-    add_relaxed(&acc[dst], to_fix(sv));
+    add_relaxed(&acc[dl], to_fix(sv));
     return false;
   }
 };
@@ -190,12 +196,12 @@ struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact 
 struct OpRecord {  // counts each processed edge and the thread that took it; pushes every destination
   using val_t = int32_t;
   struct pre_t {};
-  static constexpr bool kPush = true, kNeedSrc = true, kRecord = true, kPR = false;
+  static constexpr bool kPush = true, kNeedSrc = true, kRecord = true, kPR = false, kBatch = false;
   int32_t *hits;
   int32_t *thread_of;
-  __device__ __forceinline__ val_t load_src(int32_t, int32_t, uint32_t, bool &) const { return 0; }
-  __device__ __forceinline__ pre_t prepare(int32_t, int32_t, val_t) const { return {}; }
-  __device__ __forceinline__ bool commit(const pre_t &, int32_t pos, int32_t, val_t, int32_t, int32_t gt,
+  __device__ __forceinline__ val_t load_src(long long, int32_t, uint32_t, bool &) const { return 0; }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t) const { return {}; }
+  __device__ __forceinline__ bool commit(const pre_t &, int32_t pos, long long, val_t, int32_t, int32_t gt,
                                          uint32_t) const {
     add_relaxed(&hits[pos], 1);
     thread_of[pos] = gt;
@@ -235,12 +241,16 @@ __device__ __forceinline__ void prof_mark(const Args &a, Acc &acc, int k, uint64
   }
 }
 
-template <int B, class Op>
+// Worklist entries: a vertex id for one query; (query << 32) | vertex for a batch.
+template <bool M>
+using Entry = typename std::conditional<M, unsigned long long, int32_t>::type;
+
+template <int B, class Op, bool M = false>
 struct Smem {
   using V = typename Op::val_t;
-  int32_t pos[kU * B];  // thread-bin gather: CSR position, source value and source of each staged edge
+  int32_t pos[kU * B];  // thread-bin gather: CSR position, source value and source (batch: query) of each edge
   V sv[kU * B];
-  int32_t src[Op::kNeedSrc ? kU * B : 1];
+  int32_t src[(Op::kNeedSrc || M) ? kU * B : 1];
   int32_t wsum[B / kWave];
   unsigned long long ured[B / kWave][5];
   unsigned long long dred[B / kWave];
@@ -248,7 +258,7 @@ struct Smem {
   V osv;
   int32_t flag;
   uint32_t chunk;
-  int32_t pbuf[B / kWave][kPushBuf];  // per-wavefront push staging
+  Entry<M> pbuf[B / kWave][kPushBuf];  // per-wavefront push staging
 };
 
 // The workgroup's index and the workgroup count used for work distribution:
@@ -261,15 +271,16 @@ struct Grid {
 
 // Next-worklist pushes of one wavefront, staged in LDS and written out in
 // batches: one global reservation per batch instead of one per ballot.
+template <class E>
 struct Pusher {
-  int32_t *buf;      // this wavefront's LDS staging area
+  E *buf;            // this wavefront's LDS staging area
   uint32_t cnt;      // entries staged (wave-uniform)
-  int32_t *qn;       // next worklist
+  E *qn;             // next worklist
   uint32_t *qn_cnt;  // its size counter
 };
 
-template <int B, class Op>
-__device__ void flush_stats(Acc &acc, Smem<B, Op> &sm, Ctl *c) {
+template <int B, class Op, bool M>
+__device__ void flush_stats(Acc &acc, Smem<B, Op, M> &sm, Ctl *c) {
   const uint32_t lane = lane_id();
   const int w = threadIdx.x / kWave;
   unsigned long long v[5] = {acc.frontier, acc.edges_twc, acc.edges_lb, acc.huge_v, acc.pushes};
@@ -296,8 +307,8 @@ __device__ void flush_stats(Acc &acc, Smem<B, Op> &sm, Ctl *c) {
   acc = Acc();
 }
 
-template <int B, class Op>
-__device__ void flush_dangling(Acc &acc, Smem<B, Op> &sm, unsigned long long *dst) {
+template <int B, class Op, bool M>
+__device__ void flush_dangling(Acc &acc, Smem<B, Op, M> &sm, unsigned long long *dst) {
   unsigned long long x = acc.dangling;
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
@@ -313,7 +324,8 @@ __device__ void flush_dangling(Acc &acc, Smem<B, Op> &sm, unsigned long long *ds
 }
 
 // Write the staged entries to the next worklist (all lanes call this).
-__device__ __forceinline__ void flush_pushes(const Args &a, int round, Pusher &pu) {
+template <class E>
+__device__ __forceinline__ void flush_pushes(const Args &a, int round, Pusher<E> &pu) {
   if (pu.cnt == 0) return;
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   uint32_t base = 0;
@@ -331,7 +343,8 @@ __device__ __forceinline__ void flush_pushes(const Args &a, int round, Pusher &p
 }
 
 // Stage v for every lane with pred (all lanes of the wavefront call this).
-__device__ __forceinline__ void push_wave(bool pred, int32_t v, const Args &a, int round, Pusher &pu, Acc &acc) {
+template <class E>
+__device__ __forceinline__ void push_wave(bool pred, E v, const Args &a, int round, Pusher<E> &pu, Acc &acc) {
   const unsigned long long m = __ballot(pred);
   if (m == 0ull) return;
   const uint32_t total = (uint32_t)__popcll(m);
@@ -354,10 +367,11 @@ __device__ __forceinline__ uint32_t hint_shift(int64_t t) {
 // list and its degree to the running edge total with ONE 64-bit atomic per
 // wavefront on (count << 32 | edges).  Slot j receives the edges of all
 // earlier slots as its prefixWork entry, i.e. the exclusive scan of the huge
-// degrees in list order, with the vertex's CSR start and source value.  The
+// degrees in list order, with the vertex's CSR start, the vertex (batch: its
+// query) and the source value.  The
 // wavefront then writes the chunk index for every chunk whose first edge
 // falls in one of its new segments.  All lanes of the wavefront call this.
-__device__ __forceinline__ void reserve_huge(bool huge, int32_t v, int32_t beg, int32_t deg, int32_t sv_bits,
+__device__ __forceinline__ void reserve_huge(bool huge, int32_t v_or_q, int32_t beg, int32_t deg, int32_t sv_bits,
                                              const Args &a, int round, unsigned long long *ctr, uint32_t hs,
                                              Acc &acc) {
   const unsigned long long hm = __ballot(huge);
@@ -392,7 +406,7 @@ __device__ __forceinline__ void reserve_huge(bool huge, int32_t v, int32_t beg, 
     j = (uint32_t)(base >> 32) + bits_below(hm);
     p = (uint32_t)base + (uint32_t)(incl - mine);
     if (j < a.qcap)
-      a.huge_rec[j] = make_int4((int32_t)p, beg, v, sv_bits);
+      a.huge_rec[j] = make_int4((int32_t)p, beg, v_or_q, sv_bits);
     else
       flag_overflow(a.ctl, round);
   }
@@ -415,23 +429,41 @@ __device__ __forceinline__ void reserve_huge(bool huge, int32_t v, int32_t beg, 
 }
 
 // Apply the operator along up to kU edges per lane and push; every lane of
-// the wavefront calls this (act[u] false for empty slots).
-template <class Op>
+// the wavefront calls this (act[u] false for empty slots).  src[u] is the
+// source vertex (recorder) or, for a batch, the query of slot u.
+template <class Op, bool M>
 __device__ __forceinline__ void edges(const bool (&act)[kU], const int32_t (&pos)[kU],
                                       const typename Op::val_t (&sv)[kU], const int32_t (&src)[kU], const Op &op,
-                                      const Args &a, uint32_t tag, int round, Pusher &pu, Acc &acc, int32_t gt) {
+                                      const Args &a, uint32_t tag, int round, Pusher<Entry<M>> &pu, Acc &acc,
+                                      int32_t gt) {
   int32_t dst[kU];
+  long long dl[kU];
   typename Op::pre_t pre[kU];
 #pragma unroll
   for (int u = 0; u < kU; ++u) dst[u] = a.col[act[u] ? pos[u] : 0];
+  // an empty slot addresses label 0, which always exists (a batch's query
+  // offsets can be negative, so no other index is safe for every query)
 #pragma unroll
-  for (int u = 0; u < kU; ++u) pre[u] = op.prepare(act[u] ? pos[u] : 0, dst[u], sv[u]);
+  for (int u = 0; u < kU; ++u) {
+    if constexpr (M)
+      dl[u] = act[u] ? dst[u] + a.qoff[src[u]] : 0;
+    else
+      dl[u] = act[u] ? dst[u] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) pre[u] = op.prepare(act[u] ? pos[u] : 0, dl[u], sv[u]);
   bool p[kU];
 #pragma unroll
-  for (int u = 0; u < kU; ++u) p[u] = act[u] && op.commit(pre[u], pos[u], dst[u], sv[u], src[u], gt, tag);
+  for (int u = 0; u < kU; ++u) p[u] = act[u] && op.commit(pre[u], pos[u], dl[u], sv[u], src[u], gt, tag);
   if constexpr (Op::kPush) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) push_wave(p[u], dst[u], a, round, pu, acc);
+    for (int u = 0; u < kU; ++u) {
+      if constexpr (M)
+        push_wave<Entry<M>>(p[u], ((unsigned long long)(uint32_t)src[u] << 32) | (uint32_t)dst[u], a, round, pu,
+                            acc);
+      else
+        push_wave<Entry<M>>(p[u], dst[u], a, round, pu, acc);
+    }
   }
 }
 
@@ -462,17 +494,17 @@ __device__ __forceinline__ void block_exscan(int32_t x, int32_t &excl, int32_t &
 // ---------------------------------------------------------------------------
 // Phase 1: inspection (Algorithm 1) fused with the TWC bins.
 // ---------------------------------------------------------------------------
-template <int B, class Op>
-__device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, int round, const int32_t *F,
-                          uint32_t nF, int32_t *qn, uint32_t *qn_cnt, unsigned long long *hctr, int64_t threshold,
-                          uint32_t hs, Acc &acc) {
+template <int B, class Op, bool M>
+__device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid gr, int round,
+                          const Entry<M> *F, uint32_t nF, Entry<M> *qn, uint32_t *qn_cnt, unsigned long long *hctr,
+                          int64_t threshold, uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
   const int tid = threadIdx.x;
   const uint32_t lane = lane_id();
   const int32_t gt = (int32_t)(gr.id * B + tid);
   const uint32_t tag = (uint32_t)round + 1u;
   uint32_t *chunk_ctr = &a.ctl->chunk[round % 3];
-  Pusher pu{sm.pbuf[tid / kWave], 0u, qn, qn_cnt};
+  Pusher<Entry<M>> pu{sm.pbuf[tid / kWave], 0u, qn, qn_cnt};
   uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
   // Workgroups claim B-entry chunks of the worklist one at a time, so a chunk
   // that takes long does not hold up work queued behind it on the same
@@ -484,21 +516,31 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
     const uint64_t base = (uint64_t)sm.chunk * B;
     if (base >= nF) break;
     const uint32_t i = (uint32_t)base + tid;
-    int32_t v = -1, beg = 0, deg = 0;
+    int32_t v = -1, beg = 0, deg = 0, q = 0;  // q: the entry's query (batch)
+    int64_t thr = threshold;
     if (i < nF) {
-      v = F ? F[i] : (int32_t)i;
+      if constexpr (M) {
+        const unsigned long long e = F[i];
+        v = (int32_t)(uint32_t)e;
+        q = (int32_t)(e >> 32);
+        if (a.qthr) thr = a.qthr[q];
+      } else {
+        v = F ? F[i] : (int32_t)i;
+      }
       beg = a.off[v];
       deg = a.off[v + 1] - beg;
     }
     V sv = V(0);
     if (deg > 0) {
       bool skip = false;
-      sv = op.load_src(v, deg, tag, skip);
+      long long sl = v;
+      if constexpr (M) sl += a.qoff[q];
+      sv = op.load_src(sl, deg, tag, skip);
       if (skip) deg = 0;
     }
     // inspection: degree >= THRESHOLD goes to the huge list
-    const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= threshold;
-    reserve_huge(huge, v, beg, deg, to_bits(sv), a, round, hctr, hs, acc);
+    const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= thr;
+    reserve_huge(huge, M ? q : v, beg, deg, to_bits(sv), a, round, hctr, hs, acc);
     if constexpr (Op::kRecord) {
       if (i < nF) a.bins[i] = (int8_t)(huge ? 3 : deg >= a.c_wg ? 2 : deg >= a.c_wave ? 1 : 0);
     }
@@ -522,7 +564,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
         sm.obeg = beg;
         sm.odeg = deg;
         sm.osv = sv;
-        sm.ov = v;
+        sm.ov = M ? q : v;
         deg = 0;
       }
       __syncthreads();
@@ -540,7 +582,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
           s[u] = os;
           src[u] = ov;
         }
-        edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
+        edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       }
     }
 
@@ -550,7 +592,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       const unsigned long long mm = __ballot(deg > 0 && deg >= a.c_wave);
       if (mm == 0ull) break;
       const int ld = __ffsll(mm) - 1;
-      const int32_t ob = __shfl(beg, ld), od = __shfl(deg, ld), ov = __shfl(v, ld);
+      const int32_t ob = __shfl(beg, ld), od = __shfl(deg, ld), ov = __shfl(M ? q : v, ld);
       const V os = __shfl(sv, ld);
       if ((int)lane == ld) deg = 0;
       for (int32_t j0 = 0; j0 < od; j0 += kU * kWave) {
@@ -565,7 +607,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
           s[u] = os;
           src[u] = ov;
         }
-        edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
+        edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       }
     }
 
@@ -579,7 +621,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
       for (int32_t e = lo; e < hi; ++e) {
         sm.pos[e - done] = beg + (e - rank);
         sm.sv[e - done] = sv;
-        if constexpr (Op::kNeedSrc) sm.src[e - done] = v;
+        if constexpr (Op::kNeedSrc || M) sm.src[e - done] = M ? q : v;
       }
       __syncthreads();
       const int32_t cnt = min(kU * B, total - done);
@@ -593,9 +635,9 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr,
         pos[u] = act[u] ? sm.pos[idx] : 0;
         s[u] = act[u] ? sm.sv[idx] : V(0);
         src[u] = 0;
-        if constexpr (Op::kNeedSrc) src[u] = act[u] ? sm.src[idx] : 0;
+        if constexpr (Op::kNeedSrc || M) src[u] = act[u] ? sm.src[idx] : 0;
       }
-      edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
+      edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       __syncthreads();
     }
     prof_mark(a, acc, kProfThreadBin, pt);
@@ -628,9 +670,9 @@ __device__ __forceinline__ uint32_t owner_of(const Args &a, uint32_t vh, uint32_
 // ---------------------------------------------------------------------------
 // Phase 2: execution (Algorithm 2) with the cyclic distribution.
 // ---------------------------------------------------------------------------
-template <int B, class Op>
-__device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, int round, unsigned long long hc,
-                         int32_t *qn, uint32_t *qn_cnt, uint32_t hs, Acc &acc) {
+template <int B, class Op, bool M>
+__device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid gr, int round, unsigned long long hc,
+                         Entry<M> *qn, uint32_t *qn_cnt, uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
   const uint32_t vh = (uint32_t)(hc >> 32);
   const uint32_t e = (uint32_t)hc;
@@ -641,7 +683,7 @@ __device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, 
   const uint32_t lane = lane_id();
   const uint64_t g = (uint64_t)gr.id * B + threadIdx.x;
   const uint32_t tag = (uint32_t)round + 1u;
-  Pusher pu{sm.pbuf[threadIdx.x / kWave], 0u, qn, qn_cnt};
+  Pusher<Entry<M>> pu{sm.pbuf[threadIdx.x / kWave], 0u, qn, qn_cnt};
   uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
   // thread g takes huge edges g, g + T, g + 2T, ...; kU of them per pass
   for (uint64_t k0 = g - lane; k0 < e; k0 += kU * T) {
@@ -663,7 +705,7 @@ __device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op> &sm, Grid gr, 
       }
       acc.edges_lb += act[u];
     }
-    edges<Op>(act, pos, s, src, op, a, tag, round, pu, acc, (int32_t)g);
+    edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, (int32_t)g);
   }
   if constexpr (Op::kPush) flush_pushes(a, round, pu);
   prof_mark(a, acc, kProfLb, pt);
@@ -733,11 +775,15 @@ __device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &
   return sm.flag != 0;
 }
 
-__device__ __forceinline__ const int32_t *round_frontier(const Args &a, int r) {
+template <bool M>
+__device__ __forceinline__ const Entry<M> *round_frontier(const Args &a, int r) {
   if (a.all_rounds || (r == 0 && a.identity_first)) return nullptr;
-  return (r & 1) ? a.q1 : a.q0;
+  return (const Entry<M> *)((r & 1) ? a.q1 : a.q0);
 }
-__device__ __forceinline__ int32_t *round_next(const Args &a, int r) { return (r & 1) ? a.q0 : a.q1; }
+template <bool M>
+__device__ __forceinline__ Entry<M> *round_next(const Args &a, int r) {
+  return (Entry<M> *)((r & 1) ? a.q0 : a.q1);
+}
 
 __device__ __forceinline__ uint32_t round_size(const Args &a, int r) {
   if (a.all_rounds) return (uint32_t)a.n;
@@ -851,7 +897,7 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     c->diag_round = 0;
     c->threshold_used = a.threshold;
     for (int k = 0; k < kProfParts; ++k) c->prof[k] = 0;
-    if (source >= 0 && op != OP_RECORD) a.q0[0] = source;
+    if (source >= 0 && op != OP_RECORD) ((int32_t *)a.q0)[0] = source;
   }
 }
 
@@ -859,6 +905,58 @@ __global__ void k_finish(Args a) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)a.n; v += stride)
     a.out[v] = (int32_t)(a.word[v] >> 32);
+}
+
+// Batch set-up, part 1: every label of every query to INF, barrier words and
+// the control block cleared (the sources are seeded by k_seed_batch after).
+__global__ void k_init_batch(Args a, int op) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (size_t i = t; i < (size_t)a.nlabels; i += stride) {
+    if (op == OP_BFS) a.level[i] = kInf;
+    if (op == OP_SSSP) a.word[i] = (unsigned long long)(uint32_t)kInf << 32;
+  }
+  for (size_t i = t; i < kBarWords; i += stride) a.bar[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl *c = a.ctl;
+    c->qcount[0] = (uint32_t)a.nq;
+    c->qcount[1] = c->qcount[2] = 0;
+    c->chunk[0] = c->chunk[1] = c->chunk[2] = 0;
+    c->overflow = 0xffffffffu;
+    c->huge[0] = c->huge[1] = 0;
+    c->abort = 0;
+    c->rounds = 0;
+    c->st_frontier = c->st_edges_twc = c->st_edges_lb = c->st_huge_v = c->st_pushes = 0;
+    c->dangling[0] = c->dangling[1] = 0;
+    c->members = 0;
+    c->n_members = 0;
+    c->diag_seen = c->diag_target = 0;
+    c->diag_round = 0;
+    c->threshold_used = a.threshold;
+    for (int k = 0; k < kProfParts; ++k) c->prof[k] = 0;
+  }
+}
+
+// Batch set-up, part 2: query q's source gets label 0 and is entry q of the
+// first worklist.
+__global__ void k_seed_batch(Args a, int op) {
+  for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < a.nq; q += gridDim.x * blockDim.x) {
+    const int32_t s = a.qsrc[q];
+    const long long l = a.qoff[q] + s;
+    if (op == OP_BFS) a.level[l] = 0;
+    if (op == OP_SSSP) a.word[l] = 0ull;
+    ((unsigned long long *)a.q0)[q] = ((unsigned long long)(uint32_t)q << 32) | (uint32_t)s;
+  }
+}
+
+// Batch outputs: query blockIdx.y, its vertices strided over blockIdx.x.
+__global__ void k_finish_batch(Args a, int op) {
+  const int32_t q = blockIdx.y;
+  const int32_t n = a.qn[q];
+  const long long base = a.qlbase[q];
+  int32_t *out = a.qout[q];
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    out[v] = op == OP_BFS ? a.level[base + v] : (int32_t)(a.word[base + v] >> 32);
 }
 
 template <int B, class Op>
@@ -870,7 +968,8 @@ __global__ __launch_bounds__(B) void k_twc(Args a, Op op) {
   if (blockIdx.x == 0 && threadIdx.x == 0) clear_ahead(a, r);
   const Grid gr{blockIdx.x, gridDim.x};
   const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
-  phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
+  phase_twc<B, Op, false>(a, op, sm, gr, r, round_frontier<false>(a, r), nF, round_next<false>(a, r),
+                          &a.ctl->qcount[(r + 1) % 3],
                    &a.ctl->huge[r & 1], thr, hint_shift(thr), acc);
   if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
   flush_stats<B, Op>(acc, sm, a.ctl);
@@ -883,7 +982,8 @@ __global__ __launch_bounds__(B) void k_lb(Args a, Op op) {
   const int r = a.round;
   const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
   const int64_t thr = round_threshold(a, round_size(a, r), (uint64_t)gridDim.x * B);
-  phase_lb<B, Op>(a, op, sm, Grid{blockIdx.x, gridDim.x}, r, hc, round_next(a, r), &a.ctl->qcount[(r + 1) % 3],
+  phase_lb<B, Op, false>(a, op, sm, Grid{blockIdx.x, gridDim.x}, r, hc, round_next<false>(a, r),
+                         &a.ctl->qcount[(r + 1) % 3],
                   hint_shift(thr), acc);
   flush_stats<B, Op>(acc, sm, a.ctl);
 }
@@ -894,9 +994,9 @@ __global__ __launch_bounds__(B) void k_pr_update(Args a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->rounds, (uint32_t)a.round + 1u);
 }
 
-template <int B, class Op>
+template <int B, class Op, bool M>
 __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
-  __shared__ Smem<B, Op> sm;
+  __shared__ Smem<B, Op, M> sm;
   Acc acc;
   Grid gr;
   if (!join_members(a, sm, &gr)) return;
@@ -910,11 +1010,13 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
     const bool tl = gr.id == 0 && threadIdx.x == 0 && r < kTimeline;
     if (gr.id == 0 && threadIdx.x == 0) clear_ahead(a, r);
     if (tl) a.ctl->tl[4 * r] = (unsigned long long)wall_clock64();
-    int32_t *qn = round_next(a, r);
+    Entry<M> *qn = round_next<M>(a, r);
     uint32_t *qn_cnt = &a.ctl->qcount[(r + 1) % 3];
     const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
-    const uint32_t hs = hint_shift(thr);
-    phase_twc<B, Op>(a, op, sm, gr, r, round_frontier(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], thr, hs, acc);
+    // batch with per-query thresholds: chunk index sized for the smallest one
+    const uint32_t hs = hint_shift(M && a.qthr ? a.qthr_min : thr);
+    phase_twc<B, Op, M>(a, op, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], thr, hs,
+                        acc);
     if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
     uint64_t pb = a.profile ? (uint64_t)wall_clock64() : 0;
     if (!grid_barrier(a, sm, gr, epoch, r)) break;
@@ -925,7 +1027,7 @@ __global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
       a.ctl->tl[4 * r + 3] = (unsigned long long)nF | ((hc >> 32) << 32);
     }
     if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
-      phase_lb<B, Op>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+      phase_lb<B, Op, M>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
       pb = a.profile ? (uint64_t)wall_clock64() : 0;
       if (!grid_barrier(a, sm, gr, epoch, r)) break;
       prof_mark(a, acc, kProfBarrier, pb);
@@ -964,14 +1066,35 @@ struct LbF {
 template <int B, class Op>
 struct PersistentF {
   static hipError_t run(int grid, const Args *a, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<B, Op>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
+    hipLaunchKernelGGL((k_persistent<B, Op, false>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
     return hipGetLastError();
   }
 };
 template <int B, class Op>
 struct OccF {
   static hipError_t run(int *blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_persistent<B, Op>, B, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_persistent<B, Op, false>, B, 0);
+  }
+};
+// batches: BFS and SSSP only
+template <int B, class Op>
+struct BatchF {
+  static hipError_t run(int grid, const Args *a, hipStream_t s) {
+    if constexpr (Op::kBatch) {
+      hipLaunchKernelGGL((k_persistent<B, Op, true>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+};
+template <int B, class Op>
+struct BatchOccF {
+  static hipError_t run(int *blocks) {
+    if constexpr (Op::kBatch)
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_persistent<B, Op, true>, B, 0);
+    else
+      return hipErrorInvalidValue;
   }
 };
 
@@ -1030,6 +1153,32 @@ hipError_t launch_persistent(OpKind op, int wg, int grid, const Args &a, hipStre
 }
 hipError_t persistent_occupancy(OpKind op, int wg, int *blocks_per_cu) {
   return by_wg<OccF>(op, wg, blocks_per_cu);
+}
+hipError_t batch_occupancy(OpKind op, int wg, int *blocks_per_cu) { return by_wg<BatchOccF>(op, wg, blocks_per_cu); }
+hipError_t launch_batch(OpKind op, int wg, int grid, const Args &a, hipStream_t s) {
+  return by_wg<BatchF>(op, wg, grid, &a, s);
+}
+
+hipError_t launch_init_batch(OpKind op, const Args &a, hipStream_t s) {
+  const int threads = 256;
+  long long blocks = (a.nlabels + threads - 1) / threads;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 128) blocks = 128;
+  hipLaunchKernelGGL(k_init_batch, dim3((unsigned)blocks), dim3(threads), 0, s, a, (int)op);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int sblocks = (a.nq + threads - 1) / threads;
+  hipLaunchKernelGGL(k_seed_batch, dim3(sblocks < 1 ? 1 : sblocks), dim3(threads), 0, s, a, (int)op);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_batch(OpKind op, const Args &a, int32_t max_n, hipStream_t s) {
+  const int threads = 256;
+  int bx = (max_n + threads - 1) / threads;
+  if (bx > 64) bx = 64;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_finish_batch, dim3(bx, a.nq), dim3(threads), 0, s, a, (int)op);
+  return hipGetLastError();
 }
 
 hipError_t launch_pr_update(int wg, int grid, const Args &a, hipStream_t s) {

@@ -105,6 +105,57 @@ def test_calls_reject_null_handles(alb):
     assert alb._lib.alb_options_init(None) == alb.ALB_E_INVAL
 
 
+def _create_set(alb, members, weighted=False):
+    keep = []
+    k = len(members)
+    P = ctypes.c_void_p * k
+    offs, cols, ws = P(), P(), P()
+    ns = np.array([len(o) - 1 for o, _, _ in members], np.int32)
+    ms = np.array([len(c) for _, c, _ in members], np.int64)
+    for i, (o, c, w) in enumerate(members):
+        o, c = np.ascontiguousarray(o, np.int32), np.ascontiguousarray(c, np.int32)
+        keep += [o, c]
+        offs[i], cols[i] = o.ctypes.data, (c.ctypes.data if c.size else None)
+        if w is not None:
+            w = np.ascontiguousarray(w, np.int32)
+            keep.append(w)
+            ws[i] = w.ctypes.data if w.size else None
+    h = ctypes.c_void_p()
+    st = alb._lib.alb_graph_create_set(k, ns.ctypes.data, ms.ctypes.data, ctypes.cast(offs, ctypes.c_void_p),
+                                       ctypes.cast(cols, ctypes.c_void_p),
+                                       ctypes.cast(ws, ctypes.c_void_p) if weighted else None, ctypes.byref(h))
+    return st, alb._lib.alb_last_error().decode()
+
+
+@pytest.mark.parametrize("members,weighted", [
+    ([([0, 1, 1], [1], None), ([0, 1, 2], [3, 0], None)], False),   # member 1: column out of range
+    ([([0, 1, 1], [1], None), ([1, 1], [], None)], False),          # member 1: offsets[0] != 0
+    ([([0, 1, 1], [1], [5]), ([0, 1, 1], [0], None)], True),        # member 1 has edges but no weights
+    ([([0, 1, 1], [1], [-5])], True),                               # negative weight
+])
+def test_graph_set_validation(alb, members, weighted):
+    st, msg = _create_set(alb, members, weighted)
+    assert st == alb.ALB_E_INVAL, msg
+    assert "member" in msg or "weight" in msg
+
+
+def test_graph_set_rejects_empty_and_null(alb):
+    h = ctypes.c_void_p()
+    assert alb._lib.alb_graph_create_set(0, None, None, None, None, None, ctypes.byref(h)) == alb.ALB_E_INVAL
+    assert alb._lib.alb_graph_create_set(1, None, None, None, None, None, None) == alb.ALB_E_INVAL
+    assert alb._lib.alb_graph_members(None, None) == alb.ALB_E_INVAL
+    assert alb._lib.alb_graph_member_info(None, 0, None, None, None) == alb.ALB_E_INVAL
+
+
+def test_batch_calls_reject_null_handles(alb):
+    mb = np.zeros(1, np.int32)
+    st = alb.Stats()
+    for fn in (alb._lib.alb_bfs_batch, alb._lib.alb_sssp_batch):
+        assert fn(None, 1, mb.ctypes.data, mb.ctypes.data, mb.ctypes.data, None, None, ctypes.byref(st)) == \
+            alb.ALB_E_INVAL
+        assert st.rounds == 0
+
+
 def test_status_strings(alb):
     for s, name in [(0, "ALB_OK"), (-1, "ALB_E_INVAL"), (-5, "ALB_E_OVERFLOW"), (-6, "ALB_E_UNSUPPORTED")]:
         assert alb._lib.alb_status_str(s).decode() == name
