@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also sweep the threshold over powers of two")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-alb", action="store_true", help="skip the TWC-only comparison (profiling runs)")
+    ap.add_argument("--workload", default="sssp_rmat22", choices=["sssp_rmat22", "batch"],
+                    help="batch: 256 SSSP queries over 64 RMAT graphs of scales 12..20 in one launch, "
+                         "against the same queries one launch each")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -98,6 +101,9 @@ def main():
 
     import graphgen as gg
     from paper_1911_09135_amd import alb
+
+    if args.workload == "batch":
+        return bench_batch(args, alb, gg)
 
     t = time.perf_counter()
     g = gg.workload("rmat22w")
@@ -194,6 +200,97 @@ def main():
     if sweep is not None:
         res["threshold_sweep_gteps"] = sweep
     dg.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_batch(args, alb, gg):
+    """256 SSSP queries (query i on graph i mod 64, a random source of
+    out-degree > 0) over 64 weighted RMAT graphs of scales drawn from 12..20,
+    all resident in HBM.  A step runs every query once: batched = one
+    alb_sssp_batch launch on the graph set; one-at-a-time = 256 alb_sssp calls
+    on the graphs' own handles.  Reported: queries/s of the batched step and
+    per-query latency percentiles of both."""
+    import numpy as np
+    import torch
+
+    t = time.perf_counter()
+    graphs = gg.rmat_set(64, 12, 20, seed=7)
+    members, sources = gg.query_sources(graphs, 256, seed=8)
+    log("64 graphs, %d edges in all, generated in %.1fs" % (sum(g.m for g in graphs), time.perf_counter() - t))
+    gset = alb.GraphSet(graphs)
+    handles = [alb.Graph(g.off, g.col, g.w) for g in graphs]
+    outs = [torch.empty(graphs[int(m)].n, dtype=torch.int32, device="cuda") for m in members]
+    single_outs = [torch.empty_like(o) for o in outs]
+    q = len(members)
+    edges = int(sum(graphs[int(m)].m for m in members))  # TEPS over each query's whole graph
+
+    def batched():
+        return alb.sssp_batch(gset, members, sources, outs=outs)[1]
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    step_s = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        st = batched()
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
+    sec = time.perf_counter() - t0
+    log("batched: %.3f ms/step, %d rounds, kernel %.3f ms" % (1e3 * sec / args.steps, st["rounds"], st["kernel_ms"]))
+
+    def one_at_a_time(lat):
+        for i in range(q):
+            ts = time.perf_counter()
+            alb.sssp(handles[int(members[i])], int(sources[i]), out=single_outs[i])
+            torch.cuda.synchronize()
+            if lat is not None:
+                lat.append(time.perf_counter() - ts)
+
+    for _ in range(args.warmup):
+        one_at_a_time(None)
+    lat1 = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_at_a_time(lat1)
+    sec1 = time.perf_counter() - t0
+    log("one at a time: %.3f ms/step" % (1e3 * sec1 / args.steps))
+    same = all(bool(torch.equal(a, b)) for a, b in zip(outs, single_outs))
+
+    def pct(xs, p):
+        return round(1e3 * float(np.percentile(np.asarray(xs), p)), 3)
+
+    value = args.steps * q / sec
+    res = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "sssp_batch_256q_64rmat_s12-20_ef16_w1-100", "queries": q, "graphs": len(graphs),
+                   "vertices": int(sum(g.n for g in graphs)), "edges": int(sum(g.m for g in graphs)),
+                   "rounds": st["rounds"], "launched_threads": st["launched_threads"],
+                   "huge_threshold": st["huge_threshold"]},
+        "gteps": round(args.steps * edges / sec / 1e9, 3),
+        "latency_ms": {"p50": pct(step_s, 50), "p99": pct(step_s, 99)},
+        "one_at_a_time": {"value": round(args.steps * q / sec1, 1), "unit": "queries/s",
+                          "gteps": round(args.steps * edges / sec1 / 1e9, 3),
+                          "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99)}, "same_result": same},
+        "speedup_vs_one_at_a_time": round(sec1 / sec, 2),
+        "batch_stats": {k: st[k] for k in ("frontier_vertices", "edges_examined", "huge_vertices", "huge_edges",
+                                             "pushes", "kernel_ms")},
+    }
+    for h in handles:
+        h.close()
+    gset.close()
     print(json.dumps(res), flush=True)
 
 

@@ -301,3 +301,50 @@ def workload(name: str) -> Graph:
     g.name = name
     _cache[name] = g
     return g
+
+
+# --------------------------------------------------------------------------
+# Query workloads: many graphs and many sources.
+# --------------------------------------------------------------------------
+
+def rmat_set(count: int = 64, lo: int = 12, hi: int = 20, seed: int = 7, edge_factor: int = 16,
+             weighted: bool = True) -> list:
+    """`count` RMAT graphs whose scales are drawn uniformly from lo..hi
+    (stream `seed`); graph i uses RMAT seed 100 + i and, if weighted, weights
+    U[1,100] with seed 1000 + i."""
+    scales = uniform_ints(count, hi - lo + 1, seed) + lo
+    out = []
+    for i, s in enumerate(scales):
+        g = rmat(int(s), edge_factor, seed=100 + i)
+        if weighted:
+            g = g.with_weights(1000 + i, 1, 100)
+        out.append(g)
+    return out
+
+
+def query_sources(graphs: list, count: int, seed: int = 8):
+    """`count` queries, query i on graph i mod len(graphs), each with a source
+    of out-degree > 0 drawn uniformly; the sources on one graph are distinct
+    while the graph has enough such vertices.  Returns (graph index, source)
+    arrays."""
+    k = len(graphs)
+    members = np.arange(count, dtype=np.int32) % k
+    sources = np.zeros(count, np.int32)
+    for gi in range(k):
+        qs = np.nonzero(members == gi)[0]
+        if not len(qs):
+            continue
+        nz = np.nonzero(graphs[gi].degrees() > 0)[0].astype(np.int32)
+        if not len(nz):
+            nz = np.zeros(1, np.int32)
+        picked, stream = [], 0
+        while len(picked) < len(qs):
+            for x in uniform_ints(4 * len(qs), len(nz), seed, stream=gi + k * stream):
+                v = int(nz[x])
+                if v not in picked or len(picked) >= len(nz):
+                    picked.append(v)
+                if len(picked) == len(qs):
+                    break
+            stream += 1
+        sources[qs] = picked
+    return members, sources

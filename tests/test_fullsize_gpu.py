@@ -105,3 +105,37 @@ def test_pagerank_zipf24_full(alb, zipf24):
         assert np.array_equal(x, x0)
         log("pagerank %s ok: L1 %.2e, %.2f ms" % (c, err, st["device_ms"]))
     dg.close()
+
+
+def test_sssp_batch_rmat_set_full(alb):
+    """The batch workload: 256 SSSP queries over 64 weighted RMAT graphs of
+    scales 12..20 in one launch (device outputs, as bench.py times it).  32
+    queries, spread over every scale, against Dijkstra on their graph alone;
+    every query against the single-query call."""
+    import torch
+
+    t = time.time()
+    graphs = gg.rmat_set(64, 12, 20, seed=7)
+    members, sources = gg.query_sources(graphs, 256, seed=8)
+    log("64 graphs generated in %.1fs: m=%d" % (time.time() - t, sum(g.m for g in graphs)))
+    gs = alb.GraphSet(graphs)
+    outs = [torch.empty(graphs[int(m)].n, dtype=torch.int32, device="cuda") for m in members]
+    _, st = alb.sssp_batch(gs, members, sources, outs=outs)
+    torch.cuda.synchronize()
+    log("batch: %d rounds, kernel %.2f ms" % (st["rounds"], st["kernel_ms"]))
+    by_scale = {}
+    for q, m in enumerate(members):
+        by_scale.setdefault(graphs[int(m)].n, []).append(q)
+    sample = sorted({qs[k] for qs in by_scale.values() for k in range(min(4, len(qs)))})
+    for q in sample:
+        g = graphs[int(members[q])]
+        ref = oracle.sssp(g, int(sources[q]))
+        assert np.array_equal(outs[q].cpu().numpy(), ref), ("query", q, g.n)
+    log("%d sampled queries equal Dijkstra" % len(sample))
+    for gi, g in enumerate(graphs):
+        dg = alb.Graph(g.off, g.col, g.w)
+        for q in np.nonzero(members == gi)[0]:
+            d, _ = alb.sssp(dg, int(sources[q]))
+            assert np.array_equal(d, outs[q].cpu().numpy()), ("query", int(q))
+        dg.close()
+    gs.close()
