@@ -74,9 +74,13 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also sweep the threshold over powers of two")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-alb", action="store_true", help="skip the TWC-only comparison (profiling runs)")
-    ap.add_argument("--workload", default="sssp_rmat22", choices=["sssp_rmat22", "batch"],
+    ap.add_argument("--workload", default="sssp_rmat22", choices=["sssp_rmat22", "batch", "serve"],
                     help="batch: 256 SSSP queries over 64 RMAT graphs of scales 12..20 in one launch, "
-                         "against the same queries one launch each")
+                         "against the same queries one launch each; serve: Poisson streams of BFS/SSSP "
+                         "requests over 32 graphs through the serving loop")
+    ap.add_argument("--requests", type=int, default=5000, help="serve: requests per arrival rate")
+    ap.add_argument("--rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates per second")
+    ap.add_argument("--tune", action="store_true", help="batch: also run with autotuned settings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -104,6 +108,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args, alb, gg)
+    if args.workload == "serve":
+        return bench_serve(args, alb, gg)
 
     t = time.perf_counter()
     g = gg.workload("rmat22w")
@@ -290,6 +296,162 @@ def bench_batch(args, alb, gg):
     }
     for h in handles:
         h.close()
+    gset.close()
+    print(json.dumps(res), flush=True)
+
+
+class _BufferPool:
+    """Reusable pinned host result arrays per graph, so that allocation and
+    page faults do not land in the measured latency."""
+
+    def __init__(self, sizes):
+        import threading
+
+        import torch
+
+        self.torch = torch
+        self.sizes = sizes
+        self.free = {i: [] for i in range(len(sizes))}
+        self.lock = threading.Lock()
+
+    def get(self, m):
+        with self.lock:
+            if self.free[m]:
+                return self.free[m].pop()
+        # pinned (page-locked) memory: the device copies results at full speed
+        a = self.torch.zeros(self.sizes[m], dtype=self.torch.int32, pin_memory=True).numpy()
+        return a
+
+    def put(self, m, a):
+        with self.lock:
+            self.free[m].append(a)
+
+
+def serve_run(alb, srv, pool, reqs, arrivals):
+    """Submit reqs[i] at arrivals[i] seconds (None: all at once); returns
+    (achieved queries/s, latencies ms, batch sizes, failures)."""
+    import threading
+
+    import numpy as np
+
+    tickets = [None] * len(reqs)
+    ready = threading.Semaphore(0)
+    lat, sizes, fails = [], [], [0]
+    done_t = [0.0]
+
+    def waiter():
+        for i in range(len(reqs)):
+            ready.acquire()
+            t, buf, m = tickets[i]
+            try:
+                _, info = srv.wait(t)
+                lat.append(info["latency_ms"])
+                sizes.append(info["batch_size"])
+            except alb.AlbError:
+                fails[0] += 1
+            pool.put(m, buf)
+        done_t[0] = time.perf_counter()
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i, (a, m, s) in enumerate(reqs):
+        if arrivals is not None:
+            target = t0 + arrivals[i]
+            while True:
+                dt = target - time.perf_counter()
+                if dt <= 0:
+                    break
+                if dt > 2e-3:
+                    time.sleep(dt - 1e-3)
+        buf = pool.get(m)
+        tickets[i] = (srv.submit(a, m, s, out=buf), buf, m)
+        ready.release()
+    th.join()
+    return len(reqs) / (done_t[0] - t0), np.asarray(lat), np.asarray(sizes), fails[0]
+
+
+def bench_serve(args, alb, gg):
+    """Serving: 32 device-resident graphs (30 RMAT of scales 14..22 and Zipf
+    graphs of 2^20 and 2^23 vertices, weights U[1,100]); requests BFS:SSSP
+    1:1, graph uniform, source uniform over vertices with out-edges.  For each
+    arrival rate a Poisson stream goes through the serving loop (2 lanes,
+    batches up to 256) and, with fewer requests, through the same loop with
+    one request per batch on one lane (one launch per query).  Latency runs
+    from submit to the result in host memory.  `value` is the batched loop's
+    throughput with every request queued at once (its capacity)."""
+    import numpy as np
+
+    t = time.perf_counter()
+    graphs = gg.serving_set()
+    log("32 graphs, %d edges in all, generated in %.1fs" % (sum(g.m for g in graphs), time.perf_counter() - t))
+    gset = alb.GraphSet(graphs)
+    pool = _BufferPool([g.n for g in graphs])
+    nz = [np.nonzero(g.degrees() > 0)[0] for g in graphs]
+
+    def make_requests(count, seed):
+        algo = gg.uniform_ints(count, 2, seed, stream=1)
+        gi = gg.uniform_ints(count, len(graphs), seed, stream=2)
+        u = gg.uniform_doubles(count, seed, stream=3)
+        return [("bfs" if algo[i] == 0 else "sssp", int(gi[i]), int(nz[gi[i]][int(u[i] * len(nz[gi[i]]))]))
+                for i in range(count)]
+
+    def pct(x, p):
+        return round(float(np.percentile(x, p)), 3) if len(x) else None
+
+    batched = alb.Server(gset, lanes=2, max_batch=256, hbm_budget=32 << 30)
+    single = alb.Server(gset, lanes=1, max_batch=1, hbm_budget=32 << 30)
+    warm = make_requests(200, 99)
+    serve_run(alb, batched, pool, warm, None)
+    serve_run(alb, single, pool, warm[:50], None)
+
+    reqs = make_requests(args.requests, 9)
+    cap, lat, sizes, f = serve_run(alb, batched, pool, reqs, None)
+    log("batched capacity: %.0f queries/s, p50 %.1f ms, p99 %.1f ms, mean batch %.1f" % (
+        cap, pct(lat, 50), pct(lat, 99), sizes.mean()))
+    n1 = min(args.requests, 2000)
+    cap1, lat1, _, f1 = serve_run(alb, single, pool, reqs[:n1], None)
+    log("one-at-a-time capacity: %.0f queries/s" % cap1)
+    rates = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        arr = gg.poisson_arrivals(rate, args.requests, seed=9)
+        r = make_requests(args.requests, 10 + int(rate))
+        thr, l, sz, fb = serve_run(alb, batched, pool, r, arr)
+        m1 = min(args.requests, max(200, int(rate * 10)), 2000)
+        thr1, l1, _, fs = serve_run(alb, single, pool, r[:m1], arr[:m1])
+        rates.append({"rate": rate, "requests": len(r), "achieved": round(thr, 1), "p50_ms": pct(l, 50),
+                      "p99_ms": pct(l, 99), "mean_batch": round(float(sz.mean()), 2), "failed": fb,
+                      "one_at_a_time": {"requests": m1, "achieved": round(thr1, 1), "p50_ms": pct(l1, 50),
+                                        "p99_ms": pct(l1, 99), "failed": fs}})
+        log("rate %6.0f/s: batched %.0f/s p50 %.2f p99 %.2f ms (batch %.1f); one-at-a-time %.0f/s p50 %.2f p99 %.2f" % (
+            rate, thr, pct(l, 50), pct(l, 99), sz.mean(), thr1, pct(l1, 50), pct(l1, 99)))
+    st = batched.stats()
+    batched.close()
+    single.close()
+    res = {
+        "metric": METRIC,
+        "value": round(cap, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": len(warm),
+        "ms_per_step": round(1e3 / cap, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "serve_bfs_sssp_32graphs_rmat14-22_zipf20_zipf23", "graphs": len(graphs),
+                   "vertices": int(sum(g.n for g in graphs)), "edges": int(sum(g.m for g in graphs)),
+                   "lanes": 2, "max_batch": 256},
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "mean_batch": round(float(sizes.mean()), 2),
+        "failed": f,
+        "one_at_a_time": {"value": round(cap1, 1), "unit": "queries/s", "requests": n1,
+                          "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99)}, "failed": f1},
+        "poisson": rates,
+        "server_stats": st,
+    }
     gset.close()
     print(json.dumps(res), flush=True)
 

@@ -348,3 +348,25 @@ def query_sources(graphs: list, count: int, seed: int = 8):
             stream += 1
         sources[qs] = picked
     return members, sources
+
+
+def serving_set(weighted: bool = True) -> list:
+    """32 graphs for a serving workload: 30 RMAT graphs of scale 14 + (i mod 9)
+    (RMAT seed 200 + i) and Zipf(1.9) out-degree graphs with 2^20 and 2^23
+    vertices (degrees capped at n / 4, seeds 230, 231); weights U[1,100]
+    with seed 2000 + i."""
+    out = []
+    for i in range(30):
+        out.append(rmat(14 + i % 9, 16, seed=200 + i))
+    out.append(zipf(1 << 20, 1.9, 1 << 18, seed=230))
+    out.append(zipf(1 << 23, 1.9, 1 << 21, seed=231))
+    if weighted:
+        out = [g.with_weights(2000 + i, 1, 100) for i, g in enumerate(out)]
+    return out
+
+
+def poisson_arrivals(rate: float, count: int, seed: int = 9) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of `rate` per
+    second: cumulative sums of exponential gaps -log(1 - U) / rate."""
+    u = uniform_doubles(count, seed, stream=int(rate))
+    return np.cumsum(-np.log1p(-u) / rate)

@@ -48,7 +48,9 @@ typedef enum {
   ALB_E_DEVICE = -3,      /* HIP runtime error, no usable GPU, or a device-side abort */
   ALB_E_RANGE = -4,       /* a shortest-path distance could exceed INT32_MAX - 1 */
   ALB_E_OVERFLOW = -5,    /* a device worklist exceeded its capacity */
-  ALB_E_UNSUPPORTED = -6  /* option value not implemented */
+  ALB_E_UNSUPPORTED = -6, /* option value not implemented */
+  ALB_E_TIMEOUT = -7,     /* served request: its deadline passed before it was dispatched */
+  ALB_E_CANCELLED = -8    /* served request: cancelled before it was dispatched */
 } alb_status;
 
 /* Which vertices take the cyclic (Algorithm 2) path.
@@ -190,6 +192,138 @@ alb_status alb_bfs_batch(alb_graph g, int32_t count, const int32_t *members, con
                          int32_t *const *levels, const int64_t *thresholds, const alb_options *opt, alb_stats *stats);
 alb_status alb_sssp_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
                           int32_t *const *dists, const int64_t *thresholds, const alb_options *opt, alb_stats *stats);
+
+/* Traversals that batches, plans and the autotuner accept. */
+typedef enum { ALB_ALGO_BFS = 0, ALB_ALGO_SSSP = 1 } alb_algo;
+
+/* Batch plans: a batch laid out once -- per-query tables uploaded, its own
+ * workspace allocated -- and its device work (label initialisation, the
+ * persistent launch, the output kernel, the control-block read-back) captured
+ * into a HIP graph that every alb_batch_plan_run replays on options.stream
+ * (the library's stream if NULL).  For batches that recur with the same
+ * queries; arguments as for alb_bfs_batch / alb_sssp_batch, and `outs` must
+ * stay valid for the plan's life.  A run blocks until its results are in
+ * `outs`; runs of one plan are serialised.  stats->kernel_ms equals
+ * device_ms (the whole graph).  Destroy every plan before its graph
+ * (alb_graph_destroy refuses with ALB_E_INVAL while plans exist). */
+typedef struct alb_plan_s *alb_plan;
+alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                                 const int32_t *sources, int32_t *const *outs, const int64_t *thresholds,
+                                 const alb_options *opt, alb_plan *out);
+alb_status alb_batch_plan_run(alb_plan p, alb_stats *stats);
+alb_status alb_batch_plan_destroy(alb_plan p);
+
+/* Autotuner (not part of the paper's method; its threshold study, Section 5,
+ * motivates the search space).  Times BFS or SSSP batches of the given
+ * sources (1..64) on member `member` of g under candidate settings --
+ * workgroup size 256 or 1024, huge threshold 64 or 2^8, 2^10, 2^12, 2^14
+ * (the paper found thresholds across 2^8..2^18 to perform alike), then three
+ * TWC cutoff pairs at the winner -- and returns *base with the fastest in
+ * *tuned (and its median device time in *best_ms, if not NULL).  Results are
+ * cached per process by the member's degree distribution (vertex, edge and
+ * largest-degree orders of magnitude and the share of edges per power-of-two
+ * degree class), so graphs that look alike are tuned once.  The outputs of the
+ * timed runs are discarded. */
+alb_status alb_autotune(alb_graph g, int32_t algo, int32_t member, int32_t nsources, const int32_t *sources,
+                        const alb_options *base, alb_options *tuned, double *best_ms);
+
+/* Autotuner for a batch: tunes every member the batch uses (at most 4 of its
+ * sources each, cached as above), then picks the one workgroup size with the
+ * smallest total estimated time and returns it in *tuned and each query's best
+ * threshold at that size in thresholds[count], ready for the batch calls. */
+alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                              const int32_t *sources, const alb_options *base, alb_options *tuned,
+                              int64_t *thresholds);
+
+/* Forget every cached tuning result. */
+alb_status alb_autotune_reset(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving (not part of the paper): a request loop over one graph set.
+ *
+ * Requests (BFS or SSSP from one source on one member) are queued on submit.
+ * `lanes` dispatcher threads each take, whenever they are free, the oldest
+ * pending request's algorithm and every pending request of that algorithm
+ * in arrival order that fits -- at most max_batch queries whose workspaces
+ * (44 bytes per vertex of the query's member, plus 64) sum to at most
+ * hbm_budget / lanes -- and run them as one batch (alb_bfs_batch /
+ * alb_sssp_batch) on the lane's own stream with 1/lanes of the device's
+ * workgroups.  So requests that arrive while batches are running join the
+ * next batch of the first lane to free up, and the lanes' batches overlap
+ * on the device.  Results land in the caller's host array; a request's
+ * latency runs from submit to that array being filled.
+ * ------------------------------------------------------------------------- */
+typedef struct alb_server_s *alb_server;
+
+/* A replacement for the device (for testing the scheduling policy, or to run
+ * another engine): runs one batch synchronously and returns its status.
+ * outs[q] are the requests' host arrays. */
+typedef int32_t (*alb_exec_fn)(void *user, int32_t algo, int32_t count, const int32_t *members,
+                               const int32_t *sources, int32_t *const *outs, int32_t lane);
+
+typedef struct {
+  uint32_t struct_size;      /* sizeof(alb_server_config); set by alb_server_config_init */
+  int32_t lanes;             /* batches in flight at once (1..16); 0 = 2 */
+  int32_t max_batch;         /* queries per batch (1..65535); 0 = 256 */
+  int32_t max_wait_us;       /* a free lane with fewer than max_batch pending waits up to this long for more */
+  int64_t hbm_budget;        /* bytes of batch workspaces over all lanes; 0 = 8 GiB */
+  alb_options options;       /* balancer options of every batch (stream, grid_wgs and out_on_device are set
+                                per lane) */
+  alb_exec_fn executor;      /* NULL = the GPU */
+  void *executor_user;
+  int32_t n_members;         /* with a custom executor and no graph: member count ... */
+  const int32_t *member_vertices; /* ... and each member's vertex count (copied) */
+  int32_t reserved[8];
+} alb_server_config;
+
+typedef struct {
+  int32_t status;     /* ALB_OK, the batch's error, ALB_E_TIMEOUT or ALB_E_CANCELLED */
+  int32_t batch_size; /* requests in its batch (0 if never dispatched) */
+  int32_t lane;       /* lane that ran it (-1 if never dispatched) */
+  int32_t algo;
+  double queue_ms;    /* submit to dispatch */
+  double latency_ms;  /* submit to completion */
+} alb_request_info;
+
+typedef struct {
+  int64_t submitted, completed, failed, timed_out, cancelled, rejected, batches;
+  int64_t pending, running;  /* now */
+  double busy_ms;            /* summed over lanes: time spent running batches */
+} alb_server_stats;
+
+alb_status alb_server_config_init(alb_server_config *cfg);
+
+/* Start a server on graph g (a graph set or a plain graph).  g may be NULL
+ * only with a custom executor and member_vertices.  The graph must outlive
+ * the server. */
+alb_status alb_server_create(alb_graph g, const alb_server_config *cfg, alb_server *out);
+
+/* Queue one request: `algo` (alb_algo) from local vertex `source` of member
+ * `member`; `out` is a host array of that member's vertex count, owned by the
+ * caller and written when the request completes.  timeout_ms > 0: if the
+ * request is still queued that long after submit, it completes with
+ * ALB_E_TIMEOUT.  Returns the ticket in *ticket.  ALB_E_NOMEM if the request
+ * alone exceeds a lane's share of hbm_budget (admission rejection),
+ * ALB_E_INVAL for bad arguments or a stopped server. */
+alb_status alb_server_submit(alb_server s, int32_t algo, int32_t member, int32_t source, int32_t *out,
+                             double timeout_ms, uint64_t *ticket);
+
+/* Block until request `ticket` completes; returns its status and, if info is
+ * not NULL, its record.  Each ticket can be waited for once (ALB_E_INVAL after). */
+alb_status alb_server_wait(alb_server s, uint64_t ticket, alb_request_info *info);
+
+/* Cancel a request that is still queued (ALB_E_INVAL once dispatched). */
+alb_status alb_server_cancel(alb_server s, uint64_t ticket);
+
+/* Block until no request is queued or running. */
+alb_status alb_server_drain(alb_server s);
+
+alb_status alb_server_stats_get(alb_server s, alb_server_stats *st);
+
+/* Stop accepting requests, run what is queued, join the lanes, free.  NULL is
+ * a no-op.  Records of completed requests that were never waited for are
+ * dropped. */
+alb_status alb_server_destroy(alb_server s);
 
 /* One round of the balancer on an explicit frontier, with an operator that
  * records instead of updating labels (for checking the distribution).  Host

@@ -23,6 +23,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+ALB_E_TIMEOUT, ALB_E_CANCELLED = -7, -8
 ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC = 1, 2
 # 4 * wg_size; the launched thread count (the paper's rule); 64 in rounds smaller than the grid, else default
 THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED, THRESHOLD_ADAPTIVE = -1, -2, -3
@@ -30,6 +31,7 @@ MODES = {"alb": 0, "twc": 1, "twc_only": 1, "lb_all": 2}
 LAUNCHES = {"auto": 0, "host": 1, "host_loop": 1, "persistent": 2}
 INF = np.iinfo(np.int32).max
 BIN_THREAD, BIN_WAVE, BIN_WG, BIN_HUGE = 0, 1, 2, 3
+ALGOS = {"bfs": 0, "sssp": 1}
 
 
 class Options(ctypes.Structure):
@@ -71,6 +73,44 @@ class Stats(ctypes.Structure):
 
 
 _vp, _i32, _i64, _u32, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float
+
+# int32 (*)(void *user, int32 algo, int32 count, const int32 *members, const int32 *sources, int32 *const *outs,
+#           int32 lane)
+EXEC_FN = ctypes.CFUNCTYPE(_i32, _vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                           ctypes.POINTER(ctypes.POINTER(_i32)), _i32)
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("lanes", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("max_wait_us", ctypes.c_int32),
+        ("hbm_budget", ctypes.c_int64),
+        ("options", Options),
+        ("executor", EXEC_FN),
+        ("executor_user", ctypes.c_void_p),
+        ("n_members", ctypes.c_int32),
+        ("member_vertices", ctypes.POINTER(ctypes.c_int32)),
+        ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("batch_size", ctypes.c_int32),
+        ("lane", ctypes.c_int32),
+        ("algo", ctypes.c_int32),
+        ("queue_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "timed_out", "cancelled",
+                                              "rejected", "batches", "pending", "running")] + \
+               [("busy_ms", ctypes.c_double)]
 _POpt, _PSt = ctypes.POINTER(Options), ctypes.POINTER(Stats)
 _sig = {
     "alb_options_init": ([_POpt], ctypes.c_int),
@@ -88,6 +128,21 @@ _sig = {
                               ctypes.c_int),
     "alb_bfs_batch": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_sssp_batch": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_batch_plan_create": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp, _POpt, ctypes.POINTER(_vp)], ctypes.c_int),
+    "alb_batch_plan_run": ([_vp, _PSt], ctypes.c_int),
+    "alb_batch_plan_destroy": ([_vp], ctypes.c_int),
+    "alb_autotune": ([_vp, _i32, _i32, _i32, _vp, _POpt, _POpt, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "alb_autotune_batch": ([_vp, _i32, _i32, _vp, _vp, _POpt, _POpt, _vp], ctypes.c_int),
+    "alb_autotune_reset": ([], ctypes.c_int),
+    "alb_server_config_init": ([ctypes.POINTER(ServerConfig)], ctypes.c_int),
+    "alb_server_create": ([_vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)], ctypes.c_int),
+    "alb_server_submit": ([_vp, _i32, _i32, _i32, _vp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)],
+                          ctypes.c_int),
+    "alb_server_wait": ([_vp, ctypes.c_uint64, ctypes.POINTER(RequestInfo)], ctypes.c_int),
+    "alb_server_cancel": ([_vp, ctypes.c_uint64], ctypes.c_int),
+    "alb_server_drain": ([_vp], ctypes.c_int),
+    "alb_server_stats_get": ([_vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
+    "alb_server_destroy": ([_vp], ctypes.c_int),
     "alb_trace_round": ([_vp, _vp, _i64, _POpt, _vp, _vp, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp,
                          ctypes.POINTER(_i64), _PSt], ctypes.c_int),
     "alb_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -254,27 +309,7 @@ def _run_batch(fn, gs: GraphSet, members, sources, thresholds, outs, opts: dict)
     if members.shape != sources.shape or members.ndim != 1:
         raise ValueError("members and sources must be 1-D of one length")
     q = members.shape[0]
-    dev = False
-    # a member id out of range is left for the library to report
-    size = [gs.members[int(mb)][0] if 0 <= mb < len(gs.members) else 1 for mb in members]
-    if outs is None:
-        outs = [np.empty(n, np.int32) for n in size]
-        ptrs = [o.ctypes.data for o in outs]
-    else:
-        outs = list(outs)
-        if len(outs) != q:
-            raise ValueError("one output per query")
-        dev = not isinstance(outs[0], np.ndarray)
-        ptrs = []
-        for o, n in zip(outs, size):
-            if dev:
-                if not o.is_cuda or not o.is_contiguous() or o.numel() != n or o.dtype.itemsize != 4:
-                    raise ValueError("device outputs must be contiguous 32-bit CUDA tensors of the member's n")
-                ptrs.append(o.data_ptr())
-            else:
-                if o.dtype != np.int32 or o.shape != (n,) or not o.flags.c_contiguous:
-                    raise ValueError("host outputs must be contiguous int32 arrays of the member's n")
-                ptrs.append(o.ctypes.data)
+    outs, ptrs, dev = _batch_outputs(gs, members, outs)
     if dev and opts.get("stream") is None:
         import torch
 
@@ -290,6 +325,113 @@ def _run_batch(fn, gs: GraphSet, members, sources, thresholds, outs, opts: dict)
     return outs, st.as_dict()
 
 
+def _batch_outputs(gs: GraphSet, members, outs):
+    """(outs, pointer list, on_device) for a batch's per-query outputs."""
+    size = [gs.members[int(mb)][0] if 0 <= mb < len(gs.members) else 1 for mb in members]
+    if outs is None:
+        outs = [np.empty(n, np.int32) for n in size]
+        return outs, [o.ctypes.data for o in outs], False
+    outs = list(outs)
+    if len(outs) != len(size):
+        raise ValueError("one output per query")
+    dev = not isinstance(outs[0], np.ndarray)
+    ptrs = []
+    for o, n in zip(outs, size):
+        if dev:
+            if not o.is_cuda or not o.is_contiguous() or o.numel() != n or o.dtype.itemsize != 4:
+                raise ValueError("device outputs must be contiguous 32-bit CUDA tensors of the member's n")
+            ptrs.append(o.data_ptr())
+        else:
+            if o.dtype != np.int32 or o.shape != (n,) or not o.flags.c_contiguous:
+                raise ValueError("host outputs must be contiguous int32 arrays of the member's n")
+            ptrs.append(o.ctypes.data)
+    return outs, ptrs, dev
+
+
+class BatchPlan:
+    """A batch captured once into a HIP graph and replayed by run()
+    (alb_batch_plan_create).  Outputs stay bound to the plan."""
+
+    def __init__(self, gs: GraphSet, algo: str, members, sources, thresholds=None, outs=None, **opts):
+        members = np.ascontiguousarray(members, np.int32)
+        sources = np.ascontiguousarray(sources, np.int32)
+        if members.shape != sources.shape or members.ndim != 1:
+            raise ValueError("members and sources must be 1-D of one length")
+        self.outs, ptrs, dev = _batch_outputs(gs, members, outs)
+        if dev and opts.get("stream") is None:
+            import torch
+
+            opts = dict(opts, stream=torch.cuda.current_stream())
+        thr = None if thresholds is None else np.ascontiguousarray(thresholds, np.int64)
+        self._ptrs = (_vp * max(len(ptrs), 1))(*ptrs)
+        o = make_options(out_on_device=dev, **opts)
+        h = _vp()
+        _check(_lib.alb_batch_plan_create(gs.handle, ALGOS[algo], members.shape[0], members.ctypes.data,
+                                          sources.ctypes.data, ctypes.cast(self._ptrs, _vp),
+                                          None if thr is None else thr.ctypes.data, ctypes.byref(o),
+                                          ctypes.byref(h)), "alb_batch_plan_create")
+        self._h = h
+        self._gs = gs  # the graph must outlive the plan
+
+    def run(self):
+        """Replay the batch; returns (outputs, stats)."""
+        if self._h is None:
+            raise ValueError("plan is closed")
+        st = Stats()
+        _check(_lib.alb_batch_plan_run(self._h, ctypes.byref(st)), "alb_batch_plan_run")
+        return self.outs, st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.alb_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts_dict(o: Options) -> dict:
+    thr = o.huge_threshold
+    return {"threshold": None if thr == THRESHOLD_DEFAULT else thr, "wg_size": o.wg_size,
+            "wave_cutoff": o.wave_cutoff, "wg_cutoff": o.wg_cutoff}
+
+
+def autotune(g: Graph, algo: str, sources, member: int = 0, **opts):
+    """Fastest settings for `algo` on graph g (or member `member` of a set),
+    timed on the given sources.  Returns (options dict for the traversal
+    calls, median ms of the winner)."""
+    src = np.ascontiguousarray(sources, np.int32)
+    base = make_options(**opts)
+    tuned = Options()
+    ms = ctypes.c_double()
+    _check(_lib.alb_autotune(g.handle, ALGOS[algo], int(member), src.shape[0], src.ctypes.data, ctypes.byref(base),
+                             ctypes.byref(tuned), ctypes.byref(ms)), "alb_autotune")
+    return _opts_dict(tuned), ms.value
+
+
+def autotune_batch(gs: GraphSet, algo: str, members, sources, **opts):
+    """Launch-wide settings and per-query thresholds for a batch.  Returns
+    (options dict, thresholds array) for bfs_batch / sssp_batch."""
+    members = np.ascontiguousarray(members, np.int32)
+    sources = np.ascontiguousarray(sources, np.int32)
+    base = make_options(**opts)
+    tuned = Options()
+    thr = np.zeros(members.shape[0], np.int64)
+    _check(_lib.alb_autotune_batch(gs.handle, ALGOS[algo], members.shape[0], members.ctypes.data,
+                                   sources.ctypes.data, ctypes.byref(base), ctypes.byref(tuned), thr.ctypes.data),
+           "alb_autotune_batch")
+    d = _opts_dict(tuned)
+    d.pop("threshold")
+    return d, thr
+
+
+def autotune_reset():
+    _check(_lib.alb_autotune_reset(), "alb_autotune_reset")
+
+
 def bfs_batch(gs: GraphSet, members, sources, thresholds=None, outs=None, **opts):
     """Query q: BFS levels of member members[q] from its vertex sources[q].
     Returns (list of per-query level arrays, stats), all queries in one launch."""
@@ -299,6 +441,103 @@ def bfs_batch(gs: GraphSet, members, sources, thresholds=None, outs=None, **opts
 def sssp_batch(gs: GraphSet, members, sources, thresholds=None, outs=None, **opts):
     """Query q: SSSP distances of member members[q] from its vertex sources[q]."""
     return _run_batch(_lib.alb_sssp_batch, gs, members, sources, thresholds, outs, opts)
+
+
+class Server:
+    """Request loop over a graph set (alb_server_create).  submit() queues a
+    BFS / SSSP request and returns its ticket; wait(ticket) blocks until the
+    result is in the request's host array.
+
+    `executor(algo, members, sources, outs, lane) -> status` replaces the
+    device (outs are the requests' numpy arrays); it needs `member_vertices`
+    when no graph set is given."""
+
+    def __init__(self, gs: Optional[GraphSet] = None, lanes: int = 2, max_batch: int = 256, max_wait_us: int = 0,
+                 hbm_budget: int = 0, executor=None, member_vertices=None, **opts):
+        cfg = ServerConfig()
+        _check(_lib.alb_server_config_init(ctypes.byref(cfg)), "alb_server_config_init")
+        cfg.lanes, cfg.max_batch, cfg.max_wait_us, cfg.hbm_budget = lanes, max_batch, max_wait_us, hbm_budget
+        cfg.options = make_options(**opts)
+        if gs is not None:
+            self.member_n = [m[0] for m in gs.members]
+        else:
+            self.member_n = [int(x) for x in (member_vertices if member_vertices is not None else [])]
+        self._mv = np.ascontiguousarray(self.member_n, np.int32)
+        if executor is not None:
+            member_n = self.member_n
+
+            def trampoline(user, algo, count, members, sources, outs, lane):
+                try:
+                    mb = [members[i] for i in range(count)]
+                    src = [sources[i] for i in range(count)]
+                    arrs = [np.ctypeslib.as_array(outs[i], shape=(member_n[mb[i]],)) for i in range(count)]
+                    return int(executor(algo, mb, src, arrs, lane))
+                except Exception:  # an exception cannot cross the C boundary
+                    return ALB_E_DEVICE
+
+            self._cb = EXEC_FN(trampoline)
+            cfg.executor = self._cb
+            if gs is None:
+                cfg.n_members = len(self.member_n)
+                cfg.member_vertices = self._mv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        h = _vp()
+        _check(_lib.alb_server_create(None if gs is None else gs.handle, ctypes.byref(cfg), ctypes.byref(h)),
+               "alb_server_create")
+        self._h = h
+        self._gs = gs  # the graph must outlive the server
+        self._outs = {}
+
+    def submit(self, algo: str, member: int, source: int, out=None, timeout_ms: float = 0.0) -> int:
+        if out is None:
+            out = np.empty(self.member_n[member] if 0 <= member < len(self.member_n) else 1, np.int32)
+        elif out.dtype != np.int32 or not out.flags.c_contiguous or out.shape != (self.member_n[member],):
+            raise ValueError("out must be a contiguous int32 array of the member's vertex count")
+        t = ctypes.c_uint64()
+        _check(_lib.alb_server_submit(self._h, ALGOS[algo], int(member), int(source), out.ctypes.data,
+                                      float(timeout_ms), ctypes.byref(t)), "alb_server_submit")
+        self._outs[t.value] = out
+        return t.value
+
+    def wait(self, ticket: int):
+        """(result array, info dict); raises AlbError for a failed, timed-out
+        or cancelled request (the info is on the exception as .info)."""
+        info = RequestInfo()
+        st = _lib.alb_server_wait(self._h, ticket, ctypes.byref(info))
+        out = self._outs.pop(ticket, None)
+        d = {k: getattr(info, k) for k, _ in info._fields_}
+        if st != ALB_OK:
+            e = AlbError(st, "alb_server_wait")
+            e.info = d
+            raise e
+        return out, d
+
+    def cancel(self, ticket: int) -> None:
+        _check(_lib.alb_server_cancel(self._h, ticket), "alb_server_cancel")
+
+    def drain(self) -> None:
+        _check(_lib.alb_server_drain(self._h), "alb_server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.alb_server_stats_get(self._h, ctypes.byref(st)), "alb_server_stats_get")
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.alb_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _out_buffer(g: Graph, out, dtype):

@@ -18,8 +18,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
 # device code: no packed-fp32 instructions
 DEVICE = ["--offload-arch=%s" % ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# extra device-code defines, e.g. ALB_DEFINES="-DALB_WAVES_PER_EU=6"
+DEVICE += os.environ.get("ALB_DEFINES", "").split()
 
-SOURCES = [("alb_kernels.hip", DEVICE), ("alb_api.cpp", [])]
+SOURCES = [("alb_kernels.hip", DEVICE), ("alb_api.cpp", []), ("alb_server.cpp", [])]
 
 
 def build(verbose: bool = False) -> str:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <climits>
 #include <cstdarg>
@@ -19,6 +20,7 @@
 #include <vector>
 
 #include "../../include/alb.h"
+#include "alb_host.h"
 #include "alb_internal.h"
 
 using namespace alb;
@@ -127,6 +129,12 @@ struct alb_graph_s {
   // set's numbering, vertex and edge counts
   std::vector<int32_t> mem_vbase, mem_n;
   std::vector<int64_t> mem_m;
+  // per member: the largest out-degree and the degree distribution's
+  // signature (the share of edges held by vertices of out-degree in
+  // [2^k, 2^(k+1)), in eighths) that the autotuner keys its results by
+  std::vector<int32_t> mem_maxdeg;
+  std::vector<std::array<uint8_t, 32>> mem_hist;
+  std::atomic<int> plans{0};  // live batch plans on this graph
 };
 
 namespace {
@@ -695,22 +703,49 @@ alb_status traverse(alb_graph g, const Job &job, void *out, size_t elem, const a
   return ALB_OK;
 }
 
-// A batch of BFS or SSSP queries on a graph set, all in one persistent launch.
-alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
-                     int32_t *const *outs, const int64_t *thresholds, const alb_options *user, alb_stats *st) {
+// A batch of BFS or SSSP queries on a graph set, run in one persistent
+// launch.  prepare_batch validates and lays out the per-query tables;
+// upload_batch copies them to a workspace; enqueue_batch issues the device
+// work (no host synchronisation, no allocation: it is what a captured graph
+// replays); finish_batch waits, checks the control block and fills stats.
+struct BatchJob {
+  OpKind op = OP_BFS;
+  alb_options o;
+  int32_t count = 0;
+  std::vector<long long> qoff, qthr, qlbase;
+  std::vector<int32_t> qsrc, qn;
+  std::vector<int32_t *> qout;  // filled once the workspace is known
+  bool per_query_thr = false;
+  long long labels = 0, edges = 0, thr_min = 0;
+  int32_t max_n = 0;
+  uint64_t qcap = 0;
+  int grid = 0;
+  int64_t threshold = 0;
+  hipStream_t stream = nullptr;
+  Args a;
+};
+
+alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
+                         int32_t *const *outs, const int64_t *thresholds, const alb_options *user, BatchJob &j) {
   if (!g) return fail(ALB_E_INVAL, "graph handle is NULL");
   if (count < 1 || count > kMaxBatch) return fail(ALB_E_INVAL, "count %d not in [1, %d]", count, kMaxBatch);
   if (!members || !sources || !outs) return fail(ALB_E_INVAL, "members, sources and outs must not be NULL");
   if (op == OP_SSSP && !g->weighted) return fail(ALB_E_INVAL, "SSSP needs a graph set created with weights");
-  alb_options o;
+  alb_options &o = j.o;
   alb_status s = resolve_options(user, o);
   if (s != ALB_OK) return s;
   if (o.launch == ALB_LAUNCH_HOST_LOOP) return fail(ALB_E_UNSUPPORTED, "batches run as one persistent launch only");
   if (thresholds && o.mode != ALB_MODE_ALB) return fail(ALB_E_INVAL, "per-query thresholds need mode ALB");
+  j.op = op;
+  j.count = count;
   const int32_t nmem = (int32_t)g->mem_n.size();
-  std::vector<long long> qoff(count), qthr(count), qlbase(count);
-  std::vector<int32_t> qsrc(count), qn(count);
-  std::vector<int32_t *> qout(count);
+  j.qoff.resize(count);
+  j.qthr.resize(count);
+  j.qlbase.resize(count);
+  j.qsrc.resize(count);
+  j.qn.resize(count);
+  j.qout.assign(outs, outs + count);
+  j.per_query_thr = thresholds != nullptr;
   long long labels = 0, edges = 0, thr_min = LLONG_MAX;
   int32_t max_n = 0;
   for (int32_t q = 0; q < count; ++q) {
@@ -721,16 +756,20 @@ alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *membe
       return fail(ALB_E_INVAL, "sources[%d] = %d out of range [0, %d)", q, sources[q], n);
     if (!outs[q]) return fail(ALB_E_INVAL, "outs[%d] is NULL", q);
     if (thresholds && thresholds[q] < 0) return fail(ALB_E_INVAL, "thresholds[%d] must be >= 0", q);
-    qlbase[q] = labels;
-    qoff[q] = labels - g->mem_vbase[mb];
-    qsrc[q] = g->mem_vbase[mb] + sources[q];
-    qn[q] = n;
-    qthr[q] = thresholds ? thresholds[q] : 0;
-    thr_min = std::min(thr_min, (long long)qthr[q]);
+    j.qlbase[q] = labels;
+    j.qoff[q] = labels - g->mem_vbase[mb];
+    j.qsrc[q] = g->mem_vbase[mb] + sources[q];
+    j.qn[q] = n;
+    j.qthr[q] = thresholds ? thresholds[q] : 0;
+    thr_min = std::min(thr_min, (long long)j.qthr[q]);
     labels += n;
     edges += g->mem_m[mb];
     max_n = std::max(max_n, n);
   }
+  j.labels = labels;
+  j.edges = edges;
+  j.thr_min = thresholds ? thr_min : 0;
+  j.max_n = max_n;
   // every (query, vertex) enters a round's worklist at most once with the
   // per-round dedup, so one round holds at most `labels` entries and at most
   // `edges` huge edges, which the 32-bit worklist positions must hold
@@ -741,58 +780,36 @@ alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *membe
   if (qcap > 0xfffffffeULL || edges >= 0xffffffffLL)
     return fail(ALB_E_INVAL, "batch too large for 32-bit worklist positions (%lld labels, %lld edges): split it",
                 labels, edges);
+  j.qcap = qcap;
 
   HIP_TRY(hipSetDevice(g->device));
-  const hipStream_t stream = o.stream ? (hipStream_t)o.stream : g->stream;
+  j.stream = o.stream ? (hipStream_t)o.stream : g->stream;
   const int wg = o.wg_size;
   int resident = 0;
   s = resident_workgroups(g, op, wg, &resident, true);
   if (s != ALB_OK) return s;
-  const int grid = o.grid_wgs > 0 ? o.grid_wgs : resident;
-  if (grid > resident)
-    return fail(ALB_E_INVAL, "grid_wgs %d exceeds the %d workgroups the device can hold", grid, resident);
-  int64_t threshold;
+  j.grid = o.grid_wgs > 0 ? o.grid_wgs : resident;
+  if (j.grid > resident)
+    return fail(ALB_E_INVAL, "grid_wgs %d exceeds the %d workgroups the device can hold", j.grid, resident);
   if (o.mode == ALB_MODE_TWC_ONLY)
-    threshold = INT64_MAX;
+    j.threshold = INT64_MAX;
   else if (o.mode == ALB_MODE_LB_ALL)
-    threshold = 0;
+    j.threshold = 0;
   else if (o.huge_threshold >= 0)
-    threshold = o.huge_threshold;
+    j.threshold = o.huge_threshold;
   else if (o.huge_threshold == ALB_THRESHOLD_LAUNCHED)
-    threshold = -1;
+    j.threshold = -1;
   else
-    threshold = (int64_t)kEdgesPerLanePass * wg;
+    j.threshold = (int64_t)kEdgesPerLanePass * wg;
 
-  BatchNeeds nd{std::max<long long>(labels, 1), (uint32_t)qcap, (uint32_t)(((uint64_t)edges >> kHintMinShift) + 2),
-                count};
-  BatchWs *ws = nullptr;
-  s = bws_acquire(g, nd, &ws);
-  if (s != ALB_OK) return s;
-  GuardOf<BatchWs> guard{g, ws};
-  for (int32_t q = 0; q < count; ++q) qout[q] = o.out_on_device ? outs[q] : ws->out32 + qlbase[q];
-
-  HIP_TRY(hipMemcpyAsync(ws->qoff, qoff.data(), sizeof(long long) * count, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(ws->qthr, qthr.data(), sizeof(long long) * count, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(ws->qlbase, qlbase.data(), sizeof(long long) * count, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(ws->qsrc, qsrc.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(ws->qn, qn.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(ws->qout, qout.data(), sizeof(int32_t *) * count, hipMemcpyHostToDevice, stream));
-
-  Args a;
+  Args &a = j.a;
   std::memset(&a, 0, sizeof a);
   a.off = g->d_off;
   a.col = g->d_col;
   a.w = g->d_w;
   a.n = g->n;
   a.qcap = (uint32_t)qcap;
-  a.q0 = ws->q0;
-  a.q1 = ws->q1;
-  a.huge_rec = ws->huge_rec;
-  a.hint = ws->hint;
-  a.hint_cap = ws->hint_cap;
-  a.bar = ws->bar;
-  a.ctl = ws->ctl;
-  a.threshold = threshold;
+  a.threshold = j.threshold;
   a.c_wave = o.wave_cutoff;
   a.c_wg = o.wg_cutoff;
   a.dedup = dedup ? 1 : 0;
@@ -801,50 +818,283 @@ alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *membe
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
   a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);
   a.profile = getenv("ALB_TIMELINE") ? 1 : 0;
-  if (op == OP_BFS) a.level = (int32_t *)ws->word;
-  if (op == OP_SSSP) a.word = ws->word;
   a.nq = count;
+  a.qthr_min = j.thr_min;
+  a.nlabels = labels;
+  return ALB_OK;
+}
+
+BatchNeeds batch_needs(const BatchJob &j) {
+  return BatchNeeds{std::max<long long>(j.labels, 1), (uint32_t)j.qcap,
+                    (uint32_t)(((uint64_t)j.edges >> kHintMinShift) + 2), j.count};
+}
+
+// Point the job at workspace ws and copy its tables there (stream order).
+// Host outputs are staged in ws->out32.
+alb_status upload_batch(BatchJob &j, BatchWs *ws) {
+  Args &a = j.a;
+  a.q0 = ws->q0;
+  a.q1 = ws->q1;
+  a.huge_rec = ws->huge_rec;
+  a.hint = ws->hint;
+  a.hint_cap = ws->hint_cap;
+  a.bar = ws->bar;
+  a.ctl = ws->ctl;
+  if (j.op == OP_BFS) a.level = (int32_t *)ws->word;
+  if (j.op == OP_SSSP) a.word = ws->word;
   a.qoff = ws->qoff;
-  a.qthr = thresholds ? ws->qthr : nullptr;
-  a.qthr_min = thresholds ? thr_min : 0;
+  a.qthr = j.per_query_thr ? ws->qthr : nullptr;
   a.qlbase = ws->qlbase;
   a.qsrc = ws->qsrc;
   a.qn = ws->qn;
   a.qout = ws->qout;
-  a.nlabels = labels;
+  std::vector<int32_t *> dst(j.qout);
+  if (!j.o.out_on_device)
+    for (int32_t q = 0; q < j.count; ++q) dst[q] = ws->out32 + j.qlbase[q];
+  const hipStream_t st = j.stream;
+  const size_t c = (size_t)j.count;
+  HIP_TRY(hipMemcpyAsync(ws->qoff, j.qoff.data(), sizeof(long long) * c, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws->qthr, j.qthr.data(), sizeof(long long) * c, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws->qlbase, j.qlbase.data(), sizeof(long long) * c, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws->qsrc, j.qsrc.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws->qn, j.qn.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws->qout, dst.data(), sizeof(int32_t *) * c, hipMemcpyHostToDevice, st));
+  // the copies read pageable host vectors: finish them before those can go
+  HIP_TRY(hipStreamSynchronize(st));
+  return ALB_OK;
+}
 
-  HIP_TRY(hipEventRecord(ws->ev[0], stream));
-  HIP_TRY(launch_init_batch(op, a, stream));
-  HIP_TRY(hipEventRecord(ws->ev[1], stream));
-  HIP_TRY(launch_batch(op, wg, grid, a, stream));
-  HIP_TRY(launch_finish_batch(op, a, max_n, stream));
-  HIP_TRY(hipEventRecord(ws->ev[2], stream));
-  HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
+// The device work of one batch: initialise labels and seed the sources, run
+// every round in one persistent launch, write the outputs, and copy the
+// control block to the pinned mirror.
+alb_status enqueue_batch(const BatchJob &j, BatchWs *ws, hipStream_t st) {
+  HIP_TRY(launch_init_batch(j.op, j.a, st));
+  HIP_TRY(launch_batch(j.op, j.o.wg_size, j.grid, j.a, st));
+  HIP_TRY(launch_finish_batch(j.op, j.a, j.max_n, st));
+  HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  return ALB_OK;
+}
+
+// After the stream reached the end of enqueue_batch: errors, host outputs, stats.
+alb_status finish_batch(alb_graph g, const BatchJob &j, BatchWs *ws, int32_t *const *outs, alb_stats *st,
+                        hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
   const Ctl &c = *ws->h_ctl;
   if (c.abort) return abort_error(c);
   if (c.overflow != 0xffffffffu)
-    return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", a.qcap, c.overflow);
+    return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", j.a.qcap, c.overflow);
   const int rounds = (int)c.rounds;
-  if (getenv("ALB_TIMELINE")) print_timeline(c, (int)op, rounds, (long long)c.threshold_used, g->clock_khz);
-  if (rounds >= a.max_rounds && c.qcount[rounds % 3] != 0)
-    return fail(ALB_E_DEVICE, "no convergence within %d rounds", a.max_rounds);
-  if (!o.out_on_device) {
-    std::vector<int32_t> h;
-    try {
-      h.resize((size_t)labels);
-    } catch (const std::bad_alloc &) {
-      return fail(ALB_E_NOMEM, "host allocation failed");
-    }
-    HIP_TRY(hipMemcpy(h.data(), ws->out32, sizeof(int32_t) * (size_t)labels, hipMemcpyDeviceToHost));
-    for (int32_t q = 0; q < count; ++q)
-      std::memcpy(outs[q], h.data() + qlbase[q], sizeof(int32_t) * (size_t)qn[q]);
+  if (getenv("ALB_TIMELINE")) print_timeline(c, (int)j.op, rounds, (long long)c.threshold_used, g->clock_khz);
+  if (rounds >= j.a.max_rounds && c.qcount[rounds % 3] != 0)
+    return fail(ALB_E_DEVICE, "no convergence within %d rounds", j.a.max_rounds);
+  if (!j.o.out_on_device) {  // straight from the staging area into each query's host array
+    for (int32_t q = 0; q < j.count; ++q)
+      HIP_TRY(hipMemcpyAsync(outs[q], ws->out32 + j.qlbase[q], sizeof(int32_t) * (size_t)j.qn[q],
+                             hipMemcpyDeviceToHost, j.stream));
+    HIP_TRY(hipStreamSynchronize(j.stream));
   }
   if (st)
-    fill_stats(st, c, rounds, 1, (int64_t)c.n_members * wg, thresholds ? -1 : (int64_t)c.threshold_used, ws->ev[0],
-               ws->ev[1], ws->ev[2]);
+    fill_stats(st, c, rounds, 1, (int64_t)c.n_members * j.o.wg_size,
+               j.per_query_thr ? -1 : (int64_t)c.threshold_used, e0, e1, e2);
   return ALB_OK;
 }
+
+alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
+                     int32_t *const *outs, const int64_t *thresholds, const alb_options *user, alb_stats *st) {
+  BatchJob j;
+  alb_status s = prepare_batch(g, op, count, members, sources, outs, thresholds, user, j);
+  if (s != ALB_OK) return s;
+  BatchWs *ws = nullptr;
+  s = bws_acquire(g, batch_needs(j), &ws);
+  if (s != ALB_OK) return s;
+  GuardOf<BatchWs> guard{g, ws};
+  s = upload_batch(j, ws);
+  if (s != ALB_OK) return s;
+  const hipStream_t stream = j.stream;
+  HIP_TRY(hipEventRecord(ws->ev[0], stream));
+  HIP_TRY(launch_init_batch(op, j.a, stream));
+  HIP_TRY(hipEventRecord(ws->ev[1], stream));
+  HIP_TRY(launch_batch(op, j.o.wg_size, j.grid, j.a, stream));
+  HIP_TRY(launch_finish_batch(op, j.a, j.max_n, stream));
+  HIP_TRY(hipEventRecord(ws->ev[2], stream));
+  HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return finish_batch(g, j, ws, outs, st, ws->ev[0], ws->ev[1], ws->ev[2]);
+}
+
+// --------------------------------------------------------------------------
+// Autotuner: per degree distribution, the huge threshold and workgroup size
+// (and for one graph the TWC cutoffs) that ran a sample of queries fastest.
+// --------------------------------------------------------------------------
+
+struct TuneKey {
+  int algo;
+  int lg_n, lg_maxdeg;
+  int64_t lg_m;
+  std::array<uint8_t, 32> hist;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(algo, lg_n, lg_maxdeg, lg_m, hist) < std::tie(o.algo, o.lg_n, o.lg_maxdeg, o.lg_m, o.hist);
+  }
+};
+
+struct TuneCand {
+  int32_t wg;
+  int64_t threshold;
+  int32_t c_wave, c_wg;
+  double ms;
+};
+
+// best candidate per workgroup size, per key
+std::mutex g_tune_mu;
+std::map<TuneKey, std::vector<TuneCand>> g_tune;
+
+int ilog2(int64_t x) { return x > 0 ? 63 - __builtin_clzll((unsigned long long)x) : -1; }
+
+TuneKey tune_key(alb_graph g, OpKind op, int32_t member) {
+  return TuneKey{(int)op, ilog2(g->mem_n[member]), ilog2(g->mem_maxdeg[member]), ilog2(g->mem_m[member]),
+                 g->mem_hist[member]};
+}
+
+// Median device time of a batch of `k` queries on one member under options o.
+alb_status time_candidate(alb_graph g, OpKind op, int32_t member, int32_t k, const int32_t *sources,
+                          const alb_options &o, BatchWs *ws, double *ms) {
+  std::vector<int32_t> mb((size_t)k, member);
+  std::vector<int32_t *> outs((size_t)k, nullptr);
+  for (int32_t q = 0; q < k; ++q) outs[q] = (int32_t *)ws;  // placeholder: outputs stay on the device
+  alb_options oo = o;
+  oo.out_on_device = 1;
+  BatchJob j;
+  alb_status s = prepare_batch(g, op, k, mb.data(), sources, outs.data(), nullptr, &oo, j);
+  if (s != ALB_OK) return s;
+  const BatchNeeds nd = batch_needs(j);
+  if (ws->lab_cap < nd.labels || ws->qcap < nd.qcap || ws->hint_cap < nd.hint_cap || ws->nq_cap < nd.nq)
+    return fail(ALB_E_INVAL, "tuning workspace too small");
+  // outputs go to the workspace's own staging area, query by query
+  for (int32_t q = 0; q < k; ++q) j.qout[q] = ws->out32 + j.qlbase[q];
+  s = upload_batch(j, ws);
+  if (s != ALB_OK) return s;
+  double t[4];
+  for (int rep = 0; rep < 4; ++rep) {
+    HIP_TRY(hipEventRecord(ws->ev[0], j.stream));
+    s = enqueue_batch(j, ws, j.stream);
+    if (s != ALB_OK) return s;
+    HIP_TRY(hipEventRecord(ws->ev[2], j.stream));
+    HIP_TRY(hipStreamSynchronize(j.stream));
+    s = finish_batch(g, j, ws, nullptr, nullptr, ws->ev[0], ws->ev[0], ws->ev[2]);
+    if (s != ALB_OK) return s;
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, ws->ev[0], ws->ev[2]));
+    t[rep] = f;
+  }
+  std::sort(t + 1, t + 4);  // the first run warms up
+  *ms = t[2];
+  return ALB_OK;
+}
+
+// Tune one member (cached by its degree signature): for each workgroup size
+// the fastest of the candidate thresholds; with `cutoffs`, then also two TWC
+// cutoff pairs at the winner.
+alb_status tune_member(alb_graph g, OpKind op, int32_t member, int32_t k, const int32_t *sources,
+                       const alb_options &base, bool cutoffs, std::vector<TuneCand> *out) {
+  const TuneKey key = tune_key(g, op, member);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && (!cutoffs || it->second.size() > 2)) {
+      *out = it->second;
+      return ALB_OK;
+    }
+  }
+  // one workspace sized for the largest candidate (wg 1024, no dedup change)
+  alb_options probe = base;
+  probe.out_on_device = 1;
+  probe.wg_size = 1024;
+  BatchJob pj;
+  std::vector<int32_t> mb((size_t)k, member);
+  std::vector<int32_t *> dummy((size_t)k, (int32_t *)&pj);
+  alb_status s = prepare_batch(g, op, k, mb.data(), sources, dummy.data(), nullptr, &probe, pj);
+  if (s != ALB_OK) return s;
+  BatchWs ws;
+  s = bws_fill(&ws, batch_needs(pj));
+  if (s != ALB_OK) {
+    std::string keep = g_err;
+    ws.release();
+    g_err = keep;
+    return s;
+  }
+  std::vector<TuneCand> best;
+  static const int32_t wgs[] = {256, 1024};
+  // the paper's threshold plateau (2^8 .. 2^18) sampled every factor of 4,
+  // plus one wavefront's worth of edges
+  static const int64_t thrs[] = {64, 256, 1024, 4096, 16384};
+  for (int32_t wg : wgs) {
+    TuneCand b{wg, 0, 64, wg, 1e30};
+    for (int64_t t : thrs) {
+      alb_options o = base;
+      o.mode = ALB_MODE_ALB;
+      o.wg_size = wg;
+      o.huge_threshold = t;
+      o.wave_cutoff = 64;
+      o.wg_cutoff = wg;
+      o.grid_wgs = 0;
+      double ms = 0;
+      s = time_candidate(g, op, member, k, sources, o, &ws, &ms);
+      if (s != ALB_OK) break;
+      if (ms < b.ms) b = TuneCand{wg, t, 64, wg, ms};
+    }
+    if (s != ALB_OK) break;
+    best.push_back(b);
+  }
+  if (s == ALB_OK && cutoffs) {
+    TuneCand w = best[0].ms <= best[1].ms ? best[0] : best[1];
+    static const int32_t cw[][2] = {{32, 0}, {128, 0}, {64, -4}};  // -4: wg / 4
+    TuneCand c = w;
+    for (auto &p : cw) {
+      alb_options o = base;
+      o.mode = ALB_MODE_ALB;
+      o.wg_size = w.wg;
+      o.huge_threshold = w.threshold;
+      o.wave_cutoff = p[0];
+      o.wg_cutoff = p[1] < 0 ? w.wg / -p[1] : w.wg;
+      o.grid_wgs = 0;
+      double ms = 0;
+      s = time_candidate(g, op, member, k, sources, o, &ws, &ms);
+      if (s != ALB_OK) break;
+      if (ms < c.ms) c = TuneCand{w.wg, w.threshold, o.wave_cutoff, o.wg_cutoff, ms};
+    }
+    best.push_back(c);
+  }
+  ws.release();
+  if (s != ALB_OK) return s;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+  *out = best;
+  return ALB_OK;
+}
+
+// --------------------------------------------------------------------------
+// Batch plans: a batch laid out once and captured into a HIP graph.
+// --------------------------------------------------------------------------
+
+}  // namespace
+
+struct alb_plan_s {
+  alb_graph g = nullptr;
+  BatchJob j;
+  BatchWs ws;
+  std::vector<int32_t *> outs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::mutex mu;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    ws.release();
+  }
+};
+
+namespace {
 
 }  // namespace
 
@@ -869,6 +1119,8 @@ const char *alb_status_str(alb_status s) {
     case ALB_E_RANGE: return "ALB_E_RANGE";
     case ALB_E_OVERFLOW: return "ALB_E_OVERFLOW";
     case ALB_E_UNSUPPORTED: return "ALB_E_UNSUPPORTED";
+    case ALB_E_TIMEOUT: return "ALB_E_TIMEOUT";
+    case ALB_E_CANCELLED: return "ALB_E_CANCELLED";
   }
   return "ALB_E_UNKNOWN";
 }
@@ -878,6 +1130,21 @@ const char *alb_last_error(void) { return g_err.c_str(); }
 }  // extern "C"
 
 namespace {
+
+std::array<uint8_t, 32> degree_signature(int32_t n, const int32_t *off, int32_t *maxdeg) {
+  int64_t e[32] = {0}, m = 0;
+  int32_t md = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    const int32_t d = off[v + 1] - off[v];
+    md = std::max(md, d);
+    if (d > 0) e[31 - __builtin_clz((unsigned)d)] += d;
+    m += d;
+  }
+  std::array<uint8_t, 32> h{};
+  for (int k = 0; k < 32; ++k) h[k] = m ? (uint8_t)((8 * e[k] + m / 2) / m) : 0;
+  *maxdeg = md;
+  return h;
+}
 
 // Copy a validated host CSR to the device and make the handle.
 alb_status make_graph(int32_t n, int64_t mm, const int32_t *off, const int32_t *cl, const int32_t *w, bool symmetric,
@@ -905,6 +1172,8 @@ alb_status make_graph(int32_t n, int64_t mm, const int32_t *off, const int32_t *
   g->mem_vbase.assign(1, 0);
   g->mem_n.assign(1, n);
   g->mem_m.assign(1, mm);
+  g->mem_maxdeg.assign(1, 0);
+  g->mem_hist.assign(1, degree_signature(n, off, &g->mem_maxdeg[0]));
   int attr = 0;
   hipError_t e;
   if ((e = hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
@@ -998,6 +1267,10 @@ alb_status alb_graph_create_set(int32_t count, const int32_t *ns, const int64_t 
   (*out)->mem_vbase = vbase;
   (*out)->mem_n = nn;
   (*out)->mem_m = mm;
+  (*out)->mem_maxdeg.assign(count, 0);
+  (*out)->mem_hist.resize(count);
+  for (int32_t i = 0; i < count; ++i)
+    (*out)->mem_hist[i] = degree_signature(ns[i], row_offsets[i], &(*out)->mem_maxdeg[i]);
   return ALB_OK;
 }
 
@@ -1018,6 +1291,7 @@ alb_status alb_graph_member_info(alb_graph g, int32_t member, int32_t *n, int64_
 
 alb_status alb_graph_destroy(alb_graph g) {
   if (!g) return ALB_OK;
+  if (g->plans.load() > 0) return fail(ALB_E_INVAL, "%d batch plans still use this graph", g->plans.load());
   (void)hipSetDevice(g->device);
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   for (Workspace *w : g->pool) {
@@ -1223,4 +1497,166 @@ alb_status alb_sssp_batch(alb_graph g, int32_t count, const int32_t *members, co
   return s;
 }
 
+alb_status alb_autotune(alb_graph g, int32_t algo, int32_t member, int32_t nsources, const int32_t *sources,
+                        const alb_options *base, alb_options *tuned, double *best_ms) {
+  if (!g || !tuned) return fail(ALB_E_INVAL, "graph handle and tuned must not be NULL");
+  if (algo != ALB_ALGO_BFS && algo != ALB_ALGO_SSSP) return fail(ALB_E_UNSUPPORTED, "algo %d cannot be tuned", algo);
+  if (member < 0 || member >= (int32_t)g->mem_n.size()) return fail(ALB_E_INVAL, "member %d out of range", member);
+  if (nsources < 1 || nsources > 64 || !sources) return fail(ALB_E_INVAL, "nsources must be in [1, 64]");
+  alb_options b;
+  alb_status s = resolve_options(base, b);
+  if (s != ALB_OK) return s;
+  std::vector<TuneCand> r;
+  s = tune_member(g, algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP, member, nsources, sources, b, true, &r);
+  if (s != ALB_OK) return s;
+  const TuneCand &c = r.back();
+  b.mode = ALB_MODE_ALB;
+  b.wg_size = c.wg;
+  b.huge_threshold = c.threshold;
+  b.wave_cutoff = c.c_wave;
+  b.wg_cutoff = c.c_wg;
+  *tuned = b;
+  if (best_ms) *best_ms = c.ms;
+  return ALB_OK;
+}
+
+alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                              const int32_t *sources, const alb_options *base, alb_options *tuned,
+                              int64_t *thresholds) {
+  if (!g || !tuned || !thresholds || !members || !sources) return fail(ALB_E_INVAL, "NULL argument");
+  if (algo != ALB_ALGO_BFS && algo != ALB_ALGO_SSSP) return fail(ALB_E_UNSUPPORTED, "algo %d cannot be tuned", algo);
+  if (count < 1 || count > kMaxBatch) return fail(ALB_E_INVAL, "count %d not in [1, %d]", count, kMaxBatch);
+  alb_options b;
+  alb_status s = resolve_options(base, b);
+  if (s != ALB_OK) return s;
+  const OpKind op = algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP;
+  const int32_t nmem = (int32_t)g->mem_n.size();
+  std::map<int32_t, std::vector<int32_t>> srcs;  // member -> its sources in the batch
+  for (int32_t q = 0; q < count; ++q) {
+    if (members[q] < 0 || members[q] >= nmem) return fail(ALB_E_INVAL, "members[%d] out of range", q);
+    srcs[members[q]].push_back(sources[q]);
+  }
+  // per member, per workgroup size, the best threshold; the batch takes the
+  // workgroup size with the smallest total (each member's time scaled by its
+  // share of the batch)
+  std::map<int32_t, std::vector<TuneCand>> res;
+  double tot[2] = {0, 0};
+  for (auto &kv : srcs) {
+    const int32_t k = (int32_t)std::min<size_t>(kv.second.size(), 4);
+    std::vector<TuneCand> r;
+    s = tune_member(g, op, kv.first, k, kv.second.data(), b, false, &r);
+    if (s != ALB_OK) return s;
+    for (int i = 0; i < 2; ++i) tot[i] += r[i].ms * (double)kv.second.size() / k;
+    res[kv.first] = r;
+  }
+  const int pick = tot[0] <= tot[1] ? 0 : 1;
+  b.mode = ALB_MODE_ALB;
+  b.wg_size = res.begin()->second[pick].wg;
+  b.wave_cutoff = 64;
+  b.wg_cutoff = b.wg_size;
+  b.huge_threshold = ALB_THRESHOLD_DEFAULT;
+  for (int32_t q = 0; q < count; ++q) thresholds[q] = res[members[q]][pick].threshold;
+  *tuned = b;
+  return ALB_OK;
+}
+
+alb_status alb_autotune_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return ALB_OK;
+}
+
+alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                                 const int32_t *sources, int32_t *const *outs, const int64_t *thresholds,
+                                 const alb_options *opt, alb_plan *out) {
+  if (!out) return fail(ALB_E_INVAL, "output handle pointer is NULL");
+  *out = nullptr;
+  if (algo != ALB_ALGO_BFS && algo != ALB_ALGO_SSSP) return fail(ALB_E_UNSUPPORTED, "algo %d cannot be batched", algo);
+  alb_plan p = new (std::nothrow) alb_plan_s();
+  if (!p) return fail(ALB_E_NOMEM, "host allocation failed");
+  auto bail = [&](alb_status st) {
+    std::string keep = g_err;
+    p->release();
+    delete p;
+    g_err = keep;
+    return st;
+  };
+  alb_status s = prepare_batch(g, algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP, count, members, sources, outs, thresholds,
+                               opt, p->j);
+  if (s != ALB_OK) return bail(s);
+  p->g = g;
+  p->outs.assign(outs, outs + count);
+  s = bws_fill(&p->ws, batch_needs(p->j));
+  if (s != ALB_OK) return bail(s);
+  s = upload_batch(p->j, &p->ws);
+  if (s != ALB_OK) return bail(s);
+  // capture on a private stream, so that nothing else issued meanwhile joins the graph
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(fail(ALB_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = enqueue_batch(p->j, &p->ws, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+    if (s == ALB_OK && e2 != hipSuccess) s = fail(ALB_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+  } else {
+    s = fail(ALB_E_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  (void)hipStreamDestroy(cs);
+  if (s != ALB_OK) return bail(s);
+  e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(fail(ALB_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e)));
+  g->plans.fetch_add(1);
+  *out = p;
+  return ALB_OK;
+}
+
+alb_status alb_batch_plan_run(alb_plan p, alb_stats *stats) {
+  zero_stats(stats);
+  if (!p) return fail(ALB_E_INVAL, "plan handle is NULL");
+  std::lock_guard<std::mutex> lk(p->mu);
+  HIP_TRY(hipSetDevice(p->g->device));
+  const hipStream_t st = p->j.stream;
+  HIP_TRY(hipEventRecord(p->ws.ev[0], st));
+  HIP_TRY(hipGraphLaunch(p->exec, st));
+  HIP_TRY(hipEventRecord(p->ws.ev[2], st));
+  HIP_TRY(hipStreamSynchronize(st));
+  alb_status s = finish_batch(p->g, p->j, &p->ws, p->outs.data(), stats, p->ws.ev[0], p->ws.ev[0], p->ws.ev[2]);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_batch_plan_destroy(alb_plan p) {
+  if (!p) return ALB_OK;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    (void)hipSetDevice(p->g->device);
+    p->release();
+  }
+  p->g->plans.fetch_sub(1);
+  delete p;
+  return ALB_OK;
+}
+
 }  // extern "C"
+
+namespace alb {
+
+alb_status set_error(alb_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+alb_status batch_resident_workgroups(alb_graph g, int32_t algo, int32_t wg, int *out) {
+  if (!g || !out) return fail(ALB_E_INVAL, "NULL argument");
+  if (!supported_wg(wg)) return fail(ALB_E_UNSUPPORTED, "wg_size %d not built", wg);
+  HIP_TRY(hipSetDevice(g->device));
+  return resident_workgroups(g, algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP, wg, out, true);
+}
+
+}  // namespace alb

@@ -1,0 +1,15 @@
+// Host-side internal interface between the runtime's C++ files (not ABI).
+#pragma once
+
+#include "../../include/alb.h"
+
+namespace alb {
+
+// Set the calling thread's alb_last_error() text; returns s.
+alb_status set_error(alb_status s, const char *fmt, ...);
+
+// Workgroups of `wg` threads the device holds at once for a batch launch of
+// `algo` on g's device.
+alb_status batch_resident_workgroups(alb_graph g, int32_t algo, int32_t wg, int *out);
+
+}  // namespace alb

@@ -491,9 +491,29 @@ __device__ __forceinline__ void block_exscan(int32_t x, int32_t &excl, int32_t &
   __syncthreads();
 }
 
+// Waves per SIMD the persistent kernel's register budget is sized for: the
+// traversal is bound by the latency of dependent random loads, so more
+// resident waves keep more of them in flight.
+#ifndef ALB_WAVES_PER_EU
+#define ALB_WAVES_PER_EU 4
+#endif
+
 // ---------------------------------------------------------------------------
 // Phase 1: inspection (Algorithm 1) fused with the TWC bins.
 // ---------------------------------------------------------------------------
+
+// Worklist entries per claim: B, unless the worklist would give a workgroup
+// fewer than two claims; then whole wavefronts' worth, just enough for two
+// claims per workgroup, so that a short worklist still reaches every
+// workgroup instead of leaving most of them idle for the phase.
+__device__ __forceinline__ uint32_t twc_chunk(uint32_t nF, uint32_t wgs, int B) {
+  const uint64_t per = ((uint64_t)nF + 2ull * wgs - 1) / (2ull * wgs);
+  uint64_t c = (per + kWave - 1) / kWave * kWave;
+  if (c < (uint64_t)kWave) c = kWave;
+  if (c > (uint64_t)B) c = B;
+  return (uint32_t)c;
+}
+
 template <int B, class Op, bool M>
 __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid gr, int round,
                           const Entry<M> *F, uint32_t nF, Entry<M> *qn, uint32_t *qn_cnt, unsigned long long *hctr,
@@ -504,6 +524,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
   const int32_t gt = (int32_t)(gr.id * B + tid);
   const uint32_t tag = (uint32_t)round + 1u;
   uint32_t *chunk_ctr = &a.ctl->chunk[round % 3];
+  const uint32_t C = twc_chunk(nF, gr.n, B);
   Pusher<Entry<M>> pu{sm.pbuf[tid / kWave], 0u, qn, qn_cnt};
   uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
   // Workgroups claim B-entry chunks of the worklist one at a time, so a chunk
@@ -513,12 +534,13 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
   for (;;) {
     if (tid == 0) sm.chunk = add_relaxed(chunk_ctr, 1u);
     __syncthreads();
-    const uint64_t base = (uint64_t)sm.chunk * B;
+    const uint64_t base = (uint64_t)sm.chunk * C;
     if (base >= nF) break;
     const uint32_t i = (uint32_t)base + tid;
+    const bool mine = tid < (int)C && i < nF;
     int32_t v = -1, beg = 0, deg = 0, q = 0;  // q: the entry's query (batch)
     int64_t thr = threshold;
-    if (i < nF) {
+    if (mine) {
       if constexpr (M) {
         const unsigned long long e = F[i];
         v = (int32_t)(uint32_t)e;
@@ -542,7 +564,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
     const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= thr;
     reserve_huge(huge, M ? q : v, beg, deg, to_bits(sv), a, round, hctr, hs, acc);
     if constexpr (Op::kRecord) {
-      if (i < nF) a.bins[i] = (int8_t)(huge ? 3 : deg >= a.c_wg ? 2 : deg >= a.c_wave ? 1 : 0);
+      if (mine) a.bins[i] = (int8_t)(huge ? 3 : deg >= a.c_wg ? 2 : deg >= a.c_wave ? 1 : 0);
     }
     if constexpr (Op::kPR) {
       if (v >= 0 && deg == 0) acc.dangling += to_fix(a.rank[v]);
@@ -995,7 +1017,8 @@ __global__ __launch_bounds__(B) void k_pr_update(Args a) {
 }
 
 template <int B, class Op, bool M>
-__global__ __launch_bounds__(B) void k_persistent(Args a, Op op) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER_EU))) void k_persistent(Args a,
+                                                                                                           Op op) {
   __shared__ Smem<B, Op, M> sm;
   Acc acc;
   Grid gr;

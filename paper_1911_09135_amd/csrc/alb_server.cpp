@@ -1,0 +1,376 @@
+// Serving runtime behind the alb_server_* calls of include/alb.h: a queue of
+// BFS / SSSP requests on one graph set, admitted by workspace footprint and
+// run as batches by a few dispatcher lanes that share the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/alb.h"
+#include "alb_host.h"
+
+using alb::set_error;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+// Device bytes one request adds to its batch's workspace: per vertex of its
+// member an 8-byte label word, a 4-byte output slot, two 8-byte worklist
+// entries and a 16-byte huge-list record; plus its per-query tables.
+constexpr size_t kBytesPerVertex = 44;
+constexpr size_t kBytesPerQuery = 64;
+
+enum { kPending = 0, kRunning = 1, kDone = 2 };
+
+struct Request {
+  int32_t algo = 0, member = 0, source = 0;
+  int32_t *out = nullptr;
+  size_t footprint = 0;
+  Clock::time_point t_submit, t_dispatch, t_done, deadline;
+  int32_t state = kPending;
+  int32_t status = ALB_OK;
+  int32_t batch_size = 0, lane = -1;
+};
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+}  // namespace
+
+struct alb_server_s {
+  alb_graph g = nullptr;
+  alb_server_config cfg;
+  std::vector<int32_t> member_n;
+  size_t lane_budget = 0;
+  int grid[2] = {0, 0};  // workgroups per lane, by algo
+  std::vector<hipStream_t> streams;
+  std::vector<std::thread> lanes;
+
+  std::mutex mu;
+  std::condition_variable cv_work;  // a request was queued, or stop
+  std::condition_variable cv_done;  // a request completed
+  std::list<uint64_t> pending;      // arrival order
+  std::unordered_map<uint64_t, Request> reqs;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int running = 0;  // requests dispatched and not yet completed
+  alb_server_stats st{};
+
+  void complete(Request &r, int32_t status, Clock::time_point now) {
+    r.state = kDone;
+    r.status = status;
+    r.t_done = now;
+    if (status == ALB_OK)
+      ++st.completed;
+    else if (status == ALB_E_TIMEOUT)
+      ++st.timed_out;
+    else if (status == ALB_E_CANCELLED)
+      ++st.cancelled;
+    else
+      ++st.failed;
+  }
+
+  // Run one batch on lane `lane` (no lock held).
+  int32_t execute(int lane, int32_t algo, std::vector<int32_t> &mb, std::vector<int32_t> &src,
+                  std::vector<int32_t *> &outs) {
+    const int32_t n = (int32_t)mb.size();
+    if (cfg.executor) return cfg.executor(cfg.executor_user, algo, n, mb.data(), src.data(), outs.data(), lane);
+    alb_options o = cfg.options;
+    o.stream = streams[lane];
+    o.out_on_device = 0;
+    o.grid_wgs = grid[algo];
+    return algo == ALB_ALGO_BFS ? alb_bfs_batch(g, n, mb.data(), src.data(), outs.data(), nullptr, &o, nullptr)
+                                : alb_sssp_batch(g, n, mb.data(), src.data(), outs.data(), nullptr, &o, nullptr);
+  }
+
+  void lane_main(int lane) {
+    std::vector<uint64_t> batch;
+    std::vector<int32_t> mb, src;
+    std::vector<int32_t *> outs;
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      if (pending.empty()) {
+        if (stop) return;
+        continue;
+      }
+      if (cfg.max_wait_us > 0 && !stop && (int)pending.size() < cfg.max_batch) {
+        cv_work.wait_for(lk, std::chrono::microseconds(cfg.max_wait_us),
+                         [&] { return stop || (int)pending.size() >= cfg.max_batch; });
+        if (pending.empty()) continue;  // another lane took them
+      }
+      // expire overdue requests, then take the oldest request's algorithm and
+      // every queued request of it, in order, that still fits the batch
+      const Clock::time_point now = Clock::now();
+      int32_t algo = -1;
+      size_t foot = 0;
+      batch.clear();
+      bool expired = false;
+      for (auto it = pending.begin(); it != pending.end();) {
+        Request &r = reqs[*it];
+        if (r.deadline <= now) {
+          complete(r, ALB_E_TIMEOUT, now);
+          it = pending.erase(it);
+          expired = true;
+          continue;
+        }
+        if (algo < 0) algo = r.algo;
+        if (r.algo == algo && (int)batch.size() < cfg.max_batch && foot + r.footprint <= lane_budget) {
+          foot += r.footprint;
+          batch.push_back(*it);
+          r.state = kRunning;
+          r.t_dispatch = now;
+          it = pending.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      if (expired) cv_done.notify_all();
+      if (batch.empty()) continue;
+      mb.clear();
+      src.clear();
+      outs.clear();
+      for (uint64_t t : batch) {
+        const Request &r = reqs[t];
+        mb.push_back(r.member);
+        src.push_back(r.source);
+        outs.push_back(r.out);
+      }
+      running += (int)batch.size();
+      ++st.batches;
+      lk.unlock();
+      const Clock::time_point t0 = Clock::now();
+      const int32_t status = execute(lane, algo, mb, src, outs);
+      const Clock::time_point t1 = Clock::now();
+      lk.lock();
+      st.busy_ms += ms_between(t0, t1);
+      for (uint64_t t : batch) {
+        Request &r = reqs[t];
+        r.batch_size = (int32_t)batch.size();
+        r.lane = lane;
+        complete(r, status, t1);
+      }
+      running -= (int)batch.size();
+      cv_done.notify_all();
+    }
+  }
+};
+
+extern "C" {
+
+alb_status alb_server_config_init(alb_server_config *cfg) {
+  if (!cfg) return set_error(ALB_E_INVAL, "cfg is NULL");
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->struct_size = sizeof(alb_server_config);
+  cfg->lanes = 2;
+  cfg->max_batch = 256;
+  cfg->max_wait_us = 0;
+  cfg->hbm_budget = (int64_t)8 << 30;
+  return alb_options_init(&cfg->options);
+}
+
+alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_server *out) {
+  if (!out) return set_error(ALB_E_INVAL, "output handle pointer is NULL");
+  *out = nullptr;
+  alb_server_config cfg;
+  alb_server_config_init(&cfg);
+  if (user) {
+    if (user->struct_size != sizeof(alb_server_config))
+      return set_error(ALB_E_INVAL, "alb_server_config.struct_size = %u, expected %zu", user->struct_size,
+                       sizeof(alb_server_config));
+    cfg = *user;
+  }
+  if (cfg.lanes == 0) cfg.lanes = 2;
+  if (cfg.max_batch == 0) cfg.max_batch = 256;
+  if (cfg.hbm_budget == 0) cfg.hbm_budget = (int64_t)8 << 30;
+  if (cfg.lanes < 1 || cfg.lanes > 16) return set_error(ALB_E_INVAL, "lanes must be in [1, 16]");
+  if (cfg.max_batch < 1 || cfg.max_batch > 65535) return set_error(ALB_E_INVAL, "max_batch must be in [1, 65535]");
+  if (cfg.max_wait_us < 0 || cfg.hbm_budget < 0) return set_error(ALB_E_INVAL, "negative max_wait_us or budget");
+  alb_server s = new (std::nothrow) alb_server_s();
+  if (!s) return set_error(ALB_E_NOMEM, "host allocation failed");
+  s->g = g;
+  s->cfg = cfg;
+  s->lane_budget = (size_t)cfg.hbm_budget / (size_t)cfg.lanes;
+  auto bail = [&](alb_status st) {
+    for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+    delete s;
+    return st;
+  };
+  if (g) {
+    int32_t cnt = 0;
+    alb_status st = alb_graph_members(g, &cnt);
+    if (st != ALB_OK) return bail(st);
+    s->member_n.resize(cnt);
+    for (int32_t i = 0; i < cnt; ++i) {
+      st = alb_graph_member_info(g, i, &s->member_n[i], nullptr, nullptr);
+      if (st != ALB_OK) return bail(st);
+    }
+  } else {
+    if (!cfg.executor || cfg.n_members < 1 || !cfg.member_vertices)
+      return bail(set_error(ALB_E_INVAL, "a server without a graph needs an executor and member_vertices"));
+    s->member_n.assign(cfg.member_vertices, cfg.member_vertices + cfg.n_members);
+    for (int32_t n : s->member_n)
+      if (n < 1) return bail(set_error(ALB_E_INVAL, "member_vertices must be >= 1"));
+  }
+  s->cfg.member_vertices = nullptr;  // not kept
+  if (!cfg.executor) {
+    if (!g) return bail(set_error(ALB_E_INVAL, "graph handle is NULL"));
+    alb_options o;
+    alb_status st = alb_options_init(&o);
+    if (st != ALB_OK) return bail(st);
+    const int wg = cfg.options.wg_size ? cfg.options.wg_size : 256;
+    for (int32_t algo = 0; algo < 2; ++algo) {
+      int res = 0;
+      // also makes g's device current for the streams below
+      st = alb::batch_resident_workgroups(g, algo, wg, &res);
+      if (st != ALB_OK) return bail(st);
+      s->grid[algo] = std::max(1, res / cfg.lanes);
+    }
+    for (int i = 0; i < cfg.lanes; ++i) {
+      hipStream_t x = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+      if (e != hipSuccess) return bail(set_error(ALB_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
+      s->streams.push_back(x);
+    }
+  }
+  try {
+    for (int i = 0; i < cfg.lanes; ++i) s->lanes.emplace_back([s, i] { s->lane_main(i); });
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto &t : s->lanes) t.join();
+    return bail(set_error(ALB_E_NOMEM, "could not start the lane threads"));
+  }
+  *out = s;
+  return ALB_OK;
+}
+
+alb_status alb_server_submit(alb_server s, int32_t algo, int32_t member, int32_t source, int32_t *out,
+                             double timeout_ms, uint64_t *ticket) {
+  if (!s || !out || !ticket) return set_error(ALB_E_INVAL, "NULL argument");
+  if (algo != ALB_ALGO_BFS && algo != ALB_ALGO_SSSP) return set_error(ALB_E_INVAL, "bad algo %d", algo);
+  if (member < 0 || member >= (int32_t)s->member_n.size())
+    return set_error(ALB_E_INVAL, "member %d out of range [0, %zu)", member, s->member_n.size());
+  const int32_t n = s->member_n[member];
+  if (source < 0 || source >= n) return set_error(ALB_E_INVAL, "source %d out of range [0, %d)", source, n);
+  if (!(timeout_ms >= 0)) return set_error(ALB_E_INVAL, "timeout_ms must be >= 0");
+  Request r;
+  r.algo = algo;
+  r.member = member;
+  r.source = source;
+  r.out = out;
+  r.footprint = kBytesPerVertex * (size_t)n + kBytesPerQuery;
+  r.t_submit = Clock::now();
+  r.deadline = timeout_ms > 0 ? r.t_submit + std::chrono::duration_cast<Clock::duration>(
+                                                  std::chrono::duration<double, std::milli>(timeout_ms))
+                              : Clock::time_point::max();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return set_error(ALB_E_INVAL, "server is stopping");
+    if (r.footprint > s->lane_budget) {
+      ++s->st.rejected;
+      return set_error(ALB_E_NOMEM, "request needs %zu workspace bytes, a lane's budget is %zu", r.footprint,
+                       s->lane_budget);
+    }
+    const uint64_t t = s->next_ticket++;
+    s->reqs.emplace(t, r);
+    s->pending.push_back(t);
+    ++s->st.submitted;
+    *ticket = t;
+  }
+  s->cv_work.notify_one();
+  return ALB_OK;
+}
+
+alb_status alb_server_wait(alb_server s, uint64_t ticket, alb_request_info *info) {
+  if (!s) return set_error(ALB_E_INVAL, "server handle is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  // look the ticket up again after every wait: submits can rehash the table
+  auto it = s->reqs.find(ticket);
+  for (;;) {
+    if (it == s->reqs.end()) return set_error(ALB_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second.state == kDone) break;
+    if (it->second.state == kPending && it->second.deadline != Clock::time_point::max()) {
+      const Clock::time_point dl = it->second.deadline;
+      const bool timed_out = s->cv_done.wait_until(lk, dl) == std::cv_status::timeout;
+      it = s->reqs.find(ticket);
+      if (timed_out && it != s->reqs.end() && it->second.state == kPending) {
+        s->pending.remove(ticket);
+        s->complete(it->second, ALB_E_TIMEOUT, Clock::now());
+      }
+    } else {
+      s->cv_done.wait(lk);
+      it = s->reqs.find(ticket);
+    }
+  }
+  const Request r = it->second;
+  s->reqs.erase(it);
+  if (info) {
+    info->status = r.status;
+    info->batch_size = r.batch_size;
+    info->lane = r.lane;
+    info->algo = r.algo;
+    info->queue_ms = r.lane >= 0 ? ms_between(r.t_submit, r.t_dispatch) : ms_between(r.t_submit, r.t_done);
+    info->latency_ms = ms_between(r.t_submit, r.t_done);
+  }
+  if (r.status == ALB_E_TIMEOUT) return set_error(ALB_E_TIMEOUT, "request %llu timed out in the queue",
+                                                  (unsigned long long)ticket);
+  if (r.status == ALB_E_CANCELLED) return set_error(ALB_E_CANCELLED, "request %llu was cancelled",
+                                                    (unsigned long long)ticket);
+  return (alb_status)r.status;
+}
+
+alb_status alb_server_cancel(alb_server s, uint64_t ticket) {
+  if (!s) return set_error(ALB_E_INVAL, "server handle is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return set_error(ALB_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  if (it->second.state != kPending) return set_error(ALB_E_INVAL, "request already dispatched");
+  s->pending.remove(ticket);
+  s->complete(it->second, ALB_E_CANCELLED, Clock::now());
+  s->cv_done.notify_all();
+  return ALB_OK;
+}
+
+alb_status alb_server_drain(alb_server s) {
+  if (!s) return set_error(ALB_E_INVAL, "server handle is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->pending.empty() && s->running == 0; });
+  return ALB_OK;
+}
+
+alb_status alb_server_stats_get(alb_server s, alb_server_stats *st) {
+  if (!s || !st) return set_error(ALB_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *st = s->st;
+  st->pending = (int64_t)s->pending.size();
+  st->running = s->running;
+  return ALB_OK;
+}
+
+alb_status alb_server_destroy(alb_server s) {
+  if (!s) return ALB_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto &t : s->lanes) t.join();
+  for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+  delete s;
+  return ALB_OK;
+}
+
+}  // extern "C"

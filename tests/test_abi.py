@@ -27,6 +27,15 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(alb_[a-z_]+)\s*\(", text)))
 
 
+def test_binding_covers_every_declared_symbol(alb):
+    """The Python binding gives each C entry point a signature."""
+    import inspect
+
+    src = inspect.getsource(alb)
+    for name in declared_functions():
+        assert '"%s"' % name in src, name
+
+
 def test_every_declared_symbol_is_exported(alb):
     names = declared_functions()
     assert len(names) >= 11
@@ -59,6 +68,32 @@ int main(void) {
     O, S = alb.Options, alb.Stats
     assert vals == [ctypes.sizeof(O), ctypes.sizeof(S), O.stream.offset, O.out_on_device.offset,
                     S.device_ms.offset, S.pushes.offset]
+
+
+def test_server_struct_layouts_match_c(alb):
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "alb.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(alb_server_config), offsetof(alb_server_config, options),
+         offsetof(alb_server_config, executor), offsetof(alb_server_config, n_members),
+         offsetof(alb_server_config, member_vertices), sizeof(alb_request_info),
+         offsetof(alb_request_info, latency_ms), sizeof(alb_server_stats), offsetof(alb_server_stats, running),
+         offsetof(alb_server_stats, busy_ms));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe])
+        vals = [int(x) for x in subprocess.check_output([exe]).split()]
+    C, R, S = alb.ServerConfig, alb.RequestInfo, alb.ServerStats
+    assert vals == [ctypes.sizeof(C), C.options.offset, C.executor.offset, C.n_members.offset,
+                    C.member_vertices.offset, ctypes.sizeof(R), R.latency_ms.offset, ctypes.sizeof(S),
+                    S.running.offset, S.busy_ms.offset]
 
 
 def test_options_init_defaults(alb):

@@ -24,6 +24,13 @@ def hubgraph():
     return gg.hub_graph(40000, hubs, 3, seed=11)
 
 
+def twc_chunk(nf, wgs, wg):
+    """Worklist entries a workgroup claims at a time: wg, or whole wavefronts
+    enough for two claims per workgroup when the worklist is short."""
+    per = -(-nf // (2 * wgs))
+    return min(wg, max(64, -(-per // 64) * 64))
+
+
 def check_round(alb, g, dg, frontier, **opts):
     r = alb.trace_round(dg, frontier, off=g.off, **opts)
     st = r["stats"]
@@ -50,8 +57,9 @@ def check_round(alb, g, dg, frontier, **opts):
     assert np.array_equal(r["edge_thread"][pos], thr.astype(np.int32))
     assert np.array_equal(src, np.repeat(work, deg[work]))
     # TWC: every other edge stays inside one workgroup, the same for all the
-    # vertices of a B-entry chunk of the worklist (chunks are claimed
-    # dynamically); wavefront-bin vertices inside one wavefront
+    # vertices of a chunk of the worklist (chunks are claimed dynamically);
+    # wavefront-bin vertices inside one wavefront
+    C = twc_chunk(len(frontier), T // wg, wg)
     chunk_wg = {}
     for i, v in enumerate(frontier):
         b = r["bins"][i]
@@ -60,7 +68,7 @@ def check_round(alb, g, dg, frontier, **opts):
         th = r["edge_thread"][g.off[v]:g.off[v + 1]]
         wgs = np.unique(th // wg)
         assert len(wgs) == 1, (i, v, b)
-        assert chunk_wg.setdefault(i // wg, int(wgs[0])) == int(wgs[0]), (i, v)
+        assert chunk_wg.setdefault(i // C, int(wgs[0])) == int(wgs[0]), (i, v)
         if b == 1:
             assert len(np.unique(th // 64)) == 1
     # pushes: every processed edge pushed its destination once

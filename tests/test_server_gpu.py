@@ -1,0 +1,90 @@
+"""The serving loop on the GPU: a mix of BFS and SSSP requests on a graph set,
+submitted faster than they complete, so that they batch and the lanes'
+batches overlap on the device; every result equals the oracle's, and the
+same request alone gives the same result as in the mix."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def alb():
+    from paper_1911_09135_amd import alb as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def members():
+    return [
+        gg.rmat(13, seed=201).with_weights(31),
+        gg.rmat(11, seed=202).with_weights(32),
+        gg.zipf(1 << 14, 1.9, 1 << 12, seed=5).with_weights(4),
+        gg.star(3000, w=gg.uniform_ints(3000, 100, 6) + 1),
+        gg.path(500, w=gg.uniform_ints(499, 100, 7) + 1),
+    ]
+
+
+@pytest.fixture(scope="module")
+def gset(alb, members):
+    return alb.GraphSet(members)
+
+
+def requests(members, count, seed):
+    mb, src = gg.query_sources(members, count, seed=seed)
+    rng = np.random.default_rng(seed)
+    algo = np.where(rng.random(count) < 0.5, "bfs", "sssp")
+    return list(zip(algo, mb.tolist(), src.tolist()))
+
+
+def reference(members, algo, m, s, cache={}):
+    key = (algo, m, s)
+    if key not in cache:
+        cache[key] = (oracle.bfs if algo == "bfs" else oracle.sssp)(members[m], s)
+    return cache[key]
+
+
+@pytest.mark.parametrize("lanes,max_batch", [(1, 256), (2, 256), (3, 7)])
+def test_mix_matches_oracle(alb, gset, members, lanes, max_batch):
+    reqs = requests(members, 120, seed=lanes)
+    with alb.Server(gset, lanes=lanes, max_batch=max_batch) as srv:
+        tickets = [srv.submit(a, m, s) for a, m, s in reqs]
+        sizes = []
+        for t, (a, m, s) in zip(tickets, reqs):
+            out, info = srv.wait(t)
+            assert np.array_equal(out, reference(members, a, m, s)), (a, m, s)
+            sizes.append(info["batch_size"])
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert max(sizes) > 1  # requests queued behind a running batch were batched
+    assert max(sizes) <= max_batch
+
+
+def test_same_alone_and_in_the_mix(alb, gset, members):
+    reqs = requests(members, 40, seed=11)
+    with alb.Server(gset, lanes=2) as srv:
+        alone = []
+        for a, m, s in reqs:
+            out, info = srv.wait(srv.submit(a, m, s))
+            assert info["batch_size"] == 1
+            alone.append(out)
+        tickets = [srv.submit(a, m, s) for a, m, s in reqs]
+        for t, ref in zip(tickets, alone):
+            out, _ = srv.wait(t)
+            assert np.array_equal(out, ref)
+
+
+def test_small_budget_splits_batches(alb, gset, members):
+    n0 = members[0].n
+    budget = 2 * 2 * (44 * n0 + 64)  # two lanes, two requests of member 0 per batch
+    with alb.Server(gset, lanes=2, hbm_budget=budget) as srv:
+        reqs = [("sssp", 0, int(s)) for s in gg.query_sources([members[0]], 9, seed=2)[1]]
+        tickets = [srv.submit(*r) for r in reqs]
+        for t, (a, m, s) in zip(tickets, reqs):
+            out, info = srv.wait(t)
+            assert info["batch_size"] <= 2
+            assert np.array_equal(out, reference(members, a, m, s))
