@@ -53,7 +53,8 @@ struct Workspace {
   uint32_t hint_cap = 0;
   int32_t n = 0;
   bool busy = false;
-  int32_t *q0 = nullptr, *q1 = nullptr, *hint = nullptr, *labels = nullptr;
+  int32_t *q0 = nullptr, *q1 = nullptr, *labels = nullptr;
+  int2 *hint = nullptr;
   int4 *huge_rec = nullptr;
   unsigned long long *bar = nullptr, *word = nullptr, *acc = nullptr;
   float *rank = nullptr;
@@ -89,7 +90,8 @@ struct BatchWs {
   int32_t nq_cap = 0;
   bool busy = false;
   unsigned long long *q0 = nullptr, *q1 = nullptr, *word = nullptr, *bar = nullptr;
-  int32_t *out32 = nullptr, *hint = nullptr, *qsrc = nullptr, *qn = nullptr;
+  int32_t *out32 = nullptr, *qsrc = nullptr, *qn = nullptr;
+  int2 *hint = nullptr;
   int4 *huge_rec = nullptr;
   long long *qoff = nullptr, *qthr = nullptr, *qlbase = nullptr;
   int32_t **qout = nullptr;

@@ -31,7 +31,8 @@ constexpr size_t kBarWords = (size_t)kBarGroups + (size_t)kBarStride * kBarMaxGr
 
 // Huge-worklist chunk index: edge index k of the round's huge edges lies in
 // chunk k >> hint_shift; hint[c] holds the huge-list slot that owns the first
-// edge of chunk c.  The shift is at least kHintMinShift.
+// edge of chunk c and the end of that slot's edge range.  The shift is at
+// least kHintMinShift.
 constexpr int kHintMinShift = 10;
 // Adaptive threshold for rounds whose worklist cannot give every launched
 // thread an entry: any vertex of at least a wavefront's worth of edges goes to
@@ -50,7 +51,7 @@ struct Ctl {
   uint32_t rounds;                // rounds completed (written by workgroup 0)
   uint32_t pad0;
   unsigned long long dangling[2]; // PageRank: rank mass without out-edges (fixed point), iteration it in [it & 1]
-  alignas(256) uint32_t chunk[3]; // next worklist chunk to claim in phase 1 of round r: [r % 3]
+  alignas(256) unsigned long long chunk[3]; // worklist entries claimed in phase 1 of round r: [r % 3]
   alignas(256) uint32_t abort;    // a barrier wait timed out; every workgroup leaves
   uint32_t diag_round;            // round of the wait that timed out
   unsigned long long diag_seen;   // generation it observed
@@ -87,7 +88,7 @@ struct Args {
   void *q0;             // worklists (double buffered): int32 vertex ids, or (query << 32 | vertex) for a batch
   void *q1;
   int4 *huge_rec;       // huge list (Algorithm 1 `work`): per slot {prefixWork entry, CSR start, vertex, source value}
-  int32_t *hint;        // chunk index of the huge edges
+  int2 *hint;           // chunk index of the huge edges: {slot owning the chunk's first edge, end of its edges}
   uint32_t hint_cap;
   unsigned long long *bar;  // grid barrier words (kBarWords)
   Ctl *ctl;

@@ -24,13 +24,6 @@ def hubgraph():
     return gg.hub_graph(40000, hubs, 3, seed=11)
 
 
-def twc_chunk(nf, wgs, wg):
-    """Worklist entries a workgroup claims at a time: wg, or whole wavefronts
-    enough for two claims per workgroup when the worklist is short."""
-    per = -(-nf // (2 * wgs))
-    return min(wg, max(64, -(-per // 64) * 64))
-
-
 def check_round(alb, g, dg, frontier, **opts):
     r = alb.trace_round(dg, frontier, off=g.off, **opts)
     st = r["stats"]
@@ -56,11 +49,10 @@ def check_round(alb, g, dg, frontier, **opts):
     src, pos, thr = oracle.lb_edges(work, r["prefix"], g.off, T)
     assert np.array_equal(r["edge_thread"][pos], thr.astype(np.int32))
     assert np.array_equal(src, np.repeat(work, deg[work]))
-    # TWC: every other edge stays inside one workgroup, the same for all the
-    # vertices of a chunk of the worklist (chunks are claimed dynamically);
-    # wavefront-bin vertices inside one wavefront
-    C = twc_chunk(len(frontier), T // wg, wg)
-    chunk_wg = {}
+    # TWC: every other edge of a vertex stays inside one workgroup (runs of
+    # worklist entries are claimed dynamically, so which workgroup is not
+    # fixed); wavefront-bin vertices inside one wavefront
+    wg_of = np.full(len(frontier), -1)
     for i, v in enumerate(frontier):
         b = r["bins"][i]
         if b == 3 or deg[v] == 0:
@@ -68,9 +60,13 @@ def check_round(alb, g, dg, frontier, **opts):
         th = r["edge_thread"][g.off[v]:g.off[v + 1]]
         wgs = np.unique(th // wg)
         assert len(wgs) == 1, (i, v, b)
-        assert chunk_wg.setdefault(i // C, int(wgs[0])) == int(wgs[0]), (i, v)
+        wg_of[i] = int(wgs[0])
         if b == 1:
             assert len(np.unique(th // 64)) == 1
+    # claims are runs of at least one wavefront's worth of consecutive entries
+    # (the last one may be short): the workgroup changes at most that often
+    seq = wg_of[wg_of >= 0]
+    assert int((seq[1:] != seq[:-1]).sum()) <= -(-len(frontier) // 64)
     # pushes: every processed edge pushed its destination once
     dsts = np.concatenate([g.col[g.off[v]:g.off[v + 1]] for v in frontier]) if len(frontier) else np.zeros(0)
     assert np.array_equal(np.sort(r["next"]), np.sort(dsts))
