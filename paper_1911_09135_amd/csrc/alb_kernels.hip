@@ -251,11 +251,11 @@ struct Smem {
   int32_t pos[kU * B];  // thread-bin gather: CSR position, source value and source (batch: query) of each edge
   V sv[kU * B];
   int32_t src[(Op::kNeedSrc || M) ? kU * B : 1];
-  unsigned long long rk[B];  // workgroup and wavefront bins: start rank of each packed edge list
   int32_t wsum[B / kWave];
-  unsigned long long wsum64[B / kWave];
   unsigned long long ured[B / kWave][5];
   unsigned long long dred[B / kWave];
+  int32_t owner, obeg, odeg, ov;
+  V osv;
   int32_t flag;
   uint32_t ticket, members;  // persistent launch: this workgroup's ticket and the member count
   unsigned long long cbase;  // phase 1: first worklist entry of the current claim
@@ -504,78 +504,6 @@ __device__ __forceinline__ void block_exscan(int32_t x, int32_t &excl, int32_t &
 // Phase 1: inspection (Algorithm 1) fused with the TWC bins.
 // ---------------------------------------------------------------------------
 
-// Packed key of the bins' scans: (vertex count << 53) | edge count.
-constexpr unsigned long long kOne53 = 1ull << 53;
-constexpr unsigned long long kLow53 = kOne53 - 1;
-
-template <int B>
-__device__ __forceinline__ void block_exscan64(unsigned long long x, unsigned long long &excl,
-                                               unsigned long long &total, unsigned long long *wsum) {
-  const uint32_t lane = lane_id();
-  const int w = threadIdx.x / kWave;
-  unsigned long long incl = x;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const unsigned long long y = __shfl_up(incl, d);
-    if ((int)lane >= d) incl += y;
-  }
-  if (lane == kWave - 1) wsum[w] = incl;
-  __syncthreads();
-  unsigned long long before = 0, tot = 0;
-#pragma unroll
-  for (int j = 0; j < B / kWave; ++j) {
-    const unsigned long long s = wsum[j];
-    before += (j < w) ? s : 0ull;
-    tot += s;
-  }
-  excl = before + incl - x;
-  total = tot;
-  __syncthreads();
-}
-
-// Order one wavefront's LDS writes before its lanes read each other's.
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Edges of K edge lists laid end to end (E edges in all), described in LDS
-// at [base, base + K): start rank, CSR start, source value and source
-// (batch: query).  W lanes (the workgroup or one wavefront) stride them,
-// kU * W edge slots per pass; slot idx belongs to the last list whose rank is
-// <= idx.
-template <int W, int B, class Op, bool M>
-__device__ __forceinline__ void packed_edges(Smem<B, Op, M> &sm, uint32_t base, uint32_t K, unsigned long long E,
-                                             int me, const Op &op, const Args &a, uint32_t tag, int round,
-                                             Pusher<Entry<M>> &pu, Acc &acc, int32_t gt) {
-  using V = typename Op::val_t;
-  for (unsigned long long done = 0; done < E; done += (unsigned long long)kU * W) {
-    bool act[kU];
-    int32_t pos[kU], src[kU];
-    V s[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const unsigned long long idx = done + (unsigned long long)u * W + (unsigned long long)me;
-      act[u] = idx < E;
-      uint32_t lo = 0, hi = act[u] ? K : 1u;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (sm.rk[base + mid] <= idx)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      const uint32_t k = base + lo;
-      pos[u] = sm.pos[k] + (int32_t)(idx - sm.rk[k]);
-      s[u] = sm.sv[k];
-      src[u] = 0;
-      if constexpr (Op::kNeedSrc || M) src[u] = sm.src[k];
-    }
-    edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
-  }
-}
-
 // Worklist entries per claim: B, unless the worklist would give a workgroup
 // fewer than two claims; then whole wavefronts' worth, just enough for two
 // claims per workgroup, so that a short worklist still reaches every
@@ -602,32 +530,33 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
   uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
   // Workgroups take runs of consecutive worklist entries one at a time, so a
   // run that takes long does not hold up work queued behind it.  The first
-  // run of workgroup g is fixed (entries [g * C0, (g + 1) * C0)), so it needs
-  // no atomic; later runs are claimed from a counter, each as long as the
-  // entries still unclaimed suggest (guided self-scheduling): B while plenty
-  // remain, then fewer whole wavefronts, so that the phase ends with short
-  // runs and the workgroups reach the barrier together.  (The loop body's
-  // workgroup barriers separate one claim's reads of sm.cbase and sm.clen
-  // from the next claim's writes.)
+  // run of workgroup g is fixed (entries [g * C0, (g + 1) * C0)) and needs no
+  // atomic; later runs are claimed from a counter over the entries beyond
+  // those, each sized from the remainder the previous claim's atomic
+  // returned (guided self-scheduling): B while plenty remain, then fewer
+  // whole wavefronts, so that the phase ends with short runs and the
+  // workgroups reach the barrier together.  The counter is only ever
+  // touched by the atomic (a plain load of a contended counter is slow).
+  // (The loop body's workgroup barriers separate one claim's reads of
+  // sm.cbase and sm.clen from the next claim's writes.)
   const uint32_t C0 = twc_chunk(nF, gr.n, B);
-  const unsigned long long S = (unsigned long long)gr.n * C0;  // entries covered by the first runs
+  const unsigned long long S = (unsigned long long)gr.n * C0;  // entries of the fixed first runs
+  unsigned long long next = (unsigned long long)gr.id * C0, seen = S;  // thread 0's claim state
+  uint32_t len = C0;
   bool first = true;
   for (;;) {
     if (tid == 0) {
-      unsigned long long b = ~0ull;
-      uint32_t c = 0;
-      if (first) {
-        b = (unsigned long long)gr.id * C0;
-        c = C0;
-      } else if (S < (unsigned long long)nF) {
-        const unsigned long long seen = S + ld_relaxed(claim);
-        if (seen < (unsigned long long)nF) {
-          c = twc_chunk(nF - (uint32_t)seen, gr.n, B);
-          b = S + add_relaxed(claim, (unsigned long long)c);
+      if (!first) {
+        if (S >= (unsigned long long)nF) {
+          next = ~0ull;  // the fixed runs covered the worklist
+        } else {
+          len = twc_chunk(seen < nF ? nF - (uint32_t)seen : 0u, gr.n, B);
+          next = S + add_relaxed(claim, (unsigned long long)len);
+          seen = next + len;
         }
       }
-      sm.cbase = b;
-      sm.clen = c;
+      sm.cbase = next;
+      sm.clen = len;
     }
     first = false;
     __syncthreads();
@@ -672,59 +601,62 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
     acc.edges_twc += (unsigned long long)deg;
     prof_mark(a, acc, kProfInspect, pt);
 
-    // workgroup bin: the claim's vertices of degree >= c_wg, their edge lists
-    // laid end to end and strided by the whole workgroup, kU * B edges per
-    // pass, so that several short lists share a pass.  Lane slot idx finds
-    // its vertex by bisection over the lists' starts in LDS.
-    {
-      const bool inb = deg > 0 && deg >= a.c_wg;
-      unsigned long long excl, total;
-      block_exscan64<B>(inb ? kOne53 | (unsigned long long)(uint32_t)deg : 0ull, excl, total, sm.wsum64);
-      const uint32_t K = (uint32_t)(total >> 53);
-      if (K) {
-        if (inb) {
-          const uint32_t slot = (uint32_t)(excl >> 53);
-          sm.rk[slot] = excl & kLow53;
-          sm.pos[slot] = beg;
-          sm.sv[slot] = sv;
-          if constexpr (Op::kNeedSrc || M) sm.src[slot] = M ? q : v;
-          deg = 0;
+    // workgroup bin: the whole workgroup strides one vertex's edges
+    for (;;) {
+      if (tid == 0) sm.owner = -1;
+      __syncthreads();
+      if (deg > 0 && deg >= a.c_wg) sm.owner = tid;  // any one claimant wins
+      __syncthreads();
+      const int32_t o = sm.owner;
+      if (o < 0) break;
+      if (tid == o) {
+        sm.obeg = beg;
+        sm.odeg = deg;
+        sm.osv = sv;
+        sm.ov = M ? q : v;
+        deg = 0;
+      }
+      __syncthreads();
+      const int32_t ob = sm.obeg, od = sm.odeg, ov = sm.ov;
+      const V os = sm.osv;
+      for (int32_t j0 = 0; j0 < od; j0 += kU * B) {
+        bool act[kU];
+        int32_t pos[kU], src[kU];
+        V s[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int32_t j = j0 + u * B + tid;
+          act[u] = j < od;
+          pos[u] = ob + j;
+          s[u] = os;
+          src[u] = ov;
         }
-        __syncthreads();
-        packed_edges<B, B, Op, M>(sm, 0, K, total & kLow53, tid, op, a, tag, round, pu, acc, gt);
-        __syncthreads();  // the LDS lists are reused below
+        edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       }
     }
 
     prof_mark(a, acc, kProfWgBin, pt);
-    // wavefront bin: the same packing inside each wavefront, for its lanes'
-    // vertices of degree >= c_wave, kU * 64 edges per pass; LDS lists at
-    // [64 * wave, 64 * wave + 64)
-    {
-      const bool inb = deg > 0 && deg >= a.c_wave;
-      const unsigned long long key = inb ? kOne53 | (unsigned long long)(uint32_t)deg : 0ull;
-      unsigned long long incl = key;
+    // wavefront bin: one wavefront strides one vertex's edges
+    for (;;) {
+      const unsigned long long mm = __ballot(deg > 0 && deg >= a.c_wave);
+      if (mm == 0ull) break;
+      const int ld = __ffsll(mm) - 1;
+      const int32_t ob = __shfl(beg, ld), od = __shfl(deg, ld), ov = __shfl(M ? q : v, ld);
+      const V os = __shfl(sv, ld);
+      if ((int)lane == ld) deg = 0;
+      for (int32_t j0 = 0; j0 < od; j0 += kU * kWave) {
+        bool act[kU];
+        int32_t pos[kU], src[kU];
+        V s[kU];
 #pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) {
-        const unsigned long long y = __shfl_up(incl, d);
-        if ((int)lane >= d) incl += y;
-      }
-      const unsigned long long total = __shfl(incl, kWave - 1);
-      const uint32_t K = (uint32_t)(total >> 53);
-      if (K) {
-        const uint32_t base = (uint32_t)(tid / kWave) * kWave;
-        if (inb) {
-          const unsigned long long excl = incl - key;
-          const uint32_t slot = base + (uint32_t)(excl >> 53);
-          sm.rk[slot] = excl & kLow53;
-          sm.pos[slot] = beg;
-          sm.sv[slot] = sv;
-          if constexpr (Op::kNeedSrc || M) sm.src[slot] = M ? q : v;
-          deg = 0;
+        for (int u = 0; u < kU; ++u) {
+          const int32_t j = j0 + u * kWave + (int32_t)lane;
+          act[u] = j < od;
+          pos[u] = ob + j;
+          s[u] = os;
+          src[u] = ov;
         }
-        wave_sync_lds();
-        packed_edges<kWave, B, Op, M>(sm, base, K, total & kLow53, (int)lane, op, a, tag, round, pu, acc, gt);
-        wave_sync_lds();
+        edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, gt);
       }
     }
 
