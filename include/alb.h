@@ -227,10 +227,14 @@ alb_status alb_batch_plan_destroy(alb_plan p);
 alb_status alb_autotune(alb_graph g, int32_t algo, int32_t member, int32_t nsources, const int32_t *sources,
                         const alb_options *base, alb_options *tuned, double *best_ms);
 
-/* Autotuner for a batch: tunes every member the batch uses (at most 4 of its
- * sources each, cached as above), then picks the one workgroup size with the
- * smallest total estimated time and returns it in *tuned and each query's best
- * threshold at that size in thresholds[count], ready for the batch calls. */
+/* Autotuner for a batch: times the batch itself (outputs discarded), first
+ * with one threshold for every query (2^8, 2^10, 2^12 or 2^14) and
+ * workgroup size 256 or 1024, then, for the queries' degree signatures with
+ * the most edges (up to 8), a threshold 4x lower or higher for that group
+ * alone, kept if the batch gets at least 1 % faster.  Returns the workgroup
+ * size in *tuned and each query's threshold in thresholds[count], ready for
+ * the batch calls.  Cached per process by the batch's multiset of member
+ * signatures. */
 alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
                               const int32_t *sources, const alb_options *base, alb_options *tuned,
                               int64_t *thresholds);

@@ -948,6 +948,8 @@ struct TuneCand {
 // best candidate per workgroup size, per key
 std::mutex g_tune_mu;
 std::map<TuneKey, std::vector<TuneCand>> g_tune;
+// batch tuning: (algo, the batch's signatures) -> (workgroup size, threshold per signature)
+std::map<std::pair<int, std::vector<TuneKey>>, std::pair<int32_t, std::map<TuneKey, int64_t>>> g_tune_batch;
 
 int ilog2(int64_t x) { return x > 0 ? 63 - __builtin_clzll((unsigned long long)x) : -1; }
 
@@ -957,21 +959,20 @@ TuneKey tune_key(alb_graph g, OpKind op, int32_t member) {
 }
 
 // Median device time of a batch of `k` queries on one member under options o.
-alb_status time_candidate(alb_graph g, OpKind op, int32_t member, int32_t k, const int32_t *sources,
-                          const alb_options &o, BatchWs *ws, double *ms) {
-  std::vector<int32_t> mb((size_t)k, member);
-  std::vector<int32_t *> outs((size_t)k, nullptr);
-  for (int32_t q = 0; q < k; ++q) outs[q] = (int32_t *)ws;  // placeholder: outputs stay on the device
+// Median device time (3 runs after a warm-up) of a batch under options o and
+// optional per-query thresholds; outputs go to the workspace's staging area.
+alb_status time_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
+                      const int64_t *thresholds, const alb_options &o, BatchWs *ws, double *ms) {
+  std::vector<int32_t *> outs((size_t)count, (int32_t *)ws);  // placeholders, replaced below
   alb_options oo = o;
   oo.out_on_device = 1;
   BatchJob j;
-  alb_status s = prepare_batch(g, op, k, mb.data(), sources, outs.data(), nullptr, &oo, j);
+  alb_status s = prepare_batch(g, op, count, members, sources, outs.data(), thresholds, &oo, j);
   if (s != ALB_OK) return s;
   const BatchNeeds nd = batch_needs(j);
   if (ws->lab_cap < nd.labels || ws->qcap < nd.qcap || ws->hint_cap < nd.hint_cap || ws->nq_cap < nd.nq)
     return fail(ALB_E_INVAL, "tuning workspace too small");
-  // outputs go to the workspace's own staging area, query by query
-  for (int32_t q = 0; q < k; ++q) j.qout[q] = ws->out32 + j.qlbase[q];
+  for (int32_t q = 0; q < count; ++q) j.qout[q] = ws->out32 + j.qlbase[q];
   s = upload_batch(j, ws);
   if (s != ALB_OK) return s;
   double t[4];
@@ -992,6 +993,31 @@ alb_status time_candidate(alb_graph g, OpKind op, int32_t member, int32_t k, con
   return ALB_OK;
 }
 
+alb_status time_candidate(alb_graph g, OpKind op, int32_t member, int32_t k, const int32_t *sources,
+                          const alb_options &o, BatchWs *ws, double *ms) {
+  std::vector<int32_t> mb((size_t)k, member);
+  return time_batch(g, op, k, mb.data(), sources, nullptr, o, ws, ms);
+}
+
+// A workspace big enough for `count` queries of this batch.
+alb_status batch_scratch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
+                         const alb_options &base, BatchWs *ws) {
+  alb_options probe = base;
+  probe.out_on_device = 1;
+  probe.wg_size = 1024;
+  BatchJob pj;
+  std::vector<int32_t *> dummy((size_t)count, (int32_t *)&pj);
+  alb_status s = prepare_batch(g, op, count, members, sources, dummy.data(), nullptr, &probe, pj);
+  if (s != ALB_OK) return s;
+  s = bws_fill(ws, batch_needs(pj));
+  if (s != ALB_OK) {
+    std::string keep = g_err;
+    ws->release();
+    g_err = keep;
+  }
+  return s;
+}
+
 // Tune one member (cached by its degree signature): for each workgroup size
 // the fastest of the candidate thresholds; with `cutoffs`, then also two TWC
 // cutoff pairs at the winner.
@@ -1006,23 +1032,10 @@ alb_status tune_member(alb_graph g, OpKind op, int32_t member, int32_t k, const 
       return ALB_OK;
     }
   }
-  // one workspace sized for the largest candidate (wg 1024, no dedup change)
-  alb_options probe = base;
-  probe.out_on_device = 1;
-  probe.wg_size = 1024;
-  BatchJob pj;
   std::vector<int32_t> mb((size_t)k, member);
-  std::vector<int32_t *> dummy((size_t)k, (int32_t *)&pj);
-  alb_status s = prepare_batch(g, op, k, mb.data(), sources, dummy.data(), nullptr, &probe, pj);
-  if (s != ALB_OK) return s;
   BatchWs ws;
-  s = bws_fill(&ws, batch_needs(pj));
-  if (s != ALB_OK) {
-    std::string keep = g_err;
-    ws.release();
-    g_err = keep;
-    return s;
-  }
+  alb_status s = batch_scratch(g, op, k, mb.data(), sources, base, &ws);
+  if (s != ALB_OK) return s;
   std::vector<TuneCand> best;
   static const int32_t wgs[] = {256, 1024};
   // the paper's threshold plateau (2^8 .. 2^18) sampled every factor of 4,
@@ -1533,31 +1546,108 @@ alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const in
   if (s != ALB_OK) return s;
   const OpKind op = algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP;
   const int32_t nmem = (int32_t)g->mem_n.size();
-  std::map<int32_t, std::vector<int32_t>> srcs;  // member -> its sources in the batch
-  for (int32_t q = 0; q < count; ++q) {
+  for (int32_t q = 0; q < count; ++q)
     if (members[q] < 0 || members[q] >= nmem) return fail(ALB_E_INVAL, "members[%d] out of range", q);
-    srcs[members[q]].push_back(sources[q]);
+  // the batch's members grouped by degree signature; the cache key is the
+  // batch's multiset of signatures
+  std::map<TuneKey, std::vector<int32_t>> groups;  // signature -> queries
+  std::map<TuneKey, int64_t> group_edges;
+  for (int32_t q = 0; q < count; ++q) {
+    const TuneKey k = tune_key(g, op, members[q]);
+    groups[k].push_back(q);
+    group_edges[k] += g->mem_m[members[q]];
   }
-  // per member, per workgroup size, the best threshold; the batch takes the
-  // workgroup size with the smallest total (each member's time scaled by its
-  // share of the batch)
-  std::map<int32_t, std::vector<TuneCand>> res;
-  double tot[2] = {0, 0};
-  for (auto &kv : srcs) {
-    const int32_t k = (int32_t)std::min<size_t>(kv.second.size(), 4);
-    std::vector<TuneCand> r;
-    s = tune_member(g, op, kv.first, k, kv.second.data(), b, false, &r);
-    if (s != ALB_OK) return s;
-    for (int i = 0; i < 2; ++i) tot[i] += r[i].ms * (double)kv.second.size() / k;
-    res[kv.first] = r;
+  std::vector<TuneKey> sig;
+  for (auto &kv : groups)
+    for (size_t i = 0; i < kv.second.size(); ++i) sig.push_back(kv.first);
+  const auto ckey = std::make_pair((int)op, sig);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_batch.find(ckey);
+    if (it != g_tune_batch.end()) {
+      b.mode = ALB_MODE_ALB;
+      b.wg_size = it->second.first;
+      b.wave_cutoff = 64;
+      b.wg_cutoff = b.wg_size;
+      b.huge_threshold = ALB_THRESHOLD_DEFAULT;
+      std::map<TuneKey, int64_t> thr = it->second.second;
+      for (int32_t q = 0; q < count; ++q) thresholds[q] = thr[tune_key(g, op, members[q])];
+      *tuned = b;
+      return ALB_OK;
+    }
   }
-  const int pick = tot[0] <= tot[1] ? 0 : 1;
+  BatchWs ws;
+  s = batch_scratch(g, op, count, members, sources, b, &ws);
+  if (s != ALB_OK) return s;
+  std::vector<int64_t> thr((size_t)count);
+  auto run = [&](int32_t wg, double *ms) {
+    alb_options o = b;
+    o.mode = ALB_MODE_ALB;
+    o.wg_size = wg;
+    o.wave_cutoff = 64;
+    o.wg_cutoff = wg;
+    o.grid_wgs = 0;
+    return time_batch(g, op, count, members, sources, thr.data(), o, &ws, ms);
+  };
+  // stage 1: one threshold for every query, over the paper's plateau
+  // (2^8 .. 2^18, every factor of 4 up to 2^14) and both workgroup sizes
+  static const int32_t wgs[] = {256, 1024};
+  static const int64_t thrs[] = {256, 1024, 4096, 16384};
+  double best = 1e30;
+  int32_t best_wg = 256;
+  int64_t best_t = 1024;
+  for (int32_t wg : wgs) {
+    for (int64_t t : thrs) {
+      std::fill(thr.begin(), thr.end(), t);
+      double ms = 0;
+      s = run(wg, &ms);
+      if (s != ALB_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_wg = wg;
+        best_t = t;
+      }
+    }
+    if (s != ALB_OK) break;
+  }
+  // stage 2: per degree signature, largest edge share first (at most 8
+  // groups), try a threshold 4x lower and 4x higher for that group alone; a
+  // change must gain at least 1 %
+  std::map<TuneKey, int64_t> gthr;
+  for (auto &kv : groups) gthr[kv.first] = best_t;
+  if (s == ALB_OK) {
+    std::vector<std::pair<int64_t, TuneKey>> order;
+    for (auto &kv : group_edges) order.push_back({-kv.second, kv.first});
+    std::sort(order.begin(), order.end());
+    for (size_t gi = 0; gi < order.size() && gi < 8 && s == ALB_OK; ++gi) {
+      const TuneKey &k = order[gi].second;
+      const int64_t cur = gthr[k];
+      for (int64_t t : {cur / 4, cur * 4}) {
+        if (t < 64 || t > ((int64_t)1 << 20)) continue;
+        for (int32_t q = 0; q < count; ++q) thr[q] = gthr[tune_key(g, op, members[q])];
+        for (int32_t q : groups[k]) thr[q] = t;
+        double ms = 0;
+        s = run(best_wg, &ms);
+        if (s != ALB_OK) break;
+        if (ms < 0.99 * best) {
+          best = ms;
+          gthr[k] = t;
+        }
+      }
+    }
+  }
+  ws.release();
+  if (s != ALB_OK) return s;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_batch[ckey] = std::make_pair(best_wg, gthr);
+  }
   b.mode = ALB_MODE_ALB;
-  b.wg_size = res.begin()->second[pick].wg;
+  b.wg_size = best_wg;
   b.wave_cutoff = 64;
-  b.wg_cutoff = b.wg_size;
+  b.wg_cutoff = best_wg;
   b.huge_threshold = ALB_THRESHOLD_DEFAULT;
-  for (int32_t q = 0; q < count; ++q) thresholds[q] = res[members[q]][pick].threshold;
+  for (int32_t q = 0; q < count; ++q) thresholds[q] = gthr[tune_key(g, op, members[q])];
   *tuned = b;
   return ALB_OK;
 }
@@ -1565,6 +1655,7 @@ alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const in
 alb_status alb_autotune_reset(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.clear();
+  g_tune_batch.clear();
   return ALB_OK;
 }
 

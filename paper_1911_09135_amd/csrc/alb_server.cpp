@@ -30,10 +30,13 @@ constexpr size_t kBytesPerQuery = 64;
 
 enum { kPending = 0, kRunning = 1, kDone = 2 };
 
+constexpr int64_t kMaxPositions = 0xffffffffLL;
+
 struct Request {
   int32_t algo = 0, member = 0, source = 0;
   int32_t *out = nullptr;
   size_t footprint = 0;
+  int64_t edges = 0;  // edges of its member
   Clock::time_point t_submit, t_dispatch, t_done, deadline;
   int32_t state = kPending;
   int32_t status = ALB_OK;
@@ -50,6 +53,7 @@ struct alb_server_s {
   alb_graph g = nullptr;
   alb_server_config cfg;
   std::vector<int32_t> member_n;
+  std::vector<int64_t> member_m;
   size_t lane_budget = 0;
   int grid[2] = {0, 0};  // workgroups per lane, by algo
   std::vector<hipStream_t> streams;
@@ -111,8 +115,11 @@ struct alb_server_s {
       // expire overdue requests, then take the oldest request's algorithm and
       // every queued request of it, in order, that still fits the batch
       const Clock::time_point now = Clock::now();
+      // a batch also keeps its vertex and edge totals below 2^32 - 1 (the
+      // device's worklist positions are 32-bit)
       int32_t algo = -1;
       size_t foot = 0;
+      int64_t labels = 0, edges = 0;
       batch.clear();
       bool expired = false;
       for (auto it = pending.begin(); it != pending.end();) {
@@ -124,8 +131,11 @@ struct alb_server_s {
           continue;
         }
         if (algo < 0) algo = r.algo;
-        if (r.algo == algo && (int)batch.size() < cfg.max_batch && foot + r.footprint <= lane_budget) {
+        if (r.algo == algo && (int)batch.size() < cfg.max_batch && foot + r.footprint <= lane_budget &&
+            labels + member_n[r.member] < kMaxPositions && edges + r.edges < kMaxPositions) {
           foot += r.footprint;
+          labels += member_n[r.member];
+          edges += r.edges;
           batch.push_back(*it);
           r.state = kRunning;
           r.t_dispatch = now;
@@ -210,14 +220,16 @@ alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_ser
     alb_status st = alb_graph_members(g, &cnt);
     if (st != ALB_OK) return bail(st);
     s->member_n.resize(cnt);
+    s->member_m.resize(cnt);
     for (int32_t i = 0; i < cnt; ++i) {
-      st = alb_graph_member_info(g, i, &s->member_n[i], nullptr, nullptr);
+      st = alb_graph_member_info(g, i, &s->member_n[i], &s->member_m[i], nullptr);
       if (st != ALB_OK) return bail(st);
     }
   } else {
     if (!cfg.executor || cfg.n_members < 1 || !cfg.member_vertices)
       return bail(set_error(ALB_E_INVAL, "a server without a graph needs an executor and member_vertices"));
     s->member_n.assign(cfg.member_vertices, cfg.member_vertices + cfg.n_members);
+    s->member_m.assign(s->member_n.size(), 0);
     for (int32_t n : s->member_n)
       if (n < 1) return bail(set_error(ALB_E_INVAL, "member_vertices must be >= 1"));
   }
@@ -272,6 +284,7 @@ alb_status alb_server_submit(alb_server s, int32_t algo, int32_t member, int32_t
   r.source = source;
   r.out = out;
   r.footprint = kBytesPerVertex * (size_t)n + kBytesPerQuery;
+  r.edges = s->member_m[member];
   r.t_submit = Clock::now();
   r.deadline = timeout_ms > 0 ? r.t_submit + std::chrono::duration_cast<Clock::duration>(
                                                   std::chrono::duration<double, std::milli>(timeout_ms))
