@@ -9,7 +9,8 @@ the adaptive load balancer) with the graph resident in HBM.  Reported: GTEPS
 cyclic path disabled (TWC only), the roofline fraction of the traversal
 kernel, and the CPU oracle (Dijkstra) on the host.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--threshold T] [--sweep]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--threshold T] [--no-sweep]
+                    [--workload sssp_rmat22|batch|serve|zipf24]
 """
 import argparse
 import hashlib
@@ -71,10 +72,10 @@ def main():
     ap.add_argument("--threshold", type=int, default=None,
                     help="huge-degree threshold for the ALB run (default: the library's, 4 x workgroup size)")
     ap.add_argument("--launch", default="auto")
-    ap.add_argument("--sweep", action="store_true", help="also sweep the threshold over powers of two")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the threshold sweep over powers of two")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-alb", action="store_true", help="skip the TWC-only comparison (profiling runs)")
-    ap.add_argument("--workload", default="sssp_rmat22", choices=["sssp_rmat22", "batch", "serve"],
+    ap.add_argument("--workload", default="sssp_rmat22", choices=["sssp_rmat22", "batch", "serve", "zipf24"],
                     help="batch: 256 SSSP queries over 64 RMAT graphs of scales 12..20 in one launch, "
                          "against the same queries one launch each; serve: Poisson streams of BFS/SSSP "
                          "requests over 32 graphs through the serving loop")
@@ -110,6 +111,8 @@ def main():
         return bench_batch(args, alb, gg)
     if args.workload == "serve":
         return bench_serve(args, alb, gg)
+    if args.workload == "zipf24":
+        return bench_zipf24(args, alb, gg)
 
     t = time.perf_counter()
     g = gg.workload("rmat22w")
@@ -144,6 +147,11 @@ def main():
     bytes_per = [alb.algorithmic_bytes("sssp", s) for s in stats]
     kms = [s["kernel_ms"] for s in stats]
     achieved = float(np.mean([b / (k * 1e-3) for b, k in zip(bytes_per, kms)])) / 1e9
+    # the work-efficient lower bound (each reached edge and vertex once), so that
+    # redundant relaxations are not rewarded
+    n_reached = int(reached.sum())
+    we_bytes = 12 * m_reached + 20 * n_reached
+    we_achieved = we_bytes / (float(np.mean(kms)) * 1e-3) / 1e9
     traffic = measured_traffic()
 
     paper_rule = None
@@ -152,12 +160,44 @@ def main():
         paper_rule = {"value": round(args.steps * m_reached / s3 / 1e9, 3), "ms_per_step": round(1e3 * s3 / args.steps, 4),
                       "huge_threshold": st3[-1]["huge_threshold"], "huge_vertices": st3[-1]["huge_vertices"]}
 
-    sweep = None
-    if args.sweep:
+    # the paper's threshold study (Section 5.1): 0 and powers of two, plus the
+    # adaptive rule and LB for every vertex
+    sweep = lb_all = None
+    if not args.no_sweep and not args.only_alb:
         sweep = {}
         for thr in [0] + [1 << e for e in range(6, 21, 2)] + ["adaptive"]:
             s2, st2 = measure(dict(base_opts, mode="alb", threshold=thr), "alb t=%s" % thr)
             sweep[str(thr)] = round(args.steps * m_reached / s2 / 1e9, 3)
+        s4, st4 = measure(dict(base_opts, mode="lb_all"), "lb_all")
+        lb_all = {"value": round(args.steps * m_reached / s4 / 1e9, 3), "ms_per_step": round(1e3 * s4 / args.steps, 4)}
+
+    # the small BFS configuration: RMAT scale 14 from vertex 0, latency-bound
+    bfs_small = None
+    if not args.only_alb:
+        g14 = gg.workload("rmat14")
+        d14 = alb.Graph(g14.off, g14.col)
+        o14 = torch.empty(g14.n, dtype=torch.int32, device="cuda")
+        lv = {}
+        for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+            for _ in range(5):
+                alb.bfs(d14, 0, out=o14, **opts)
+            ts = []
+            for _ in range(20):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                alb.bfs(d14, 0, out=o14, **opts)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            lv[label] = float(np.median(ts))
+        lev = o14.cpu().numpy()
+        m14 = int(g14.degrees()[lev < alb.INF].sum())
+        import oracle as _oracle
+
+        bfs_small = {"workload": "bfs_rmat14_ef16_from0", "n": g14.n, "m": g14.m,
+                     "latency_us": round(1e6 * lv["alb"], 1), "gteps": round(m14 / lv["alb"] / 1e9, 3),
+                     "twc_only_latency_us": round(1e6 * lv["twc_only"], 1),
+                     "bit_exact": bool(np.array_equal(lev, _oracle.bfs(g14, 0)))}
+        d14.close()
 
     cpu = None
     if not args.no_cpu:
@@ -202,6 +242,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_persistent<256, OpSSSP>" if stats[-1]["kernel_launches"] == 1 else "host loop",
                      "algorithmic_bytes_per_launch": int(np.mean(bytes_per)),
+                     "work_efficient_bytes": we_bytes, "work_efficient_gbs": round(we_achieved, 1),
+                     "work_efficient_frac": round(we_achieved / HBM_PEAK_GBS, 4),
                      "kernel_ms": round(float(np.mean(kms)), 4)},
         "cpu_baseline": cpu,
         "alb_stats": {k: stats[-1][k] for k in ("frontier_vertices", "edges_examined", "huge_vertices",
@@ -209,6 +251,9 @@ def main():
     }
     if sweep is not None:
         res["threshold_sweep_gteps"] = sweep
+        res["lb_all"] = lb_all
+    if bfs_small is not None:
+        res["bfs_small"] = bfs_small
     dg.close()
     print(json.dumps(res), flush=True)
 
@@ -324,6 +369,97 @@ def bench_batch(args, alb, gg):
         h.close()
     gset.close()
     print(json.dumps(res), flush=True)
+
+
+def bench_zipf24(args, alb, gg):
+    """The extreme-skew graph: Zipf(1.9) out-degrees capped at 4,194,304,
+    n = 2^24 (~372M edges).  BFS from the highest-degree vertex, CC on the
+    symmetrised graph, PageRank (0.85, 50 iterations), each with the default
+    balancer and TWC only; plus a 2048 x 2048 undirected grid (low skew, high
+    diameter) where the balancer should cost nothing.  Times are the
+    traversal kernels' device time (median of the steps)."""
+    import numpy as np
+    import torch
+
+    def timed(fn, dg, out, opts, *a):
+        for _ in range(max(1, args.warmup)):
+            fn(dg, *a, out=out, **opts)
+        ks, st = [], None
+        for _ in range(args.steps):
+            _, st = fn(dg, *a, out=out, **opts)
+            ks.append(st["kernel_ms"])
+        return float(np.median(ks)), st
+
+    res = {}
+    t = time.perf_counter()
+    g = gg.workload("zipf24")
+    src = g.max_degree_vertex()
+    deg = g.degrees()
+    log("zipf24: n=%d m=%d max_deg=%d (%.1fs)" % (g.n, g.m, deg.max(), time.perf_counter() - t))
+    dg = alb.Graph(g.off, g.col)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+        ms, st = timed(alb.bfs, dg, out, opts, src)
+        m_r = int(deg[out.cpu().numpy() < alb.INF].sum())
+        b = alb.algorithmic_bytes("bfs", st)
+        res.setdefault("bfs", {})[label] = {"kernel_ms": round(ms, 4), "gteps": round(m_r / ms / 1e6, 3),
+                                            "achieved_gbs": round(b / ms / 1e6, 1),
+                                            "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                            "huge_vertices": st["huge_vertices"]}
+        log("bfs %s: %.3f ms" % (label, ms))
+    outf = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+        ms, st = timed(alb.pagerank, dg, outf, opts, 0.85, 50)
+        b = alb.algorithmic_bytes("pagerank", st, n=g.n, iterations=50)
+        res.setdefault("pagerank", {})[label] = {"kernel_ms": round(ms, 3),
+                                                 "gteps": round(50 * g.m / ms / 1e6, 3),
+                                                 "achieved_gbs": round(b / ms / 1e6, 1),
+                                                 "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        log("pagerank %s: %.3f ms" % (label, ms))
+    dg.close()
+    t = time.perf_counter()
+    ds = alb.Graph(g.off, g.col, build_symmetric=True)
+    log("symmetrised: m=%d (%.1fs)" % (ds.m, time.perf_counter() - t))
+    for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+        ms, st = timed(lambda d, out=None, **o: alb.cc(d, out=out, **o), ds, out, opts)
+        b = alb.algorithmic_bytes("cc", st)
+        res.setdefault("cc", {})[label] = {"kernel_ms": round(ms, 3),
+                                           "edges_per_s_g": round(st["edges_examined"] / ms / 1e6, 3),
+                                           "achieved_gbs": round(b / ms / 1e6, 1),
+                                           "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4), "rounds": st["rounds"]}
+        log("cc %s: %.3f ms" % (label, ms))
+    ds.close()
+    del g
+    gr = gg.grid(2048, 2048).with_weights(5)
+    dgr = alb.Graph(gr.off, gr.col, gr.w)
+    outg = torch.empty(gr.n, dtype=torch.int32, device="cuda")
+    for kind, fn in (("bfs", alb.bfs), ("sssp", alb.sssp)):
+        for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+            ms, st = timed(fn, dgr, outg, opts, 0)
+            res.setdefault("grid2048_" + kind, {})[label] = {"kernel_ms": round(ms, 3), "rounds": st["rounds"],
+                                                             "huge_vertices": st["huge_vertices"]}
+            log("grid %s %s: %.3f ms" % (kind, label, ms))
+    dgr.close()
+    bfs = res["bfs"]["alb"]
+    line = {
+        "metric": METRIC,
+        "value": bfs["gteps"],
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": bfs["kernel_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "zipf1.9_n2^24_cap4194304: bfs, cc, pagerank; grid2048 bfs, sssp", "source": src},
+        "roofline": {"bound": "hbm", "achieved": bfs["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bfs["frac"], "traffic": None},
+        "results": res,
+    }
+    print(json.dumps(line), flush=True)
 
 
 class _BufferPool:

@@ -505,6 +505,33 @@ void print_timeline(const Ctl &c, int op, int rounds, long long threshold, uint6
   fprintf(stderr, "\n");
 }
 
+// Edges per member workgroup in each round: the largest over the mean (1 is
+// perfect balance), and over the whole launch.
+void print_skew(const uint32_t *d_counts, int rounds, int members) {
+  std::vector<uint32_t> h((size_t)kTimeline * kProfMembers);
+  if (hipMemcpy(h.data(), d_counts, sizeof(uint32_t) * h.size(), hipMemcpyDeviceToHost) != hipSuccess) return;
+  std::vector<unsigned long long> tot((size_t)members, 0);
+  for (int r = 0; r < rounds; ++r) {
+    unsigned long long sum = 0, mx = 0;
+    for (int w = 0; w < members; ++w) {
+      const uint32_t x = h[(size_t)r * kProfMembers + w];
+      sum += x;
+      mx = std::max<unsigned long long>(mx, x);
+      tot[w] += x;
+    }
+    if (sum)
+      fprintf(stderr, "[alb] skew round %2d  edges %llu  max/mean per workgroup %.2f\n", r, sum,
+              (double)mx * members / (double)sum);
+  }
+  unsigned long long sum = 0, mx = 0;
+  for (unsigned long long x : tot) {
+    sum += x;
+    mx = std::max(mx, x);
+  }
+  if (sum) fprintf(stderr, "[alb] skew launch  edges %llu  max/mean per workgroup %.2f\n", sum,
+                   (double)mx * members / (double)sum);
+}
+
 void fill_stats(alb_stats *st, const Ctl &c, int rounds, int launches, int64_t T, int64_t threshold, hipEvent_t e0,
                 hipEvent_t e1, hipEvent_t e2) {
   float ms_all = 0.f, ms_k = 0.f;
@@ -622,6 +649,17 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   if (job.h_frontier && job.nfront0)
     HIP_TRY(hipMemcpyAsync(ws->q0, job.h_frontier, sizeof(int32_t) * job.nfront0, hipMemcpyHostToDevice, stream));
 
+  // profiling aid: per-round, per-workgroup edge counts (freed below)
+  struct ProfBuf {
+    uint32_t *p = nullptr;
+    ~ProfBuf() { (void)hipFree(p); }
+  } prof;
+  if (a.profile && launch == ALB_LAUNCH_PERSISTENT) {
+    const size_t nb = sizeof(uint32_t) * (size_t)kTimeline * kProfMembers;
+    HIP_TRY(hipMalloc((void **)&prof.p, nb));
+    HIP_TRY(hipMemsetAsync(prof.p, 0, nb, stream));
+    a.prof_wg = prof.p;
+  }
   HIP_TRY(hipEventRecord(ws->ev[0], stream));
   HIP_TRY(launch_init(job.op, a, job.source, job.nfront0, stream));
   HIP_TRY(hipEventRecord(ws->ev[1], stream));
@@ -673,8 +711,10 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", a.qcap, c.overflow);
   if (launch == ALB_LAUNCH_PERSISTENT) {
     rounds = (int)c.rounds;
-    if (getenv("ALB_TIMELINE"))  // profiling aid: per-round phase times on stderr
+    if (getenv("ALB_TIMELINE")) {  // profiling aid: per-round phase times on stderr
       print_timeline(c, (int)job.op, rounds, (long long)threshold, g->clock_khz);
+      if (prof.p) print_skew(prof.p, std::min(rounds, kTimeline), (int)std::min<uint32_t>(c.n_members, kProfMembers));
+    }
   }
   if (!job.all_rounds && job.max_rounds > 1 && rounds >= job.max_rounds && c.qcount[rounds % 3] != 0)
     return fail(ALB_E_DEVICE, "no convergence within %d rounds", job.max_rounds);

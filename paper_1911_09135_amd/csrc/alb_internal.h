@@ -74,6 +74,9 @@ struct Ctl {
   unsigned long long prof[8];
 };
 constexpr int kTimeline = 64;
+// With Args::prof_wg: edges each member workgroup processed in each of the
+// first kTimeline rounds, for at most kProfMembers members.
+constexpr int kProfMembers = 8192;
 enum { kProfInspect = 0, kProfWgBin, kProfWaveBin, kProfThreadBin, kProfLb, kProfBarrier, kProfParts };
 
 enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4 };
@@ -104,6 +107,7 @@ struct Args {
   uint64_t timeout_ticks;  // barrier wait limit in wall-clock ticks
   uint64_t join_window_ticks;  // persistent launch: close membership after this long without a new member
   int32_t profile;         // accumulate Ctl::prof (profiling aid)
+  uint32_t *prof_wg;       // profiling: [kTimeline][kProfMembers] edges per round and member, or null
   // operator state
   int32_t *level;       // BFS levels
   unsigned long long *word;  // SSSP / CC: (label << 32) | tag, tag = 1 + last round that lowered it

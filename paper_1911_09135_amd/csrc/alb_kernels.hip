@@ -241,6 +241,19 @@ __device__ __forceinline__ void prof_mark(const Args &a, Acc &acc, int k, uint64
   }
 }
 
+// Profiling aid: the edges this workgroup processed in round r (each wave
+// adds its lanes' counts since the last call).
+__device__ __forceinline__ void prof_round_edges(const Args &a, const Acc &acc, unsigned long long &last, uint32_t id,
+                                                 int r) {
+  const unsigned long long now = acc.edges_twc + acc.edges_lb;
+  unsigned long long d = now - last;
+  last = now;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) d += __shfl_xor(d, o);
+  if (lane_id() == 0 && d && r < kTimeline && id < (uint32_t)kProfMembers)
+    add_relaxed(&a.prof_wg[(size_t)r * kProfMembers + id], (uint32_t)d);
+}
+
 // Worklist entries: a vertex id for one query; (query << 32) | vertex for a batch.
 template <bool M>
 using Entry = typename std::conditional<M, unsigned long long, int32_t>::type;
@@ -1055,7 +1068,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
   Grid gr;
   if (!join_members(a, sm, &gr)) return;
   if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // the launched thread count (the paper's rule)
-  unsigned long long epoch = 0;
+  unsigned long long epoch = 0, prof_last = 0;
   int r = 0;
   for (; r < a.max_rounds; ++r) {
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;  // set in an earlier round: seen by all alike
@@ -1087,6 +1100,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
       prof_mark(a, acc, kProfBarrier, pb);
     }
     if (tl) a.ctl->tl[4 * r + 2] = (unsigned long long)wall_clock64();
+    if (a.prof_wg) prof_round_edges(a, acc, prof_last, gr.id, r);
     if constexpr (Op::kPR) {
       phase_pr_update<B>(a, gr, ld_relaxed(&a.ctl->dangling[r & 1]));
       if (!grid_barrier(a, sm, gr, epoch, r)) break;
