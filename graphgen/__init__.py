@@ -200,6 +200,13 @@ def undirected(n: int, src, dst, w=None, name: str = "") -> Graph:
     return from_edges(n, np.concatenate([src, dst]), np.concatenate([dst, src]), ww, name)
 
 
+def symmetrised(g: Graph) -> Graph:
+    """Both directions of every edge of g, self-loops and duplicates removed
+    (unweighted): the undirected graph that k-core and CC work on."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    return undirected(g.n, src, g.col.astype(np.int64), name=g.name + "_sym")
+
+
 def path(n: int, w=None, directed: bool = True) -> Graph:
     s = np.arange(n - 1)
     f = from_edges if directed else undirected

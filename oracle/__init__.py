@@ -56,6 +56,8 @@ def _load():
         lib.oracle_sssp.argtypes = [i32, vp, vp, vp, i32, vp]
         lib.oracle_cc.restype = ctypes.c_int
         lib.oracle_cc.argtypes = [i32, vp, vp, vp]
+        lib.oracle_kcore.restype = ctypes.c_int
+        lib.oracle_kcore.argtypes = [i32, vp, vp, i32, vp]
         lib.oracle_pagerank.restype = ctypes.c_int
         lib.oracle_pagerank.argtypes = [i32, vp, vp, dbl, i32, i32, vp]
         lib.oracle_inspect.restype = i64
@@ -108,6 +110,16 @@ def cc(g) -> np.ndarray:
     rc = _load().oracle_cc(g.n, _p(off), _p(col), _p(out))
     if rc != 0:
         raise ValueError("oracle_cc failed: %d" % rc)
+    return out
+
+
+def kcore(g, k: int) -> np.ndarray:
+    """k-core membership (1 in the core, 0 removed) of a symmetric CSR."""
+    off, col = _i32(g.off), _i32(g.col)
+    out = np.empty(g.n, dtype=np.int32)
+    rc = _load().oracle_kcore(g.n, _p(off), _p(col), int(k), _p(out))
+    if rc != 0:
+        raise ValueError("oracle_kcore failed: %d" % rc)
     return out
 
 

@@ -189,6 +189,45 @@ int oracle_cc(int32_t n, const int32_t *off, const int32_t *col, int32_t *label)
 }
 
 /* ------------------------------------------------------------------ */
+/* k-core (the paper's kcore application, Section 5): the k-core of an
+ * undirected graph is its largest subgraph in which every vertex has at least
+ * k neighbours.  Peeling: every vertex of degree < k is removed; removing a
+ * vertex lowers its neighbours' degrees; a neighbour whose degree falls
+ * below k is removed in turn, until none is left to remove.  The input is
+ * the symmetric CSR (both directions of every edge, no self-loops);
+ * in_core[v] = 1 for the vertices that remain, else 0.
+ * ------------------------------------------------------------------ */
+int oracle_kcore(int32_t n, const int32_t *off, const int32_t *col, int32_t k, int32_t *in_core) {
+  if (n < 1 || k < 0) return -1;
+  int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!deg || !queue) { free(deg); free(queue); return -2; }
+  int64_t head = 0, tail = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    deg[v] = off[v + 1] - off[v];
+    in_core[v] = 1;
+    if (deg[v] < k) {
+      in_core[v] = 0;
+      queue[tail++] = v;
+    }
+  }
+  while (head < tail) {
+    const int32_t u = queue[head++];
+    for (int32_t p = off[u]; p < off[u + 1]; ++p) {
+      const int32_t v = col[p];
+      if (!in_core[v]) continue;
+      if (--deg[v] < k) {
+        in_core[v] = 0;
+        queue[tail++] = v;
+      }
+    }
+  }
+  free(deg);
+  free(queue);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* PageRank, fp64, synchronous iteration with uniform teleport and the rank
  * of dangling vertices (out-degree 0) spread uniformly:
  *   x_0(v) = 1/N

@@ -258,6 +258,67 @@ def dense_pagerank(g, d, iters):
     return x
 
 
+# ----------------------------------------------------------------------------
+# k-core
+# ----------------------------------------------------------------------------
+
+def kcore_brute_force(g, k):
+    """The k-core straight from its definition: the union of every vertex set
+    in which each member has at least k neighbours inside the set."""
+    n = g.n
+    adj = np.zeros((n, n), dtype=bool)
+    adj[edge_src(g), g.col] = True
+    core = np.zeros(n, dtype=bool)
+    for mask in range(1, 1 << n):
+        inside = np.array([(mask >> v) & 1 for v in range(n)], dtype=bool)
+        if (adj[inside][:, inside].sum(axis=1) >= k).all():
+            core |= inside
+    return core.astype(np.int32)
+
+
+@pytest.mark.parametrize("n,m,seed", [(6, 9, 1), (8, 14, 2), (10, 22, 3), (10, 30, 4), (11, 12, 5)])
+def test_kcore_vs_brute_force(n, m, seed):
+    g = gg.symmetrised(gg.random_digraph(n, m, seed))
+    for k in range(0, 7):
+        assert np.array_equal(oracle.kcore(g, k), kcore_brute_force(g, k)), (n, m, seed, k)
+
+
+def test_kcore_closed_forms():
+    ones, zeros = (lambda n: np.ones(n, np.int32)), (lambda n: np.zeros(n, np.int32))
+    K = gg.complete(7)  # every vertex has 6 neighbours
+    assert np.array_equal(oracle.kcore(K, 6), ones(7)) and np.array_equal(oracle.kcore(K, 7), zeros(7))
+    cyc = gg.symmetrised(gg.cycle(30))
+    assert np.array_equal(oracle.kcore(cyc, 2), ones(30)) and np.array_equal(oracle.kcore(cyc, 3), zeros(30))
+    p = gg.path(25, directed=False)  # the ends peel inwards
+    assert np.array_equal(oracle.kcore(p, 1), ones(25)) and np.array_equal(oracle.kcore(p, 2), zeros(25))
+    st = gg.star(40)
+    assert np.array_equal(oracle.kcore(st, 1), ones(41)) and np.array_equal(oracle.kcore(st, 2), zeros(41))
+    gr = gg.grid(9, 13)  # corners have 2 neighbours; at k = 3 the border peels and so does the rest
+    assert np.array_equal(oracle.kcore(gr, 2), ones(117)) and np.array_equal(oracle.kcore(gr, 3), zeros(117))
+    assert np.array_equal(oracle.kcore(gg.edgeless(5), 0), ones(5))
+    assert np.array_equal(oracle.kcore(gg.edgeless(5), 1), zeros(5))
+    # a 5-clique with a pendant path: only the clique is in the 4-core
+    src = [i for i in range(5) for j in range(5) if i != j] + [4, 5, 6]
+    dst = [j for i in range(5) for j in range(5) if i != j] + [5, 6, 7]
+    g = gg.undirected(8, src, dst)
+    assert np.array_equal(oracle.kcore(g, 4), np.array([1] * 5 + [0] * 3, np.int32))
+
+
+def test_kcore_invariants_rmat():
+    g = gg.symmetrised(gg.rmat(12, 8, seed=5))
+    prev = np.ones(g.n, np.int32)
+    src = edge_src(g)
+    for k in (1, 2, 4, 8, 16, 32):
+        c = oracle.kcore(g, k)
+        # inside the core every vertex keeps at least k core neighbours
+        inside = np.zeros(g.n, np.int64)
+        np.add.at(inside, src, c[g.col])
+        assert (inside[c == 1] >= k).all()
+        # cores are nested
+        assert (c <= prev).all()
+        prev = c
+
+
 def test_pagerank_vs_dense():
     for g in [gg.random_digraph(30, 70, 4), gg.star(6), gg.path(9), gg.random_digraph(64, 300, 8),
               gg.rmat(7, 4, seed=2)]:
