@@ -162,7 +162,7 @@ def main():
 
     # the paper's threshold study (Section 5.1): 0 and powers of two, plus the
     # adaptive rule and LB for every vertex
-    sweep = lb_all = None
+    sweep = lb_all = blocked = None
     if not args.no_sweep and not args.only_alb:
         sweep = {}
         for thr in [0] + [1 << e for e in range(6, 21, 2)] + ["adaptive"]:
@@ -170,6 +170,11 @@ def main():
             sweep[str(thr)] = round(args.steps * m_reached / s2 / 1e9, 3)
         s4, st4 = measure(dict(base_opts, mode="lb_all"), "lb_all")
         lb_all = {"value": round(args.steps * m_reached / s4 / 1e9, 3), "ms_per_step": round(1e3 * s4 / args.steps, 4)}
+        # the blocked distribution of huge edges (Section 4.1) at the default threshold and at t = 64
+        blocked = {}
+        for thr in (None, 64):
+            s5, _ = measure(dict(base_opts, mode="alb", threshold=thr, distribution=1), "blocked t=%s" % thr)
+            blocked["default" if thr is None else str(thr)] = round(args.steps * m_reached / s5 / 1e9, 3)
 
     # the small BFS configuration: RMAT scale 14 from vertex 0, latency-bound
     bfs_small = None
@@ -252,6 +257,7 @@ def main():
     if sweep is not None:
         res["threshold_sweep_gteps"] = sweep
         res["lb_all"] = lb_all
+        res["blocked_distribution_gteps"] = blocked
     if bfs_small is not None:
         res["bfs_small"] = bfs_small
     dg.close()

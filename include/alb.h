@@ -88,7 +88,8 @@ typedef struct {
   int32_t wg_size;           /* 0 = 256; one of 64, 256, 1024 */
   int32_t wave_cutoff;       /* TWC wavefront bin: degree >= this (0 = 64) */
   int32_t wg_cutoff;         /* TWC workgroup bin: degree >= this (0 = wg_size) */
-  int32_t distribution;      /* 0 = cyclic (Section 4.1 default); others unsupported */
+  int32_t distribution;      /* huge edges over threads (Section 4.1): 0 = cyclic, edge k to thread k mod T
+                                (the default); 1 = blocked, thread i takes edges [i*c, (i+1)*c), c = ceil(e/T) */
   int32_t dedup;             /* -1 = default (on for sssp and cc), 0 = off, 1 = on */
   int32_t launch;            /* alb_launch */
   int32_t grid_wgs;          /* 0 = every resident workgroup; else this many workgroups */
@@ -164,6 +165,14 @@ alb_status alb_sssp(alb_graph g, int32_t source, int32_t *dist, const alb_option
  * must be symmetric (ALB_SYMMETRIC or ALB_BUILD_SYMMETRIC), else
  * ALB_E_INVAL.  label[v] = the smallest vertex id of v's component. */
 alb_status alb_cc(alb_graph g, int32_t *label, const alb_options *opt, alb_stats *stats);
+
+/* k-core (the paper's kcore application, Section 5): the largest subgraph in
+ * which every vertex keeps at least k neighbours, by peeling -- vertices with
+ * fewer than k edges leave, their neighbours' degrees drop, a neighbour whose
+ * degree falls below k leaves in the next round.  The handle must be
+ * symmetric (as for alb_cc) and free of self-loops.  in_core[v] = 1 if v is
+ * in the k-core, else 0.  k >= 0. */
+alb_status alb_kcore(alb_graph g, int32_t k, int32_t *in_core, const alb_options *opt, alb_stats *stats);
 
 /* PageRank, fp32, push over out-edges, exactly `iterations` synchronous
  * iterations from rank = 1/n:  r'(v) = (1-d)/n + d * (sum over in-edges (u,v)

@@ -122,6 +122,7 @@ _sig = {
     "alb_sssp": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_cc": ([_vp, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_pagerank": ([_vp, _f32, _i32, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_kcore": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_graph_create_set": ([_i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
     "alb_graph_members": ([_vp, ctypes.POINTER(_i32)], ctypes.c_int),
     "alb_graph_member_info": ([_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
@@ -578,6 +579,11 @@ def sssp(g: Graph, source: int, out=None, **opts):
 
 def cc(g: Graph, out=None, **opts):
     return _run(_lib.alb_cc, g, out, np.int32, opts)
+
+
+def kcore(g: Graph, k: int, out=None, **opts):
+    """k-core membership (int32 1/0) of a symmetric graph and the stats dict."""
+    return _run(_lib.alb_kcore, g, out, np.int32, opts, int(k))
 
 
 def pagerank(g: Graph, damping: float = 0.85, iterations: int = 50, out=None, **opts):

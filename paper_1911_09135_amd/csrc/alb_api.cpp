@@ -410,7 +410,8 @@ alb_status resolve_options(const alb_options *user, alb_options &o) {
   if (o.wave_cutoff == 0) o.wave_cutoff = 64;
   if (o.wg_cutoff == 0) o.wg_cutoff = o.wg_size;
   if (o.wave_cutoff < 1 || o.wg_cutoff < 1) return fail(ALB_E_INVAL, "cutoffs must be >= 1");
-  if (o.distribution != 0) return fail(ALB_E_UNSUPPORTED, "only the cyclic distribution (0) is implemented");
+  if (o.distribution != 0 && o.distribution != 1)
+    return fail(ALB_E_UNSUPPORTED, "distribution %d (0 cyclic, 1 blocked)", o.distribution);
   if (o.dedup < -1 || o.dedup > 1) return fail(ALB_E_INVAL, "bad dedup %d", o.dedup);
   if (o.launch < ALB_LAUNCH_AUTO || o.launch > ALB_LAUNCH_PERSISTENT) return fail(ALB_E_INVAL, "bad launch %d", o.launch);
   if (o.grid_wgs < 0) return fail(ALB_E_INVAL, "grid_wgs must be >= 0");
@@ -465,6 +466,7 @@ struct Job {
   bool all_rounds = false;     // PageRank
   int32_t max_rounds = 0;
   float damping = 0.85f;
+  int32_t k = 0;               // k-core
   const int32_t *h_frontier = nullptr;  // trace: explicit round-0 worklist (host)
   int32_t *d_hits = nullptr, *d_thread = nullptr;
   int8_t *d_bins = nullptr;
@@ -587,7 +589,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   uint64_t qcap;
   if (o.worklist_capacity > 0)
     qcap = (uint64_t)o.worklist_capacity;
-  else if (job.op == OP_BFS || dedup || job.op == OP_PR)
+  else if (job.op == OP_BFS || dedup || job.op == OP_PR || job.op == OP_KCORE)
     qcap = (uint64_t)g->n;
   else
     qcap = (uint64_t)g->n + (uint64_t)g->m;
@@ -623,6 +625,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.c_wg = o.wg_cutoff;
   a.dedup = dedup ? 1 : 0;
   a.adaptive = adaptive ? 1 : 0;
+  a.blocked = o.distribution == 1;
   a.identity_first = job.identity_first;
   a.all_rounds = job.all_rounds;
   a.max_rounds = job.max_rounds;
@@ -633,6 +636,11 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   if (job.op == OP_BFS) a.level = dev_out ? (int32_t *)dev_out : ws->labels;
   if (job.op == OP_SSSP || job.op == OP_CC) {
     a.word = ws->word;
+    a.out = dev_out ? (int32_t *)dev_out : ws->labels;
+  }
+  if (job.op == OP_KCORE) {
+    a.level = (int32_t *)ws->word;  // remaining degrees (ws->word has room for n int32)
+    a.kcore_k = job.k;
     a.out = dev_out ? (int32_t *)dev_out : ws->labels;
   }
   if (job.op == OP_PR) {
@@ -697,7 +705,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
       rounds = r + 1;
     }
   }
-  if (job.op == OP_SSSP || job.op == OP_CC) HIP_TRY(launch_finish(a, stream));
+  if (job.op == OP_SSSP || job.op == OP_CC || job.op == OP_KCORE) HIP_TRY(launch_finish(job.op, a, stream));
   HIP_TRY(hipEventRecord(ws->ev[2], stream));
   HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -856,6 +864,7 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
   a.c_wg = o.wg_cutoff;
   a.dedup = dedup ? 1 : 0;
   a.adaptive = (!thresholds && o.mode == ALB_MODE_ALB && o.huge_threshold == ALB_THRESHOLD_ADAPTIVE) ? 1 : 0;
+  a.blocked = o.distribution == 1;
   a.max_rounds = max_n + 1;
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
   a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);
@@ -1426,6 +1435,25 @@ alb_status alb_cc(alb_graph g, int32_t *label, const alb_options *opt, alb_stats
   job.nfront0 = (uint32_t)g->n;
   job.max_rounds = g->n + 1;
   s = traverse(g, job, label, sizeof(int32_t), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_kcore(alb_graph g, int32_t k, int32_t *in_core, const alb_options *opt, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (!in_core) return fail(ALB_E_INVAL, "in_core is NULL");
+  if (k < 0) return fail(ALB_E_INVAL, "k must be >= 0");
+  if (!g->symmetric)
+    return fail(ALB_E_INVAL, "alb_kcore needs a symmetric graph (ALB_SYMMETRIC or ALB_BUILD_SYMMETRIC)");
+  Job job;
+  job.op = OP_KCORE;
+  job.identity_first = true;
+  job.nfront0 = (uint32_t)g->n;
+  job.max_rounds = g->n + 1;
+  job.k = k;
+  s = traverse(g, job, in_core, sizeof(int32_t), opt, stats);
   if (s != ALB_OK) zero_stats(stats);
   return s;
 }

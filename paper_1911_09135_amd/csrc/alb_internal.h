@@ -79,7 +79,7 @@ constexpr int kTimeline = 64;
 constexpr int kProfMembers = 8192;
 enum { kProfInspect = 0, kProfWgBin, kProfWaveBin, kProfThreadBin, kProfLb, kProfBarrier, kProfParts };
 
-enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4 };
+enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4, OP_KCORE = 5 };
 
 // Everything a traversal kernel reads.  Passed by value.
 struct Args {
@@ -100,6 +100,7 @@ struct Args {
   int32_t c_wg;
   int32_t dedup;        // SSSP / CC: push a vertex at most once per round
   int32_t adaptive;     // per-round threshold: kAdaptiveSmall when the worklist has fewer entries than threads
+  int32_t blocked;      // huge edges in contiguous runs per thread instead of cyclically
   int32_t identity_first;  // round 0 works on every vertex (no worklist)
   int32_t all_rounds;      // every round works on every vertex (PageRank)
   int32_t max_rounds;
@@ -109,7 +110,8 @@ struct Args {
   int32_t profile;         // accumulate Ctl::prof (profiling aid)
   uint32_t *prof_wg;       // profiling: [kTimeline][kProfMembers] edges per round and member, or null
   // operator state
-  int32_t *level;       // BFS levels
+  int32_t *level;       // BFS levels; k-core: remaining degrees
+  int32_t kcore_k;      // k-core: k
   unsigned long long *word;  // SSSP / CC: (label << 32) | tag, tag = 1 + last round that lowered it
   int32_t *out;         // SSSP / CC: int32 labels written by the finishing kernel
   float *rank;          // PageRank: fp32 ranks
@@ -136,8 +138,8 @@ hipError_t launch_twc(OpKind op, int wg, int grid, const Args &a, hipStream_t s)
 hipError_t launch_lb(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_pr_update(int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_persistent(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
-// SSSP / CC: out[v] = word[v] >> 32.
-hipError_t launch_finish(const Args &a, hipStream_t s);
+// SSSP / CC: out[v] = word[v] >> 32; k-core: out[v] = (level[v] >= k).
+hipError_t launch_finish(OpKind op, const Args &a, hipStream_t s);
 // Workgroups of `wg` threads that fit on one CU for the persistent kernel of
 // `op`, by the runtime's occupancy calculator (an upper bound: the launch
 // itself finds out how many are co-resident).

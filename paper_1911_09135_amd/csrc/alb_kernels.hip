@@ -176,6 +176,29 @@ struct OpCC {  // min-label propagation
   }
 };
 
+// k-core (peeling): an active vertex has left the core; each of its edges
+// lowers the neighbour's remaining degree, and the neighbour whose degree
+// falls from k to k - 1 leaves in the next round, so every vertex is pushed
+// at most once.  Round 0 inspects every vertex (no worklist) and takes those
+// with fewer than k edges, judged by the CSR degree rather than the
+// remaining degree that other lanes are already lowering.
+struct OpKCore {
+  using val_t = int32_t;
+  struct pre_t {};
+  static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false, kBatch = false;
+  int32_t *rem;
+  int32_t k;
+  __device__ __forceinline__ val_t load_src(long long, int32_t deg, uint32_t tag, bool &skip) const {
+    if (tag == 1u) skip = deg >= k;
+    return 0;
+  }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t) const { return {}; }
+  __device__ __forceinline__ bool commit(const pre_t &, int32_t, long long dl, val_t, int32_t, int32_t,
+                                         uint32_t) const {
+    return __hip_atomic_fetch_add(&rem[dl], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k;
+  }
+};
+
 struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact fixed-point sum
   using val_t = float;
   struct pre_t {};
@@ -221,6 +244,8 @@ template <>
 OpPR make_op<OpPR>(const Args &a) { return OpPR{a.rank, a.acc}; }
 template <>
 OpRecord make_op<OpRecord>(const Args &a) { return OpRecord{a.hits, a.thread_of}; }
+template <>
+OpKCore make_op<OpKCore>(const Args &a) { return OpKCore{a.level, a.kcore_k}; }
 
 // ---------------------------------------------------------------------------
 // Per-thread statistics, shared memory, work-distribution grid, push staging.
@@ -751,27 +776,46 @@ __device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid g
   const uint32_t tag = (uint32_t)round + 1u;
   Pusher<Entry<M>> pu{sm.pbuf[threadIdx.x / kWave], 0u, qn, qn_cnt};
   uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
-  // thread g takes huge edges g, g + T, g + 2T, ...; kU of them per pass
-  for (uint64_t k0 = g - lane; k0 < e; k0 += kU * T) {
-    bool act[kU];
-    int32_t pos[kU], src[kU];
-    V s[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const uint64_t k = k0 + lane + (uint64_t)u * T;
-      act[u] = k < e;
-      pos[u] = 0;
-      src[u] = 0;
-      s[u] = V(0);
-      if (act[u]) {
-        const int4 r = a.huge_rec[owner_of(a, vh, hs, (uint32_t)k)];
-        pos[u] = r.y + (int32_t)((uint32_t)k - (uint32_t)r.x);
-        src[u] = r.z;
-        s[u] = from_bits<V>(r.w);
-      }
-      acc.edges_lb += act[u];
+  // slot u of a pass: huge edge k (if active) -> CSR position, source, source value
+  auto take = [&](uint64_t k, bool on, bool &act, int32_t &pos, int32_t &src, V &sv) {
+    act = on;
+    pos = 0;
+    src = 0;
+    sv = V(0);
+    if (on) {
+      const int4 r = a.huge_rec[owner_of(a, vh, hs, (uint32_t)k)];
+      pos = r.y + (int32_t)((uint32_t)k - (uint32_t)r.x);
+      src = r.z;
+      sv = from_bits<V>(r.w);
     }
-    edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, (int32_t)g);
+    acc.edges_lb += on;
+  };
+  bool act[kU];
+  int32_t pos[kU], src[kU];
+  V s[kU];
+  if (!a.blocked) {
+    // cyclic: thread g takes huge edges g, g + T, g + 2T, ...; kU of them per
+    // pass, so a wavefront's lanes read consecutive CSR entries
+    for (uint64_t k0 = g - lane; k0 < e; k0 += kU * T) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint64_t k = k0 + lane + (uint64_t)u * T;
+        take(k, k < e, act[u], pos[u], src[u], s[u]);
+      }
+      edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, (int32_t)g);
+    }
+  } else {
+    // blocked (the alternative of Section 4.1): thread g takes the run
+    // [g * c, (g + 1) * c) of c = ceil(e / T) consecutive huge edges
+    const uint64_t c = (e + T - 1) / T;
+    for (uint64_t j0 = 0; j0 < c; j0 += kU) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint64_t j = j0 + (uint64_t)u, k = g * c + j;
+        take(k, j < c && k < e, act[u], pos[u], src[u], s[u]);
+      }
+      edges<Op, M>(act, pos, s, src, op, a, tag, round, pu, acc, (int32_t)g);
+    }
   }
   if constexpr (Op::kPush) flush_pushes(a, round, pu);
   prof_mark(a, acc, kProfLb, pt);
@@ -937,6 +981,7 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     if (op == OP_BFS) a.level[v] = ((int32_t)v == source) ? 0 : kInf;
     if (op == OP_SSSP) a.word[v] = (unsigned long long)(uint32_t)((int32_t)v == source ? 0 : kInf) << 32;
     if (op == OP_CC) a.word[v] = (unsigned long long)v << 32;
+    if (op == OP_KCORE) a.level[v] = a.off[v + 1] - a.off[v];
     if (op == OP_PR) {
       a.rank[v] = r0;
       a.acc[v] = 0ull;
@@ -967,10 +1012,10 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
   }
 }
 
-__global__ void k_finish(Args a) {
+__global__ void k_finish(Args a, int op) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)a.n; v += stride)
-    a.out[v] = (int32_t)(a.word[v] >> 32);
+    a.out[v] = op == OP_KCORE ? (int32_t)(a.level[v] >= a.kcore_k) : (int32_t)(a.word[v] >> 32);
 }
 
 // Batch set-up, part 1: every label of every query to INF, barrier words and
@@ -1174,6 +1219,7 @@ hipError_t by_op(OpKind op, Xs... xs) {
     case OP_CC: return F<B, OpCC>::run(xs...);
     case OP_PR: return F<B, OpPR>::run(xs...);
     case OP_RECORD: return F<B, OpRecord>::run(xs...);
+    case OP_KCORE: return F<B, OpKCore>::run(xs...);
   }
   return hipErrorInvalidValue;
 }
@@ -1201,12 +1247,12 @@ hipError_t launch_init(OpKind op, const Args &a, int32_t source, uint32_t nfront
   return hipGetLastError();
 }
 
-hipError_t launch_finish(const Args &a, hipStream_t s) {
+hipError_t launch_finish(OpKind op, const Args &a, hipStream_t s) {
   const int threads = 256;
   int blocks = (int)(((int64_t)a.n + threads - 1) / threads);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(threads), 0, s, a);
+  hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(threads), 0, s, a, (int)op);
   return hipGetLastError();
 }
 

@@ -102,6 +102,7 @@ CONFIGS = [
     dict(wg_size=64, grid_wgs=2, threshold=64),
     dict(wg_size=256, grid_wgs=3),
     dict(wave_cutoff=8, wg_cutoff=100, threshold=5000),
+    dict(threshold=64, distribution=1),
 ]
 
 

@@ -45,8 +45,12 @@ def check_round(alb, g, dg, frontier, **opts):
     for v in frontier:
         expect_hits[g.off[v]:g.off[v + 1]] += 1
     assert np.array_equal(r["edge_hits"], expect_hits)
-    # Algorithm 2, cyclic distribution: huge edge k on global thread k mod T
+    # Algorithm 2: huge edge k on global thread k mod T (cyclic), or on thread
+    # k / ceil(e / T) (blocked)
     src, pos, thr = oracle.lb_edges(work, r["prefix"], g.off, T)
+    if opts.get("distribution", 0) == 1:
+        e = int(r["prefix"][-1])
+        thr = np.array([oracle.blocked_thread(k, e, T) for k in range(e)], np.int64)
     assert np.array_equal(r["edge_thread"][pos], thr.astype(np.int32))
     assert np.array_equal(src, np.repeat(work, deg[work]))
     # TWC: every other edge of a vertex stays inside one workgroup (runs of
@@ -128,4 +132,18 @@ def test_two_sources_per_wave_at_default_threshold(alb):
     waves = thr // 64
     for w in np.unique(waves):
         assert len(np.unique(src[waves == w])) <= 2
+    dg.close()
+
+
+@pytest.mark.parametrize("launch", ["host", "persistent"])
+def test_trace_blocked_distribution(alb, hubgraph, launch):
+    """The blocked alternative of Section 4.1: thread i takes a contiguous run
+    of ceil(e / T) huge edges."""
+    g = hubgraph
+    dg = alb.Graph(g.off, g.col)
+    for fr in (np.array([0], np.int32), np.array([0, 17, 99, 1234, 3], np.int32),
+               np.arange(g.n, dtype=np.int32)):
+        for thr in (0, 64, 4096, None):
+            check_round(alb, g, dg, fr, threshold=thr, distribution=1, launch=launch)
+        check_round(alb, g, dg, fr, threshold=64, distribution=1, wg_size=64, grid_wgs=2, launch=launch)
     dg.close()

@@ -79,6 +79,11 @@ def configs(maxdeg):
     out.append(dict(mode="alb", threshold=64, wg_size=64, grid_wgs=3, launch="persistent"))
     out.append(dict(mode="lb_all", wg_size=64, grid_wgs=1, launch="host"))
     out.append(dict(mode="alb", threshold=100, wg_size=256, grid_wgs=7, launch="host"))
+    # the blocked distribution (Section 4.1's alternative)
+    for thr in (0, 64, 1024):
+        for launch in ("host", "persistent"):
+            out.append(dict(mode="alb", threshold=thr, distribution=1, launch=launch))
+    out.append(dict(mode="lb_all", distribution=1, wg_size=64, grid_wgs=2, launch="persistent"))
     return out
 
 
@@ -140,6 +145,19 @@ def test_cc_matrix(alb, name):
         lab, _ = alb.cc(dg, **c)
         assert np.array_equal(lab, ref), (name, c)
     check_no_dedup(alb, lambda **o: alb.cc(dg, **o)[0], ref, g)
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_kcore_matrix(alb, name):
+    g = gg.symmetrised(graph(name))
+    dg = device_graph(alb, name, symmetric=True)
+    maxdeg = dg.max_out_degree
+    ks = sorted({0, 1, 2, 3, 5, 16, max(1, maxdeg // 2), maxdeg, maxdeg + 1})
+    refs = {k: oracle.kcore(g, k) for k in ks}
+    for i, c in enumerate(configs(maxdeg)):
+        for k in (ks if i % 7 == 0 else ks[1:4]):
+            got, st = alb.kcore(dg, k, **c)
+            assert np.array_equal(got, refs[k]), (name, k, c)
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
@@ -229,13 +247,19 @@ def test_option_errors(alb):
         alb.bfs(dg, 0, wg_size=128)
     assert e.value.status == alb.ALB_E_UNSUPPORTED
     with pytest.raises(alb.AlbError) as e:
-        alb.bfs(dg, 0, distribution=1)
+        alb.bfs(dg, 0, distribution=2)
     assert e.value.status == alb.ALB_E_UNSUPPORTED
     with pytest.raises(alb.AlbError) as e:
         alb.bfs(dg, dg.n)
     assert e.value.status == alb.ALB_E_INVAL
     with pytest.raises(alb.AlbError) as e:
         alb.cc(dg)  # not symmetric
+    assert e.value.status == alb.ALB_E_INVAL
+    with pytest.raises(alb.AlbError) as e:
+        alb.kcore(dg, 2)  # not symmetric
+    assert e.value.status == alb.ALB_E_INVAL
+    with pytest.raises(alb.AlbError) as e:
+        alb.kcore(device_graph(alb, "rmat14", symmetric=True), -1)
     assert e.value.status == alb.ALB_E_INVAL
     with pytest.raises(alb.AlbError) as e:
         alb.bfs(dg, 0, launch="persistent", grid_wgs=10**6)
