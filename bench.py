@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--threshold", type=int, default=None,
-                    help="huge-degree threshold for the ALB run (default: the library's, 4 x workgroup size)")
+                    help="huge-degree threshold for the ALB run (default: the library's, min(16 x workgroup size, 4096))")
     ap.add_argument("--launch", default="auto")
     ap.add_argument("--no-sweep", action="store_true", help="skip the threshold sweep over powers of two")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -285,8 +285,10 @@ def bench_batch(args, alb, gg):
     q = len(members)
     edges = int(sum(graphs[int(m)].m for m in members))  # TEPS over each query's whole graph
 
+    bopts = {} if args.threshold is None else {"threshold": args.threshold}
+
     def batched():
-        return alb.sssp_batch(gset, members, sources, outs=outs)[1]
+        return alb.sssp_batch(gset, members, sources, outs=outs, **bopts)[1]
 
     for _ in range(args.warmup):
         batched()
@@ -404,7 +406,8 @@ def bench_zipf24(args, alb, gg):
     log("zipf24: n=%d m=%d max_deg=%d (%.1fs)" % (g.n, g.m, deg.max(), time.perf_counter() - t))
     dg = alb.Graph(g.off, g.col)
     out = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+    alb_opts = {} if args.threshold is None else {"threshold": args.threshold}
+    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
         ms, st = timed(alb.bfs, dg, out, opts, src)
         m_r = int(deg[out.cpu().numpy() < alb.INF].sum())
         b = alb.algorithmic_bytes("bfs", st)
@@ -414,7 +417,7 @@ def bench_zipf24(args, alb, gg):
                                             "huge_vertices": st["huge_vertices"]}
         log("bfs %s: %.3f ms" % (label, ms))
     outf = torch.empty(g.n, dtype=torch.float32, device="cuda")
-    for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
         ms, st = timed(alb.pagerank, dg, outf, opts, 0.85, 50)
         b = alb.algorithmic_bytes("pagerank", st, n=g.n, iterations=50)
         res.setdefault("pagerank", {})[label] = {"kernel_ms": round(ms, 3),
@@ -426,7 +429,7 @@ def bench_zipf24(args, alb, gg):
     t = time.perf_counter()
     ds = alb.Graph(g.off, g.col, build_symmetric=True)
     log("symmetrised: m=%d (%.1fs)" % (ds.m, time.perf_counter() - t))
-    for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
         ms, st = timed(lambda d, out=None, **o: alb.cc(d, out=out, **o), ds, out, opts)
         b = alb.algorithmic_bytes("cc", st)
         res.setdefault("cc", {})[label] = {"kernel_ms": round(ms, 3),
@@ -440,7 +443,7 @@ def bench_zipf24(args, alb, gg):
     dgr = alb.Graph(gr.off, gr.col, gr.w)
     outg = torch.empty(gr.n, dtype=torch.int32, device="cuda")
     for kind, fn in (("bfs", alb.bfs), ("sssp", alb.sssp)):
-        for label, opts in (("alb", {}), ("twc_only", {"mode": "twc"})):
+        for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
             ms, st = timed(fn, dgr, outg, opts, 0)
             res.setdefault("grid2048_" + kind, {})[label] = {"kernel_ms": round(ms, 3), "rounds": st["rounds"],
                                                              "huge_vertices": st["huge_vertices"]}

@@ -82,9 +82,10 @@ enum {
 typedef struct {
   uint32_t struct_size;      /* sizeof(alb_options); set by alb_options_init */
   int32_t mode;              /* alb_mode */
-  int64_t huge_threshold;    /* ALB mode: degree >= this is huge; ALB_THRESHOLD_DEFAULT (-1) = 4 * wg_size
-                                (the edges one workgroup covers in one pass), ALB_THRESHOLD_LAUNCHED (-2) =
-                                the launched thread count (the paper's rule, Section 5) */
+  int64_t huge_threshold;    /* ALB mode: degree >= this is huge; ALB_THRESHOLD_DEFAULT (-1) =
+                                min(16 * wg_size, 4096) (four passes of one workgroup over a vertex's edges,
+                                at most 4,096), ALB_THRESHOLD_LAUNCHED (-2) = the launched thread count (the
+                                paper's rule, Section 5) */
   int32_t wg_size;           /* 0 = 256; one of 64, 256, 1024 */
   int32_t wave_cutoff;       /* TWC wavefront bin: degree >= this (0 = 64) */
   int32_t wg_cutoff;         /* TWC workgroup bin: degree >= this (0 = wg_size) */

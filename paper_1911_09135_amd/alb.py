@@ -25,7 +25,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 ALB_E_TIMEOUT, ALB_E_CANCELLED = -7, -8
 ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC = 1, 2
-# 4 * wg_size; the launched thread count (the paper's rule); 64 in rounds smaller than the grid, else default
+# min(16 * wg_size, 4096); the launched thread count (the paper's rule); 64 in rounds smaller than the grid,
+# else default
 THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED, THRESHOLD_ADAPTIVE = -1, -2, -3
 MODES = {"alb": 0, "twc": 1, "twc_only": 1, "lb_all": 2}
 LAUNCHES = {"auto": 0, "host": 1, "host_loop": 1, "persistent": 2}
