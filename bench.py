@@ -425,7 +425,23 @@ def bench_zipf24(args, alb, gg):
                                                  "achieved_gbs": round(b / ms / 1e6, 1),
                                                  "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
         log("pagerank %s: %.3f ms" % (label, ms))
+    push_rank = outf.cpu().numpy()
     dg.close()
+    # the paper's pr: pull over the in-edges, classified by in-degree
+    t = time.perf_counter()
+    dt = alb.Graph(g.off, g.col, build_transpose=True)
+    log("transposed (%.1fs)" % (time.perf_counter() - t))
+    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+        ms, st = timed(alb.pagerank_pull, dt, outf, opts, 0.85, 50)
+        b = alb.algorithmic_bytes("pagerank", st, n=g.n, iterations=50)
+        res.setdefault("pagerank_pull", {})[label] = {"kernel_ms": round(ms, 3),
+                                                      "gteps": round(50 * g.m / ms / 1e6, 3),
+                                                      "achieved_gbs": round(b / ms / 1e6, 1),
+                                                      "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                                      "huge_vertices": st["huge_vertices"]}
+        log("pagerank pull %s: %.3f ms" % (label, ms))
+    res["pagerank_pull"]["equals_push"] = bool(np.array_equal(outf.cpu().numpy(), push_rank))
+    dt.close()
     t = time.perf_counter()
     ds = alb.Graph(g.off, g.col, build_symmetric=True)
     log("symmetrised: m=%d (%.1fs)" % (ds.m, time.perf_counter() - t))

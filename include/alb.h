@@ -76,7 +76,8 @@ enum { ALB_THRESHOLD_DEFAULT = -1, ALB_THRESHOLD_LAUNCHED = -2, ALB_THRESHOLD_AD
 /* Graph creation flags. */
 enum {
   ALB_SYMMETRIC = 1u,       /* caller asserts the CSR already holds both directions of every edge */
-  ALB_BUILD_SYMMETRIC = 2u  /* create adds the reverse of every edge on the host (for alb_cc) */
+  ALB_BUILD_SYMMETRIC = 2u, /* create adds the reverse of every edge on the host (for alb_cc, alb_kcore) */
+  ALB_BUILD_TRANSPOSE = 4u  /* create also keeps the in-edge CSR on the device (for alb_pagerank_pull) */
 };
 
 typedef struct {
@@ -338,6 +339,16 @@ alb_status alb_server_stats_get(alb_server s, alb_server_stats *st);
  * a no-op.  Records of completed requests that were never waited for are
  * dropped. */
 alb_status alb_server_destroy(alb_server s);
+
+/* PageRank as the paper's pr does it (pull, Section 5): the same iteration
+ * and arguments as alb_pagerank, but every vertex sums its in-neighbours'
+ * rank(u)/outdeg(u) over the transposed graph, and the balancer classifies
+ * vertices by in-degree.  The sums use the same exact fixed point, so the
+ * ranks equal alb_pagerank's bit for bit.  Needs a handle created with
+ * ALB_BUILD_TRANSPOSE (ALB_E_INVAL otherwise); one persistent launch only
+ * (launch = HOST_LOOP is ALB_E_UNSUPPORTED). */
+alb_status alb_pagerank_pull(alb_graph g, float damping, int32_t iterations, float *rank, const alb_options *opt,
+                             alb_stats *stats);
 
 /* One round of the balancer on an explicit frontier, with an operator that
  * records instead of updating labels (for checking the distribution).  Host

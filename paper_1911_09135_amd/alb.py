@@ -24,7 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 ALB_E_TIMEOUT, ALB_E_CANCELLED = -7, -8
-ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC = 1, 2
+ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC, ALB_BUILD_TRANSPOSE = 1, 2, 4
 # min(16 * wg_size, 4096); the launched thread count (the paper's rule); 64 in rounds smaller than the grid,
 # else default
 THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED, THRESHOLD_ADAPTIVE = -1, -2, -3
@@ -124,6 +124,7 @@ _sig = {
     "alb_cc": ([_vp, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_pagerank": ([_vp, _f32, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_kcore": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_pagerank_pull": ([_vp, _f32, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_graph_create_set": ([_i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
     "alb_graph_members": ([_vp, ctypes.POINTER(_i32)], ctypes.c_int),
     "alb_graph_member_info": ([_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
@@ -211,11 +212,13 @@ def _i32arr(a) -> np.ndarray:
 class Graph:
     """Device-resident CSR graph (alb_graph_create)."""
 
-    def __init__(self, off, col, weights=None, symmetric: bool = False, build_symmetric: bool = False):
+    def __init__(self, off, col, weights=None, symmetric: bool = False, build_symmetric: bool = False,
+                 build_transpose: bool = False):
         off, col = _i32arr(off), _i32arr(col)
         w = None if weights is None else _i32arr(weights)
         n = off.shape[0] - 1
-        flags = (ALB_SYMMETRIC if symmetric else 0) | (ALB_BUILD_SYMMETRIC if build_symmetric else 0)
+        flags = (ALB_SYMMETRIC if symmetric else 0) | (ALB_BUILD_SYMMETRIC if build_symmetric else 0) | \
+            (ALB_BUILD_TRANSPOSE if build_transpose else 0)
         h = _vp()
         _check(_lib.alb_graph_create(n, col.shape[0], off.ctypes.data, col.ctypes.data if col.size else None,
                                      None if w is None else w.ctypes.data, flags, ctypes.byref(h)),
@@ -585,6 +588,11 @@ def cc(g: Graph, out=None, **opts):
 def kcore(g: Graph, k: int, out=None, **opts):
     """k-core membership (int32 1/0) of a symmetric graph and the stats dict."""
     return _run(_lib.alb_kcore, g, out, np.int32, opts, int(k))
+
+
+def pagerank_pull(g: Graph, damping: float = 0.85, iterations: int = 50, out=None, **opts):
+    """PageRank by pull over the in-edges (graph built with build_transpose)."""
+    return _run(_lib.alb_pagerank_pull, g, out, np.float32, opts, ctypes.c_float(damping), int(iterations))
 
 
 def pagerank(g: Graph, damping: float = 0.85, iterations: int = 50, out=None, **opts):

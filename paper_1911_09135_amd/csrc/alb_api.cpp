@@ -122,6 +122,7 @@ struct alb_graph_s {
   int cus = 0;
   uint64_t clock_khz = 100000;
   int32_t *d_off = nullptr, *d_col = nullptr, *d_w = nullptr;
+  int32_t *d_toff = nullptr, *d_tcol = nullptr;  // transposed CSR (ALB_BUILD_TRANSPOSE)
   hipStream_t stream = nullptr;
   size_t graph_bytes = 0;
   std::mutex mu;
@@ -456,7 +457,8 @@ alb_status resident_workgroups(alb_graph g, OpKind op, int wg, int *out, bool ba
   auto it = g_res.find(key);
   if (it == g_res.end()) {
     int per_cu = 0;
-    HIP_TRY(batch ? batch_occupancy(op, wg, &per_cu) : persistent_occupancy(op, wg, &per_cu));
+    HIP_TRY(batch ? batch_occupancy(op, wg, &per_cu)
+                  : op == OP_PR_PULL ? pull_occupancy(wg, &per_cu) : persistent_occupancy(op, wg, &per_cu));
     if (per_cu < 1) return fail(ALB_E_DEVICE, "persistent kernel does not fit on a CU with wg_size %d", wg);
     it = g_res.emplace(key, per_cu * g->cus).first;
   }
@@ -595,7 +597,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   uint64_t qcap;
   if (o.worklist_capacity > 0)
     qcap = (uint64_t)o.worklist_capacity;
-  else if (job.op == OP_BFS || dedup || job.op == OP_PR || job.op == OP_KCORE)
+  else if (job.op == OP_BFS || dedup || job.op == OP_PR || job.op == OP_PR_PULL || job.op == OP_KCORE)
     qcap = (uint64_t)g->n;
   else
     qcap = (uint64_t)g->n + (uint64_t)g->m;
@@ -649,7 +651,12 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     a.kcore_k = job.k;
     a.out = dev_out ? (int32_t *)dev_out : ws->labels;
   }
-  if (job.op == OP_PR) {
+  if (job.op == OP_PR_PULL) {
+    a.contrib = (float *)ws->labels;  // ws->labels has room for n fp32
+    a.toff = g->d_toff;
+    a.tcol = g->d_tcol;
+  }
+  if (job.op == OP_PR || job.op == OP_PR_PULL) {
     a.rank = dev_out ? (float *)dev_out : ws->rank;
     a.acc = ws->acc;
     a.damping = job.damping;
@@ -675,14 +682,22 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     a.prof_wg = prof.p;
   }
   HIP_TRY(hipEventRecord(ws->ev[0], stream));
-  HIP_TRY(launch_init(job.op, a, job.source, job.nfront0, stream));
+  if (job.op == OP_PR_PULL) {
+    HIP_TRY(launch_init(OP_PR, a, -1, job.nfront0, stream));
+    HIP_TRY(launch_pull_prepare(a, stream));
+  } else {
+    HIP_TRY(launch_init(job.op, a, job.source, job.nfront0, stream));
+  }
   HIP_TRY(hipEventRecord(ws->ev[1], stream));
 
   int launches = 0;
   int rounds = 0;
   if (launch == ALB_LAUNCH_PERSISTENT) {
     if (job.max_rounds > 0) {
-      HIP_TRY(launch_persistent(job.op, wg, grid, a, stream));
+      if (job.op == OP_PR_PULL)
+        HIP_TRY(launch_pull_pr(wg, grid, a, stream));
+      else
+        HIP_TRY(launch_persistent(job.op, wg, grid, a, stream));
       launches = 1;
     }
   } else {
@@ -752,7 +767,7 @@ alb_status traverse(alb_graph g, const Job &job, void *out, size_t elem, const a
   s = run_job(g, job, o, o.out_on_device ? out : nullptr, st, guard, ro);
   if (s != ALB_OK) return s;
   if (!o.out_on_device) {
-    const void *src = job.op == OP_PR ? (const void *)ro.d_rank : (const void *)ro.d_labels;
+    const void *src = (job.op == OP_PR || job.op == OP_PR_PULL) ? (const void *)ro.d_rank : (const void *)ro.d_labels;
     HIP_TRY(hipMemcpyAsync(out, src, elem * (size_t)g->n, hipMemcpyDeviceToHost, ro.stream));
     HIP_TRY(hipStreamSynchronize(ro.stream));
   }
@@ -1218,7 +1233,7 @@ std::array<uint8_t, 32> degree_signature(int32_t n, const int32_t *off, int32_t 
 
 // Copy a validated host CSR to the device and make the handle.
 alb_status make_graph(int32_t n, int64_t mm, const int32_t *off, const int32_t *cl, const int32_t *w, bool symmetric,
-                      alb_graph *out) {
+                      alb_graph *out, bool transpose = false) {
   int32_t maxd = 0;
   for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, off[v + 1] - off[v]);
   int dev = 0;
@@ -1229,6 +1244,8 @@ alb_status make_graph(int32_t n, int64_t mm, const int32_t *off, const int32_t *
     (void)hipFree(g->d_off);
     (void)hipFree(g->d_col);
     (void)hipFree(g->d_w);
+    (void)hipFree(g->d_toff);
+    (void)hipFree(g->d_tcol);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
     return st;
@@ -1255,6 +1272,28 @@ alb_status make_graph(int32_t n, int64_t mm, const int32_t *off, const int32_t *
       (e = dalloc(&g->d_col, (size_t)mm, bytes)) != hipSuccess ||
       (w && (e = dalloc(&g->d_w, (size_t)mm, bytes)) != hipSuccess))
     return cleanup(fail(e == hipErrorOutOfMemory ? ALB_E_NOMEM : ALB_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e)));
+  if (transpose) {
+    // in-edges of every vertex, sources ascending (counting sort)
+    std::vector<int32_t> toff, tcol;
+    try {
+      toff.assign((size_t)n + 1, 0);
+      tcol.resize((size_t)mm);
+    } catch (const std::bad_alloc &) {
+      return cleanup(fail(ALB_E_NOMEM, "host allocation failed"));
+    }
+    for (int64_t p = 0; p < mm; ++p) ++toff[(size_t)cl[p] + 1];
+    for (int32_t v = 0; v < n; ++v) toff[(size_t)v + 1] += toff[(size_t)v];
+    std::vector<int32_t> cur(toff.begin(), toff.end() - 1);
+    for (int32_t u = 0; u < n; ++u)
+      for (int32_t p = off[u]; p < off[u + 1]; ++p) tcol[(size_t)cur[(size_t)cl[p]]++] = u;
+    if ((e = dalloc(&g->d_toff, (size_t)n + 1, bytes)) != hipSuccess ||
+        (e = dalloc(&g->d_tcol, (size_t)mm, bytes)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ALB_E_NOMEM : ALB_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e)));
+    if ((e = hipMemcpy(g->d_toff, toff.data(), sizeof(int32_t) * toff.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (mm && (e = hipMemcpy(g->d_tcol, tcol.data(), sizeof(int32_t) * (size_t)mm, hipMemcpyHostToDevice)) !=
+                   hipSuccess))
+      return cleanup(fail(ALB_E_DEVICE, "hipMemcpy: %s", hipGetErrorString(e)));
+  }
   g->graph_bytes = bytes;
   if ((e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess)
     return cleanup(fail(ALB_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
@@ -1274,7 +1313,8 @@ alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, co
                             const int32_t *weights, uint32_t flags, alb_graph *out) {
   if (!out) return fail(ALB_E_INVAL, "output handle pointer is NULL");
   *out = nullptr;
-  if (flags & ~(uint32_t)(ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) return fail(ALB_E_INVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(uint32_t)(ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC | ALB_BUILD_TRANSPOSE))
+    return fail(ALB_E_INVAL, "unknown flags 0x%x", flags);
   alb_status s = validate_csr(n, m, row_offsets, col, weights);
   if (s != ALB_OK) return s;
   std::vector<int32_t> soff, scol;
@@ -1288,7 +1328,8 @@ alb_status alb_graph_create(int32_t n, int64_t m, const int32_t *row_offsets, co
     mm = (int64_t)scol.size();
     w = nullptr;
   }
-  return make_graph(n, mm, off, cl, w, (flags & (ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) != 0, out);
+  return make_graph(n, mm, off, cl, w, (flags & (ALB_SYMMETRIC | ALB_BUILD_SYMMETRIC)) != 0, out,
+                    (flags & ALB_BUILD_TRANSPOSE) != 0);
 }
 
 alb_status alb_graph_create_set(int32_t count, const int32_t *ns, const int64_t *ms,
@@ -1375,6 +1416,8 @@ alb_status alb_graph_destroy(alb_graph g) {
   (void)hipFree(g->d_off);
   (void)hipFree(g->d_col);
   (void)hipFree(g->d_w);
+  (void)hipFree(g->d_toff);
+  (void)hipFree(g->d_tcol);
   if (g->stream) (void)hipStreamDestroy(g->stream);
   delete g;
   return ALB_OK;
@@ -1474,6 +1517,28 @@ alb_status alb_pagerank(alb_graph g, float damping, int32_t iterations, float *r
   if (iterations < 0) return fail(ALB_E_INVAL, "iterations must be >= 0");
   Job job;
   job.op = OP_PR;
+  job.all_rounds = true;
+  job.nfront0 = (uint32_t)g->n;
+  job.max_rounds = iterations;
+  job.damping = damping;
+  s = traverse(g, job, rank, sizeof(float), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_pagerank_pull(alb_graph g, float damping, int32_t iterations, float *rank, const alb_options *opt,
+                             alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (!rank) return fail(ALB_E_INVAL, "rank is NULL");
+  if (!(damping > 0.0f && damping < 1.0f)) return fail(ALB_E_INVAL, "damping must be in (0, 1)");
+  if (iterations < 0) return fail(ALB_E_INVAL, "iterations must be >= 0");
+  if (!g->d_toff) return fail(ALB_E_INVAL, "alb_pagerank_pull needs a graph created with ALB_BUILD_TRANSPOSE");
+  if (opt && opt->struct_size == sizeof(alb_options) && opt->launch == ALB_LAUNCH_HOST_LOOP)
+    return fail(ALB_E_UNSUPPORTED, "pull PageRank runs as one persistent launch only");
+  Job job;
+  job.op = OP_PR_PULL;
   job.all_rounds = true;
   job.nfront0 = (uint32_t)g->n;
   job.max_rounds = iterations;

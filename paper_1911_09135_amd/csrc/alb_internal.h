@@ -79,7 +79,7 @@ constexpr int kTimeline = 64;
 constexpr int kProfMembers = 8192;
 enum { kProfInspect = 0, kProfWgBin, kProfWaveBin, kProfThreadBin, kProfLb, kProfBarrier, kProfParts };
 
-enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4, OP_KCORE = 5 };
+enum OpKind : int { OP_BFS = 0, OP_SSSP = 1, OP_CC = 2, OP_PR = 3, OP_RECORD = 4, OP_KCORE = 5, OP_PR_PULL = 6 };
 
 // Everything a traversal kernel reads.  Passed by value.
 struct Args {
@@ -115,6 +115,9 @@ struct Args {
   unsigned long long *word;  // SSSP / CC: (label << 32) | tag, tag = 1 + last round that lowered it
   int32_t *out;         // SSSP / CC: int32 labels written by the finishing kernel
   float *rank;          // PageRank: fp32 ranks
+  float *contrib;       // pull PageRank: rank(u) / outdeg(u) of the current iteration
+  const int32_t *toff;  // pull PageRank: transposed CSR (in-edges), n + 1
+  const int32_t *tcol;  //   and m sources
   unsigned long long *acc;  // exact sums of fp32 contributions in 64-bit fixed point (kFix)
   float damping;
   int32_t *hits;        // trace operator
@@ -137,6 +140,11 @@ hipError_t launch_init(OpKind op, const Args &a, int32_t source, uint32_t nfront
 hipError_t launch_twc(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_lb(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_pr_update(int wg, int grid, const Args &a, hipStream_t s);
+// Pull PageRank: every iteration in one persistent launch (after launch_init
+// with OP_PR and launch_pull_prepare).
+hipError_t launch_pull_pr(int wg, int grid, const Args &a, hipStream_t s);
+hipError_t launch_pull_prepare(const Args &a, hipStream_t s);
+hipError_t pull_occupancy(int wg, int *blocks_per_cu);
 hipError_t launch_persistent(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 // SSSP / CC: out[v] = word[v] >> 32; k-core: out[v] = (level[v] >= k).
 hipError_t launch_finish(OpKind op, const Args &a, hipStream_t s);

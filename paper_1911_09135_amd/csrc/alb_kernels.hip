@@ -554,6 +554,43 @@ __device__ __forceinline__ uint32_t twc_chunk(uint32_t nF, uint32_t wgs, int B) 
   return (uint32_t)c;
 }
 
+// Workgroups take runs of consecutive worklist entries one at a time, so a
+// run that takes long does not hold up work queued behind it.  The first run
+// of workgroup g is fixed (entries [g * C0, (g + 1) * C0)) and needs no
+// atomic; later runs are claimed from a counter over the entries beyond
+// those, each sized from the remainder the previous claim's atomic returned
+// (guided self-scheduling): B while plenty remain, then fewer whole
+// wavefronts, so that the phase ends with short runs and the workgroups
+// reach the barrier together.  The counter is only ever touched by the
+// atomic (a plain load of a contended counter is slow).  Thread 0 of the
+// workgroup holds the state; the caller's workgroup barriers separate one
+// claim's reads of the published run from the next claim's writes.
+struct Claims {
+  uint32_t C0, len;
+  unsigned long long S, nxt, seen;
+  bool first;
+  __device__ Claims(uint32_t nF, Grid gr, int B)
+      : C0(twc_chunk(nF, gr.n, B)), len(C0), S((unsigned long long)gr.n * C0),
+        nxt((unsigned long long)gr.id * C0), seen(S), first(true) {}
+  // Publish the next run as (*base, *n); *base >= nF means no more work.
+  __device__ void next(unsigned long long *claim, uint32_t nF, Grid gr, int B, unsigned long long &base,
+                       uint32_t &n) {
+    if (!first) {
+      if (S >= (unsigned long long)nF) {
+        nxt = ~0ull;  // the fixed runs covered the worklist
+      } else {
+        len = twc_chunk(seen < nF ? nF - (uint32_t)seen : 0u, gr.n, B);
+        nxt = S + add_relaxed(claim, (unsigned long long)len);
+        seen = nxt + len;
+      }
+    }
+    first = false;
+    base = nxt;
+    n = len;
+  }
+};
+
+
 template <int B, class Op, bool M>
 __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid gr, int round,
                           const Entry<M> *F, uint32_t nF, Entry<M> *qn, uint32_t *qn_cnt, unsigned long long *hctr,
@@ -566,37 +603,9 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
   unsigned long long *claim = &a.ctl->chunk[round % 3];
   Pusher<Entry<M>> pu{sm.pbuf[tid / kWave], 0u, qn, qn_cnt};
   uint64_t pt = a.profile ? (uint64_t)wall_clock64() : 0;
-  // Workgroups take runs of consecutive worklist entries one at a time, so a
-  // run that takes long does not hold up work queued behind it.  The first
-  // run of workgroup g is fixed (entries [g * C0, (g + 1) * C0)) and needs no
-  // atomic; later runs are claimed from a counter over the entries beyond
-  // those, each sized from the remainder the previous claim's atomic
-  // returned (guided self-scheduling): B while plenty remain, then fewer
-  // whole wavefronts, so that the phase ends with short runs and the
-  // workgroups reach the barrier together.  The counter is only ever
-  // touched by the atomic (a plain load of a contended counter is slow).
-  // (The loop body's workgroup barriers separate one claim's reads of
-  // sm.cbase and sm.clen from the next claim's writes.)
-  const uint32_t C0 = twc_chunk(nF, gr.n, B);
-  const unsigned long long S = (unsigned long long)gr.n * C0;  // entries of the fixed first runs
-  unsigned long long next = (unsigned long long)gr.id * C0, seen = S;  // thread 0's claim state
-  uint32_t len = C0;
-  bool first = true;
+  Claims cl(nF, gr, B);
   for (;;) {
-    if (tid == 0) {
-      if (!first) {
-        if (S >= (unsigned long long)nF) {
-          next = ~0ull;  // the fixed runs covered the worklist
-        } else {
-          len = twc_chunk(seen < nF ? nF - (uint32_t)seen : 0u, gr.n, B);
-          next = S + add_relaxed(claim, (unsigned long long)len);
-          seen = next + len;
-        }
-      }
-      sm.cbase = next;
-      sm.clen = len;
-    }
-    first = false;
+    if (tid == 0) cl.next(claim, nF, gr, B, sm.cbase, sm.clen);
     __syncthreads();
     const unsigned long long base = sm.cbase;
     const uint32_t C = sm.clen;
@@ -1159,6 +1168,263 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
 }
 
 // ---------------------------------------------------------------------------
+// Pull PageRank (the paper's pr, Section 5): each vertex v sums its
+// in-neighbours' contributions c(u) = rank(u) / outdeg(u) over the transposed
+// graph, so no atomic touches a destination label except for the edges of
+// huge in-degree vertices.  Inspection and bins work on in-degrees: the TWC
+// bins reduce each vertex's sum inside one workgroup, wavefront or lane and
+// store it once; the huge vertices' in-edges take the cyclic distribution of
+// Algorithm 2, each wavefront adds its lanes' contributions per vertex
+// (segmented by the owning vertex) with one atomic per segment.  The sums use
+// the same exact 64-bit fixed point as the push version, so both give
+// bitwise the same ranks.
+// ---------------------------------------------------------------------------
+struct OpPRPull {  // type facts for Smem only; the pull phases do the work
+  using val_t = float;
+  struct pre_t {};
+  static constexpr bool kPush = false, kNeedSrc = false, kRecord = false, kPR = true, kBatch = false;
+};
+
+// Fixed-point contributions of up to kU in-edges per lane, loads issued first.
+__device__ __forceinline__ unsigned long long pull_edges(const Args &a, const bool (&act)[kU],
+                                                         const int32_t (&pos)[kU]) {
+  int32_t u[kU];
+#pragma unroll
+  for (int i = 0; i < kU; ++i) u[i] = a.tcol[act[i] ? pos[i] : 0];
+  float c[kU];
+#pragma unroll
+  for (int i = 0; i < kU; ++i) c[i] = a.contrib[u[i]];
+  unsigned long long x = 0;
+#pragma unroll
+  for (int i = 0; i < kU; ++i) x += act[i] ? to_fix(c[i]) : 0ull;
+  return x;
+}
+
+template <int B>
+__device__ unsigned long long block_sum(unsigned long long x, Smem<B, OpPRPull> &sm) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
+  if (lane_id() == 0) sm.dred[threadIdx.x / kWave] = x;
+  __syncthreads();
+  unsigned long long t = 0;
+#pragma unroll
+  for (int j = 0; j < B / kWave; ++j) t += sm.dred[j];
+  __syncthreads();
+  return t;
+}
+
+template <int B>
+__device__ void pull_gather(const Args &a, Smem<B, OpPRPull> &sm, Grid gr, int it, int64_t thr, uint32_t hs,
+                            Acc &acc) {
+  const int tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t nF = (uint32_t)a.n;
+  Claims cl(nF, gr, B);
+  for (;;) {
+    if (tid == 0) cl.next(&a.ctl->chunk[it % 3], nF, gr, B, sm.cbase, sm.clen);
+    __syncthreads();
+    const unsigned long long base = sm.cbase;
+    const uint32_t C = sm.clen;
+    if (base >= nF) break;
+    const uint32_t i = (uint32_t)base + tid;
+    const bool mine = tid < (int)C && i < nF;
+    int32_t v = -1, beg = 0, deg = 0;
+    if (mine) {
+      v = (int32_t)i;
+      beg = a.toff[v];
+      deg = a.toff[v + 1] - beg;
+    }
+    // inspection by in-degree (Algorithm 1); huge vertices wait for phase 2
+    const bool huge = deg > 0 && (int64_t)deg >= thr;
+    reserve_huge(huge, v, beg, deg, 0, a, it, &a.ctl->huge[it & 1], hs, acc);
+    if (huge) deg = 0;
+    acc.frontier += mine;
+    acc.edges_twc += (unsigned long long)deg;
+
+    // workgroup bin: the workgroup sums one vertex's in-edges, then stores
+    for (;;) {
+      if (tid == 0) sm.owner = -1;
+      __syncthreads();
+      if (deg >= a.c_wg) sm.owner = tid;
+      __syncthreads();
+      const int32_t o = sm.owner;
+      if (o < 0) break;
+      if (tid == o) {
+        sm.obeg = beg;
+        sm.odeg = deg;
+        sm.ov = v;
+        deg = 0;
+      }
+      __syncthreads();
+      const int32_t ob = sm.obeg, od = sm.odeg, ov = sm.ov;
+      unsigned long long x = 0;
+      for (int32_t j0 = 0; j0 < od; j0 += kU * B) {
+        bool act[kU];
+        int32_t pos[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          act[u] = j0 + u * B + tid < od;
+          pos[u] = ob + j0 + u * B + tid;
+        }
+        x += pull_edges(a, act, pos);
+      }
+      x = block_sum<B>(x, sm);
+      if (tid == 0) a.acc[ov] = x;
+    }
+    // wavefront bin: one wavefront sums one vertex's in-edges
+    for (;;) {
+      const unsigned long long mm = __ballot(deg >= a.c_wave && deg > 0);
+      if (mm == 0ull) break;
+      const int ld = __ffsll(mm) - 1;
+      const int32_t ob = __shfl(beg, ld), od = __shfl(deg, ld), ov = __shfl(v, ld);
+      if ((int)lane == ld) deg = 0;
+      unsigned long long x = 0;
+      for (int32_t j0 = 0; j0 < od; j0 += kU * kWave) {
+        bool act[kU];
+        int32_t pos[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          act[u] = j0 + u * kWave + (int32_t)lane < od;
+          pos[u] = ob + j0 + u * kWave + (int32_t)lane;
+        }
+        x += pull_edges(a, act, pos);
+      }
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
+      if ((int)lane == ld) a.acc[ov] = x;
+    }
+    // thread bin: each lane sums its own short list (fewer than c_wave edges)
+    if (deg > 0) {
+      unsigned long long x = 0;
+      for (int32_t j0 = 0; j0 < deg; j0 += kU) {
+        bool act[kU];
+        int32_t pos[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          act[u] = j0 + u < deg;
+          pos[u] = beg + j0 + u;
+        }
+        x += pull_edges(a, act, pos);
+      }
+      a.acc[v] = x;
+    }
+    // vertices without in-edges keep the 0 the update phase left
+  }
+}
+
+template <int B>
+__device__ void pull_lb(const Args &a, Grid gr, unsigned long long hc, uint32_t hs, Acc &acc) {
+  const uint32_t vh = (uint32_t)(hc >> 32);
+  const uint32_t e = (uint32_t)hc;
+  if (vh == 0 || ld_relaxed(&a.ctl->overflow) != 0xffffffffu) return;
+  const uint64_t T = (uint64_t)gr.n * B;
+  const uint32_t lane = lane_id();
+  const uint64_t g = (uint64_t)gr.id * B + threadIdx.x;
+  for (uint64_t k0 = g - lane; k0 < e; k0 += kU * T) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint64_t k = k0 + lane + (uint64_t)u * T;
+      const bool act = k < e;
+      int32_t v = -1;
+      unsigned long long x = 0;
+      if (act) {
+        const int4 r = a.huge_rec[owner_of(a, vh, hs, (uint32_t)k)];
+        v = r.z;
+        x = to_fix(a.contrib[a.tcol[r.y + (int32_t)((uint32_t)k - (uint32_t)r.x)]]);
+      }
+      acc.edges_lb += act;
+      // consecutive lanes hold consecutive huge edges, so lanes of one vertex
+      // form one run: add each run with one atomic from its last lane
+      unsigned long long incl = x;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const unsigned long long y = __shfl_up(incl, d);
+        if ((int)lane >= d) incl += y;
+      }
+      const int32_t vprev = __shfl_up(v, 1), vnext = __shfl_down(v, 1);
+      const unsigned long long heads = __ballot(lane == 0 || v != vprev);
+      const int start = 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull));
+      const unsigned long long before = __shfl(incl, start > 0 ? start - 1 : 0);
+      const bool tail = lane == kWave - 1 || v != vnext;
+      if (act && tail) add_relaxed(&a.acc[v], incl - (start > 0 ? before : 0ull));
+    }
+  }
+}
+
+// rank(v) from the sums, the next contributions, the next dangling mass.
+template <int B>
+__device__ void pull_update(const Args &a, Smem<B, OpPRPull> &sm, Grid gr, int it, Acc &acc) {
+  const double d = (double)a.damping;
+  const double N = (double)a.n;
+  const unsigned long long dfix = ld_relaxed(&a.ctl->dangling[it & 1]);
+  const double base = (1.0 - d) / N + d * ((double)dfix * kFixInv) / N;
+  for (uint32_t v = gr.id * B + threadIdx.x; v < (uint32_t)a.n; v += gr.n * B) {
+    const float r = (float)(base + d * ((double)a.acc[v] * kFixInv));
+    a.rank[v] = r;
+    a.acc[v] = 0ull;  // huge vertices' sums start from 0 in the next phase 2
+    const int32_t od = a.off[v + 1] - a.off[v];
+    a.contrib[v] = od > 0 ? r / (float)od : 0.0f;
+    if (od == 0) acc.dangling += to_fix(r);
+  }
+  flush_dangling<B, OpPRPull>(acc, sm, &a.ctl->dangling[(it + 1) & 1]);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER_EU))) void k_pull_pr(Args a) {
+  __shared__ Smem<B, OpPRPull> sm;
+  Acc acc;
+  Grid gr;
+  if (!join_members(a, sm, &gr)) return;
+  if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;
+  const uint32_t hs = hint_shift(a.threshold);
+  unsigned long long epoch = 0;
+  int it = 0;
+  for (; it < a.max_rounds; ++it) {
+    if (gr.id == 0 && threadIdx.x == 0) {
+      st_relaxed(&a.ctl->chunk[(it + 1) % 3], 0ull);
+      st_relaxed(&a.ctl->huge[(it + 1) & 1], 0ull);
+      st_relaxed(&a.ctl->dangling[(it + 1) & 1], 0ull);
+    }
+    pull_gather<B>(a, sm, gr, it, a.threshold, hs, acc);
+    if (!grid_barrier(a, sm, gr, epoch, it)) break;
+    const unsigned long long hc = ld_relaxed(&a.ctl->huge[it & 1]);
+    if ((hc >> 32) != 0) {
+      pull_lb<B>(a, gr, hc, hs, acc);
+      if (!grid_barrier(a, sm, gr, epoch, it)) break;
+    }
+    pull_update<B>(a, sm, gr, it, acc);
+    if (!grid_barrier(a, sm, gr, epoch, it)) break;
+  }
+  if (gr.id == 0 && threadIdx.x == 0) {
+    st_relaxed(&a.ctl->rounds, (uint32_t)it);
+    st_relaxed(&a.ctl->threshold_used, (long long)a.threshold);
+  }
+  flush_stats<B, OpPRPull>(acc, sm, a.ctl);
+}
+
+// Pull set-up after k_init: contributions of the initial ranks and the
+// initial dangling mass (block sums, one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_pull_prepare(Args a) {
+  __shared__ unsigned long long part[256 / kWave];
+  unsigned long long x = 0;
+  const float r0 = 1.0f / (float)a.n;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < (uint32_t)a.n; v += gridDim.x * blockDim.x) {
+    const int32_t od = a.off[v + 1] - a.off[v];
+    a.contrib[v] = od > 0 ? r0 / (float)od : 0.0f;
+    if (od == 0) x += to_fix(r0);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int j = 0; j < 256 / kWave; ++j) t += part[j];
+    if (t) add_relaxed(&a.ctl->dangling[0], t);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch over workgroup size and operator.
 // ---------------------------------------------------------------------------
 
@@ -1292,6 +1558,34 @@ hipError_t launch_finish_batch(OpKind op, const Args &a, int32_t max_n, hipStrea
   if (bx > 64) bx = 64;
   if (bx < 1) bx = 1;
   hipLaunchKernelGGL(k_finish_batch, dim3(bx, a.nq), dim3(threads), 0, s, a, (int)op);
+  return hipGetLastError();
+}
+
+hipError_t pull_occupancy(int wg, int *blocks_per_cu) {
+  switch (wg) {
+    case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_pull_pr<64>, 64, 0);
+    case 256: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_pull_pr<256>, 256, 0);
+    case 1024:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_pull_pr<1024>, 1024, 0);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pull_pr(int wg, int grid, const Args &a, hipStream_t s) {
+  switch (wg) {
+    case 64: hipLaunchKernelGGL(k_pull_pr<64>, dim3(grid), dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL(k_pull_pr<256>, dim3(grid), dim3(256), 0, s, a); break;
+    case 1024: hipLaunchKernelGGL(k_pull_pr<1024>, dim3(grid), dim3(1024), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pull_prepare(const Args &a, hipStream_t s) {
+  int blocks = (int)(((int64_t)a.n + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_pull_prepare, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

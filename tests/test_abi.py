@@ -136,6 +136,7 @@ def test_calls_reject_null_handles(alb):
     assert alb._lib.alb_cc(None, lvl.ctypes.data, None, None) == alb.ALB_E_INVAL
     assert alb._lib.alb_pagerank(None, ctypes.c_float(0.85), 5, lvl.ctypes.data, None, None) == alb.ALB_E_INVAL
     assert alb._lib.alb_kcore(None, 2, lvl.ctypes.data, None, None) == alb.ALB_E_INVAL
+    assert alb._lib.alb_pagerank_pull(None, ctypes.c_float(0.85), 5, lvl.ctypes.data, None, None) == alb.ALB_E_INVAL
     assert alb._lib.alb_graph_info(None, None, None, None, None) == alb.ALB_E_INVAL
     assert alb._lib.alb_graph_destroy(None) == alb.ALB_OK
     assert alb._lib.alb_options_init(None) == alb.ALB_E_INVAL

@@ -147,6 +147,42 @@ def test_cc_matrix(alb, name):
     check_no_dedup(alb, lambda **o: alb.cc(dg, **o)[0], ref, g)
 
 
+def reversed_graph(g):
+    src = np.repeat(np.arange(g.n), g.degrees())
+    return gg.from_edges(g.n, g.col, src)
+
+
+@pytest.mark.parametrize("name", list(GRAPHS) + ["inhubs"])
+def test_pagerank_pull_matrix(alb, name):
+    """Pull PageRank over the in-edges: within L1 1e-5 of the fp64 oracle and
+    bit-identical to the push version (both sum in exact fixed point)."""
+    if name == "inhubs":  # huge in-degrees: the hub graph with every edge reversed
+        g = reversed_graph(graph("hubs"))
+    else:
+        g = graph(name)
+    dg = alb.Graph(g.off, g.col, build_transpose=True)
+    ref = oracle.pagerank(g, 0.85, 50)
+    push, _ = alb.pagerank(dg, 0.85, 50)
+    indeg = np.bincount(g.col, minlength=g.n) if g.m else np.zeros(g.n, np.int64)
+    maxin = int(indeg.max()) if g.n else 0
+    cfgs = [dict()]
+    for thr in (0, 1, 64, 1024, maxin, maxin + 1):
+        for wg in (64, 256, 1024):
+            cfgs.append(dict(threshold=thr, wg_size=wg))
+    cfgs += [dict(mode="twc"), dict(mode="lb_all"), dict(threshold=64, grid_wgs=3, wg_size=64),
+             dict(wave_cutoff=8, wg_cutoff=100, threshold=5000)]
+    for c in cfgs:
+        x, st = alb.pagerank_pull(dg, 0.85, 50, **c)
+        assert np.abs(x.astype(np.float64) - ref).sum() <= PR_L1_TOL, (name, c)
+        assert np.array_equal(x, push), (name, c)
+        assert st["rounds"] == 50
+    x, _ = alb.pagerank_pull(dg, 0.85, 0)
+    assert np.all(x == np.float32(1.0 / g.n))
+    with pytest.raises(alb.AlbError):
+        alb.pagerank_pull(device_graph(alb, "rmat14"), 0.85, 5)  # no transpose
+    dg.close()
+
+
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_kcore_matrix(alb, name):
     g = gg.symmetrised(graph(name))
