@@ -56,6 +56,8 @@ def _load():
         lib.oracle_sssp.argtypes = [i32, vp, vp, vp, i32, vp]
         lib.oracle_cc.restype = ctypes.c_int
         lib.oracle_cc.argtypes = [i32, vp, vp, vp]
+        lib.oracle_symmetrise.restype = i64
+        lib.oracle_symmetrise.argtypes = [i32, vp, vp, vp, vp]
         lib.oracle_kcore.restype = ctypes.c_int
         lib.oracle_kcore.argtypes = [i32, vp, vp, i32, vp]
         lib.oracle_pagerank.restype = ctypes.c_int
@@ -111,6 +113,28 @@ def cc(g) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_cc failed: %d" % rc)
     return out
+
+
+class _Csr:
+    def __init__(self, n, off, col):
+        self.n, self.off, self.col = n, off, col
+        self.m = int(col.shape[0])
+
+
+def symmetrised(g):
+    """The undirected graph of g (both directions, no self-loops or
+    duplicates, rows sorted), as an object with n, off, col."""
+    off, col = _i32(g.off), _i32(g.col)
+    off64 = np.empty(g.n + 1, dtype=np.int64)
+    lib = _load()
+    m = lib.oracle_symmetrise(g.n, _p(off), _p(col), _p(off64), None)
+    if m < 0:
+        raise MemoryError("oracle_symmetrise failed")
+    if m >= 2 ** 31:
+        raise ValueError("symmetrised graph too large")
+    out = np.empty(max(m, 1), dtype=np.int32)
+    lib.oracle_symmetrise(g.n, _p(off), _p(col), _p(off64), _p(out))
+    return _Csr(g.n, off64.astype(np.int32), out[:m])
 
 
 def kcore(g, k: int) -> np.ndarray:

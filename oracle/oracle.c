@@ -189,6 +189,54 @@ int oracle_cc(int32_t n, const int32_t *off, const int32_t *col, int32_t *label)
 }
 
 /* ------------------------------------------------------------------ */
+/* The undirected graph of a CSR: both directions of every edge, self-loops
+ * and duplicates dropped, each row sorted.  Two calls: with out_col == NULL
+ * only the row lengths (out_off) are computed; then the columns. */
+static int cmp_i32(const void *a, const void *b) {
+  const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+int64_t oracle_symmetrise(int32_t n, const int32_t *off, const int32_t *col, int64_t *out_off, int32_t *out_col) {
+  int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  if (!cnt) return -2;
+  for (int32_t u = 0; u < n; ++u)
+    for (int32_t p = off[u]; p < off[u + 1]; ++p) {
+      ++cnt[u + 1];
+      ++cnt[col[p] + 1];
+    }
+  for (int32_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+  const int64_t total = cnt[n];
+  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
+  int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!tmp || !cur) { free(cnt); free(tmp); free(cur); return -2; }
+  for (int32_t v = 0; v < n; ++v) cur[v] = cnt[v];
+  for (int32_t u = 0; u < n; ++u)
+    for (int32_t p = off[u]; p < off[u + 1]; ++p) {
+      const int32_t v = col[p];
+      tmp[cur[u]++] = v;
+      tmp[cur[v]++] = u;
+    }
+  int64_t m = 0;
+  out_off[0] = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    int32_t *row = tmp + cnt[v];
+    const int64_t len = cnt[v + 1] - cnt[v];
+    qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+    for (int64_t i = 0; i < len; ++i) {
+      if (row[i] == v || (i > 0 && row[i] == row[i - 1])) continue;
+      if (out_col) out_col[m] = row[i];
+      ++m;
+    }
+    out_off[v + 1] = m;
+  }
+  free(cnt);
+  free(tmp);
+  free(cur);
+  return m;
+}
+
+/* ------------------------------------------------------------------ */
 /* k-core (the paper's kcore application, Section 5): the k-core of an
  * undirected graph is its largest subgraph in which every vertex has at least
  * k neighbours.  Peeling: every vertex of degree < k is removed; removing a

@@ -4,7 +4,8 @@
   the highest-degree vertex: every distance equal to Dijkstra's.
   Zipf(1.9) out-degree graph, n = 2^24, degrees capped at 4,194,304 (~372M
   edges): BFS levels equal to the queue BFS, CC labels equal to union-find,
-  PageRank (50 iterations) within L1 1e-5 of the fp64 oracle.
+  PageRank (50 iterations, push and pull) within L1 1e-5 of the fp64 oracle.
+  k-core membership on the Zipf graph with 2^20 vertices equal to peeling.
 """
 import os
 import time
@@ -89,6 +90,27 @@ def test_cc_zipf24_full(alb, zipf24):
     dg.close()
 
 
+def test_kcore_zipf20():
+    """k-core on the symmetrised Zipf(1.9) graph with 2^20 vertices (capped at
+    2^18; ~46M undirected edge entries): membership equal to the oracle's
+    peeling for several k, under the default balancer and TWC only."""
+    from paper_1911_09135_amd import alb
+
+    g = gg.zipf(1 << 20, 1.9, 1 << 18, seed=230)
+    t = time.time()
+    gs = oracle.symmetrised(g)
+    log("symmetrised for the oracle in %.1fs: m=%d" % (time.time() - t, gs.m))
+    dg = alb.Graph(g.off, g.col, None, build_symmetric=True)
+    assert dg.m == gs.m
+    for k in (2, 12, 16, 18, 20, 24):  # the core shrinks from almost all vertices to none
+        ref = oracle.kcore(gs, k)
+        for c in (dict(), dict(mode="twc")):
+            got, st = alb.kcore(dg, k, **c)
+            assert np.array_equal(got, ref), (k, c)
+        log("kcore k=%d ok: %d in core, rounds %d" % (k, int(ref.sum()), st["rounds"]))
+    dg.close()
+
+
 def test_pagerank_zipf24_full(alb, zipf24):
     g = zipf24
     t = time.time()
@@ -105,6 +127,13 @@ def test_pagerank_zipf24_full(alb, zipf24):
         assert np.array_equal(x, x0)
         log("pagerank %s ok: L1 %.2e, %.2f ms" % (c, err, st["device_ms"]))
     dg.close()
+    # the pull version over the transposed graph: the same ranks bit for bit
+    dt = alb.Graph(g.off, g.col, build_transpose=True)
+    for c in [dict(), dict(threshold=22)]:
+        x, st = alb.pagerank_pull(dt, 0.85, 50, **c)
+        assert np.array_equal(x, x0), c
+        log("pagerank pull %s ok: huge %d, %.2f ms" % (c, st["huge_vertices"], st["device_ms"]))
+    dt.close()
 
 
 def test_sssp_batch_rmat_set_full(alb):

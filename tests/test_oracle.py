@@ -304,6 +304,15 @@ def test_kcore_closed_forms():
     assert np.array_equal(oracle.kcore(g, 4), np.array([1] * 5 + [0] * 3, np.int32))
 
 
+def test_symmetrised_matches_edge_list_construction():
+    """The oracle's C symmetrisation equals the undirected graph built from the
+    edge list in Python (both directions, no self-loops or duplicates)."""
+    for g in (gg.rmat(10, seed=3), gg.random_digraph(500, 3000, 2), gg.star(20), gg.edgeless(4),
+              gg.from_edges(5, [0, 1, 1, 2, 3], [1, 0, 1, 4, 3], keep_self_loops=True)):
+        a, b = oracle.symmetrised(g), gg.symmetrised(g)
+        assert np.array_equal(a.off, b.off) and np.array_equal(a.col, b.col)
+
+
 def test_kcore_invariants_rmat():
     g = gg.symmetrised(gg.rmat(12, 8, seed=5))
     prev = np.ones(g.n, np.int32)
