@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--requests", type=int, default=5000, help="serve: requests per arrival rate")
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates per second")
     ap.add_argument("--tune", action="store_true", help="batch: also run with autotuned settings")
+    ap.add_argument("--random-probe", action="store_true",
+                    help="only measure plain random 8-byte gathers (the access pattern of the label reads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -103,6 +105,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                           "launches": max(args.steps, 1)}))
         return
+
+    if args.random_probe:
+        return random_probe(args)
 
     import graphgen as gg
     from paper_1911_09135_amd import alb
@@ -204,6 +209,20 @@ def main():
                      "bit_exact": bool(np.array_equal(lev, _oracle.bfs(g14, 0)))}
         d14.close()
 
+    # the access pattern's own ceiling: plain random 8-byte gathers from a
+    # table the size of the label array, as many as the query examined edges
+    random_access = None
+    if not args.only_alb:
+        ex = int(np.mean([s["edges_examined"] for s in stats]))
+        probe = gather_rate(g.n, ex)
+        kernel_rate = ex / (float(np.mean(kms)) * 1e-3)
+        random_access = {"probe": "torch index_select of int64 words at uniform random indices, table = label "
+                                  "array (%d words), %d indices" % (g.n, ex),
+                         "probe_reads_per_s_g": round(probe / 1e9, 2),
+                         "kernel_edges_per_s_g": round(kernel_rate / 1e9, 2),
+                         "frac": round(kernel_rate / probe, 3)}
+        log("random-access ceiling: %.1f G reads/s; kernel %.1f G edges/s" % (probe / 1e9, kernel_rate / 1e9))
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -250,6 +269,7 @@ def main():
                      "work_efficient_bytes": we_bytes, "work_efficient_gbs": round(we_achieved, 1),
                      "work_efficient_frac": round(we_achieved / HBM_PEAK_GBS, 4),
                      "kernel_ms": round(float(np.mean(kms)), 4)},
+        "random_access": random_access,
         "cpu_baseline": cpu,
         "alb_stats": {k: stats[-1][k] for k in ("frontier_vertices", "edges_examined", "huge_vertices",
                                                   "huge_edges", "pushes")},
@@ -262,6 +282,56 @@ def main():
         res["bfs_small"] = bfs_small
     dg.close()
     print(json.dumps(res), flush=True)
+
+
+def gather_rate(words: int, n_idx: int, reps: int = 5) -> float:
+    """Random 8-byte reads per second that torch's gather sustains from a
+    table of `words` int64 words (uniform random indices, event-timed)."""
+    import torch
+
+    table = torch.arange(words, dtype=torch.int64, device="cuda")
+    idx = torch.randint(0, words, (n_idx,), dtype=torch.int64, device="cuda")
+    out = torch.empty(n_idx, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        torch.index_select(table, 0, idx, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.index_select(table, 0, idx, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = n_idx * reps / (e0.elapsed_time(e1) * 1e-3)
+    del table, idx, out
+    return rate
+
+
+def random_probe(args):
+    """What the device sustains for the label access pattern alone: torch's
+    gather of 8-byte words at uniformly random indices from tables of the
+    RMAT-22 label size (4,194,304 words, 33.5 MB), a quarter of it and 16x
+    it, 128M indices per call, timed with events.  A reference point for
+    the traversal's random-access rate, not part of it."""
+    import torch
+
+    res = {}
+    n_idx = 1 << 27
+    for words in (1 << 20, 1 << 22, 1 << 26):
+        table = torch.arange(words, dtype=torch.int64, device="cuda")
+        idx = torch.randint(0, words, (n_idx,), dtype=torch.int64, device="cuda")
+        out = torch.empty(n_idx, dtype=torch.int64, device="cuda")
+        for _ in range(2):
+            torch.index_select(table, 0, idx, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            torch.index_select(table, 0, idx, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        res[str(words * 8)] = {"ms": round(ms, 3), "random_reads_per_s_g": round(n_idx / ms / 1e6, 2),
+                               "stream_gbs": round(16 * n_idx / ms / 1e6, 1)}
+        log("table %d MB: %.3f ms, %.2f G random reads/s" % (words * 8 >> 20, ms, n_idx / ms / 1e6))
+    print(json.dumps({"random_probe": res, "indices": n_idx}), flush=True)
 
 
 def bench_batch(args, alb, gg):
