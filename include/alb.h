@@ -73,6 +73,9 @@ typedef enum { ALB_LAUNCH_AUTO = 0, ALB_LAUNCH_HOST_LOOP = 1, ALB_LAUNCH_PERSIST
  * DEFAULT value otherwise. */
 enum { ALB_THRESHOLD_DEFAULT = -1, ALB_THRESHOLD_LAUNCHED = -2, ALB_THRESHOLD_ADAPTIVE = -3 };
 
+/* Special value of alb_options.grid_wgs: every workgroup the device holds. */
+enum { ALB_GRID_ALL = -1 };
+
 /* Graph creation flags. */
 enum {
   ALB_SYMMETRIC = 1u,       /* caller asserts the CSR already holds both directions of every edge */
@@ -94,7 +97,9 @@ typedef struct {
                                 (the default); 1 = blocked, thread i takes edges [i*c, (i+1)*c), c = ceil(e/T) */
   int32_t dedup;             /* -1 = default (on for sssp and cc), 0 = off, 1 = on */
   int32_t launch;            /* alb_launch */
-  int32_t grid_wgs;          /* 0 = every resident workgroup; else this many workgroups */
+  int32_t grid_wgs;          /* 0 = automatic: about 2 * cbrt(edges) workgroups of 256 threads (edges of the
+                                graph, or of a batch's queries), at least 16, at most every resident one;
+                                ALB_GRID_ALL (-1) = every resident workgroup; else this many */
   int64_t worklist_capacity; /* 0 = automatic (n with dedup, n + m without) */
   void *stream;              /* hipStream_t; NULL = the library's stream */
   uint32_t out_on_device;    /* outputs are device pointers (see above) */
@@ -263,7 +268,8 @@ alb_status alb_autotune_reset(void);
  * (44 bytes per vertex of the query's member, plus 64) sum to at most
  * hbm_budget / lanes -- and run them as one batch (alb_bfs_batch /
  * alb_sssp_batch) on the lane's own stream with 1/lanes of the device's
- * workgroups.  So requests that arrive while batches are running join the
+ * workgroups (all of them when no other lane is running, see
+ * whole_device_when_alone).  So requests that arrive while batches are running join the
  * next batch of the first lane to free up, and the lanes' batches overlap
  * on the device.  Results land in the caller's host array; a request's
  * latency runs from submit to that array being filled.
@@ -288,7 +294,9 @@ typedef struct {
   void *executor_user;
   int32_t n_members;         /* with a custom executor and no graph: member count ... */
   const int32_t *member_vertices; /* ... and each member's vertex count (copied) */
-  int32_t reserved[8];
+  int32_t whole_device_when_alone; /* a batch that starts while no other lane runs uses every resident
+                                      workgroup instead of its lane's share (1 = on, the default) */
+  int32_t reserved[7];
 } alb_server_config;
 
 typedef struct {

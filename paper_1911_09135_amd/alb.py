@@ -28,6 +28,7 @@ ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC, ALB_BUILD_TRANSPOSE = 1, 2, 4
 # min(16 * wg_size, 4096); the launched thread count (the paper's rule); 64 in rounds smaller than the grid,
 # else default
 THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED, THRESHOLD_ADAPTIVE = -1, -2, -3
+GRID_ALL = -1  # grid_wgs: every resident workgroup (0 = automatic)
 MODES = {"alb": 0, "twc": 1, "twc_only": 1, "lb_all": 2}
 LAUNCHES = {"auto": 0, "host": 1, "host_loop": 1, "persistent": 2}
 INF = np.iinfo(np.int32).max
@@ -93,7 +94,8 @@ class ServerConfig(ctypes.Structure):
         ("executor_user", ctypes.c_void_p),
         ("n_members", ctypes.c_int32),
         ("member_vertices", ctypes.POINTER(ctypes.c_int32)),
-        ("reserved", ctypes.c_int32 * 8),
+        ("whole_device_when_alone", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -458,10 +460,12 @@ class Server:
     when no graph set is given."""
 
     def __init__(self, gs: Optional[GraphSet] = None, lanes: int = 2, max_batch: int = 256, max_wait_us: int = 0,
-                 hbm_budget: int = 0, executor=None, member_vertices=None, **opts):
+                 hbm_budget: int = 0, executor=None, member_vertices=None, whole_device_when_alone: bool = True,
+                 **opts):
         cfg = ServerConfig()
         _check(_lib.alb_server_config_init(ctypes.byref(cfg)), "alb_server_config_init")
         cfg.lanes, cfg.max_batch, cfg.max_wait_us, cfg.hbm_budget = lanes, max_batch, max_wait_us, hbm_budget
+        cfg.whole_device_when_alone = 1 if whole_device_when_alone else 0
         cfg.options = make_options(**opts)
         if gs is not None:
             self.member_n = [m[0] for m in gs.members]

@@ -8,6 +8,9 @@ namespace alb {
 // Set the calling thread's alb_last_error() text; returns s.
 alb_status set_error(alb_status s, const char *fmt, ...);
 
+// The automatic grid of a traversal over `edges` edges (alb_options.grid_wgs = 0).
+int auto_grid(int64_t edges, int wg, int resident);
+
 // Workgroups of `wg` threads the device holds at once for a batch launch of
 // `algo` on g's device.
 alb_status batch_resident_workgroups(alb_graph g, int32_t algo, int32_t wg, int *out);

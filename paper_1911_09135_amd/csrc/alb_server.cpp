@@ -55,7 +55,9 @@ struct alb_server_s {
   std::vector<int32_t> member_n;
   std::vector<int64_t> member_m;
   size_t lane_budget = 0;
-  int grid[2] = {0, 0};  // workgroups per lane, by algo
+  int grid[2] = {0, 0};      // workgroups per lane, by algo
+  int grid_all[2] = {0, 0};  // every resident workgroup, by algo
+  int busy_lanes = 0;        // lanes running a batch
   std::vector<hipStream_t> streams;
   std::vector<std::thread> lanes;
 
@@ -84,14 +86,19 @@ struct alb_server_s {
   }
 
   // Run one batch on lane `lane` (no lock held).
-  int32_t execute(int lane, int32_t algo, std::vector<int32_t> &mb, std::vector<int32_t> &src,
-                  std::vector<int32_t *> &outs) {
+  int32_t execute(int lane, int32_t algo, bool alone, int64_t edges, std::vector<int32_t> &mb,
+                  std::vector<int32_t> &src, std::vector<int32_t *> &outs) {
     const int32_t n = (int32_t)mb.size();
     if (cfg.executor) return cfg.executor(cfg.executor_user, algo, n, mb.data(), src.data(), outs.data(), lane);
     alb_options o = cfg.options;
     o.stream = streams[lane];
     o.out_on_device = 0;
-    o.grid_wgs = grid[algo];
+    // the batch's automatic grid, capped by the lane's share of the device,
+    // or by the whole device when no other lane runs (if the other lane's
+    // batch reaches the device first, a batch launched just before it runs
+    // on the workgroups still free: correct, only narrower)
+    const int cap = alone && cfg.whole_device_when_alone ? grid_all[algo] : grid[algo];
+    o.grid_wgs = alb::auto_grid(edges, o.wg_size ? o.wg_size : 256, cap);
     return algo == ALB_ALGO_BFS ? alb_bfs_batch(g, n, mb.data(), src.data(), outs.data(), nullptr, &o, nullptr)
                                 : alb_sssp_batch(g, n, mb.data(), src.data(), outs.data(), nullptr, &o, nullptr);
   }
@@ -157,9 +164,11 @@ struct alb_server_s {
       }
       running += (int)batch.size();
       ++st.batches;
+      const bool alone = busy_lanes == 0;
+      ++busy_lanes;
       lk.unlock();
       const Clock::time_point t0 = Clock::now();
-      const int32_t status = execute(lane, algo, mb, src, outs);
+      const int32_t status = execute(lane, algo, alone, edges, mb, src, outs);
       const Clock::time_point t1 = Clock::now();
       lk.lock();
       st.busy_ms += ms_between(t0, t1);
@@ -170,6 +179,7 @@ struct alb_server_s {
         complete(r, status, t1);
       }
       running -= (int)batch.size();
+      --busy_lanes;
       cv_done.notify_all();
     }
   }
@@ -185,6 +195,7 @@ alb_status alb_server_config_init(alb_server_config *cfg) {
   cfg->max_batch = 256;
   cfg->max_wait_us = 0;
   cfg->hbm_budget = (int64_t)8 << 30;
+  cfg->whole_device_when_alone = 1;
   return alb_options_init(&cfg->options);
 }
 
@@ -246,6 +257,7 @@ alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_ser
       st = alb::batch_resident_workgroups(g, algo, wg, &res);
       if (st != ALB_OK) return bail(st);
       s->grid[algo] = std::max(1, res / cfg.lanes);
+      s->grid_all[algo] = res;
     }
     for (int i = 0; i < cfg.lanes; ++i) {
       hipStream_t x = nullptr;

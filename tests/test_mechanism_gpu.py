@@ -128,10 +128,13 @@ def test_two_sources_per_wave_at_default_threshold(alb):
     dg = alb.Graph(g.off, g.col)
     fr = np.array([i * 37 for i in range(60)], np.int32)
     r = check_round(alb, g, dg, fr, threshold=64)
-    src, pos, thr = oracle.lb_edges(r["work"], r["prefix"], g.off, r["stats"]["launched_threads"])
-    waves = thr // 64
-    for w in np.unique(waves):
-        assert len(np.unique(src[waves == w])) <= 2
+    T = r["stats"]["launched_threads"]
+    src, pos, thr = oracle.lb_edges(r["work"], r["prefix"], g.off, T)
+    # one sweep of one wavefront: its 64 lanes in the same pass over the grid
+    k = np.arange(len(src))
+    sweep = (thr // 64) * (len(src) // T + 1) + k // T
+    for w in np.unique(sweep):
+        assert len(np.unique(src[sweep == w])) <= 2
     dg.close()
 
 
