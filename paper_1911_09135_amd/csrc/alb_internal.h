@@ -19,15 +19,17 @@ constexpr int kEdgesPerLanePass = 4;
 constexpr double kFixScale = 1152921504606846976.0;     // 2^60
 constexpr double kFixInv = 1.0 / 1152921504606846976.0;  // 2^-60
 
-// Grid barrier: workgroups arrive on one of several group counters (kBarGroup
-// workgroups each); the last of a group arrives on the root counter; the last
-// root arrival bumps the generation word that every workgroup polls.  Each
-// word sits on its own 256-byte line of the barrier buffer.
-constexpr int kBarGroup = 32;
-constexpr int kBarMaxGroups = 1024;
+// Grid barrier: each XCD (one L2) has an arrival counter, an open flag and
+// the count of members it holds; the last arrival of an XCD arrives on the
+// root counter, and the last root arrival bumps the generation word.  Each
+// word sits on its own 256-byte line of the barrier buffer.  XCC_ID has 4
+// bits, so up to 16 XCDs are provided for.
+constexpr int kBarXcds = 16;
 constexpr int kBarStride = 32;  // uint64 words per line
-constexpr int kBarRoot = 0, kBarGen = kBarStride, kBarGroups = 2 * kBarStride;
-constexpr size_t kBarWords = (size_t)kBarGroups + (size_t)kBarStride * kBarMaxGroups;
+constexpr int kBarRoot = 0, kBarGen = kBarStride, kBarXcdArrive = 2 * kBarStride;
+constexpr int kBarXcdFlag = kBarXcdArrive + kBarXcds * kBarStride;
+constexpr int kBarXcdMembers = kBarXcdFlag + kBarXcds * kBarStride;
+constexpr size_t kBarWords = (size_t)kBarXcdMembers + (size_t)kBarXcds * kBarStride;
 
 // Huge-worklist chunk index: edge index k of the round's huge edges lies in
 // chunk k >> hint_shift; hint[c] holds the huge-list slot that owns the first

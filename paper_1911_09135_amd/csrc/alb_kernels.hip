@@ -296,6 +296,7 @@ struct Smem {
   V osv;
   int32_t flag;
   uint32_t ticket, members;  // persistent launch: this workgroup's ticket and the member count
+  uint32_t xcd, xcd_n, n_xcd;  // its XCD, the members on that XCD, the XCDs holding members
   unsigned long long cbase;  // phase 1: first worklist entry of the current claim
   uint32_t clen;             // and its length
   Entry<M> pbuf[B / kWave][kPushBuf];  // per-wavefront push staging
@@ -307,6 +308,7 @@ struct Smem {
 struct Grid {
   uint32_t id;
   uint32_t n;
+  uint32_t xcd = 0, xcd_n = 1, n_xcd = 1;  // persistent launch: barrier topology (see grid_barrier)
 };
 
 // Next-worklist pushes of one wavefront, staged in LDS and written out in
@@ -843,51 +845,70 @@ __device__ void phase_pr_update(const Args &a, Grid gr, unsigned long long dangl
   }
 }
 
-// Grid-wide barrier among the members of the persistent launch.  After the
-// workgroup barrier, thread 0 alone releases the workgroup's writes at agent
-// scope (L2 write-back across the 8 XCDs) and arrives on its group counter;
-// the last of a group arrives on the root counter, and the last root arrival
-// publishes the next generation.  Thread 0 polls the generation with relaxed
-// loads and s_sleep, then acquires (L1/L2 invalidate) before the workgroup
-// barrier lets the other waves on.  The counters only grow, so nothing is
-// reset between barriers.  A wait longer than timeout_ticks sets ctl->abort,
-// which makes every workgroup leave at its next barrier.
+// The XCD (accelerator complex die, one L2) the calling wave runs on: the
+// XCC_ID hardware register, bits [3:0].
+__device__ __forceinline__ uint32_t xcd_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (uint32_t)(kBarXcds - 1);
+}
+
+// Wait until every memory operation this wave issued has completed; also a
+// compiler barrier, so no load or store moves across it.
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
+
+// Bounded wait of thread 0 until *w reaches target.  Returns false if the
+// launch was aborted or this wait outlasted timeout_ticks (which then
+// aborts it: every workgroup leaves at its next barrier).
+__device__ __forceinline__ bool bar_wait(const Args &a, unsigned long long *w, unsigned long long target, int round) {
+  Ctl *c = a.ctl;
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  unsigned long long seen;
+  while ((seen = ld_relaxed(w)) < target) {
+    if (ld_relaxed(&c->abort)) return false;
+    if ((uint64_t)wall_clock64() - t0 > a.timeout_ticks) {
+      st_relaxed(&c->diag_seen, seen);
+      st_relaxed(&c->diag_target, target);
+      st_relaxed(&c->diag_round, (uint32_t)round);
+      st_relaxed(&c->abort, 1u);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// Grid-wide barrier among the members of the persistent launch, with one
+// agent-scope release (L2 write-back) per XCD instead of one per workgroup:
+// the write-back covers the whole L2 of the XCD it runs on, whichever CU
+// wrote the lines, and a hundred of them in a row per L2 made the barrier
+// cost grow with the grid.  Every wave first waits until its own memory
+// operations have completed, so after the workgroup barrier all of the
+// workgroup's stores are in its XCD's L2 (the vector L1 writes through).
+// Thread 0 then arrives on its XCD's counter.  The XCD's last arrival does
+// the release, arrives on the root counter, waits for the generation and
+// opens the XCD's flag; the others wait for the flag.  Every workgroup then
+// acquires at agent scope itself (one acquire per XCD followed by an L1-only
+// invalidate elsewhere was tried and gave stale reads).  Counters only grow,
+// so nothing is reset between barriers.
 template <class S>
 __device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round) {
+  wait_memory();
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long *b = a.bar;
-    Ctl *c = a.ctl;
-    const uint32_t grp = gr.id / kBarGroup;
-    const uint32_t ngrp = (gr.n + kBarGroup - 1) / kBarGroup;
-    const uint32_t gsz = min((uint32_t)kBarGroup, gr.n - grp * kBarGroup);
     const unsigned long long target = epoch + 1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned long long o1 = add_relaxed(&b[kBarGroups + (size_t)kBarStride * grp], 1ull);
-    if ((o1 + 1) % gsz == 0) {
+    const unsigned long long o1 = add_relaxed(&b[kBarXcdArrive + (size_t)kBarStride * gr.xcd], 1ull);
+    bool ok;
+    if ((o1 + 1) % gr.xcd_n == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned long long o2 = add_relaxed(&b[kBarRoot], 1ull);
-      if ((o2 + 1) % ngrp == 0) st_relaxed(&b[kBarGen], target);
-    }
-    int ok = 1;
-    const uint64_t t0 = (uint64_t)wall_clock64();
-    unsigned long long seen;
-    while ((seen = ld_relaxed(&b[kBarGen])) < target) {
-      if (ld_relaxed(&c->abort)) {
-        ok = 0;
-        break;
-      }
-      if ((uint64_t)wall_clock64() - t0 > a.timeout_ticks) {
-        st_relaxed(&c->diag_seen, seen);
-        st_relaxed(&c->diag_target, target);
-        st_relaxed(&c->diag_round, (uint32_t)round);
-        st_relaxed(&c->abort, 1u);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
+      if ((o2 + 1) % gr.n_xcd == 0) st_relaxed(&b[kBarGen], target);
+      ok = bar_wait(a, &b[kBarGen], target, round);
+      if (ok) st_relaxed(&b[kBarXcdFlag + (size_t)kBarStride * gr.xcd], target);
+    } else {
+      ok = bar_wait(a, &b[kBarXcdFlag + (size_t)kBarStride * gr.xcd], target, round);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    sm.flag = ok;
+    sm.flag = ok ? 1 : 0;
   }
   __syncthreads();
   ++epoch;
@@ -932,8 +953,9 @@ __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
 // no new one has joined for join_window_ticks, and publishes the member
 // count.  A workgroup whose ticket shows the closed bit is not a member and
 // leaves at once.  Members are running when they join and never leave before
-// the end, so every barrier among them completes.  Returns false for a
-// non-member; *gr gets (ticket, member count).
+// the end, so every barrier among them completes.  Each member also counts
+// itself on its XCD, for the barrier.  Returns false for a non-member; *gr
+// gets (ticket, member count, XCD, members on that XCD, XCDs in use).
 template <class S>
 __device__ bool join_members(const Args &a, S &sm, Grid *gr) {
   constexpr unsigned long long kClosed = 1ull << 63;
@@ -941,6 +963,8 @@ __device__ bool join_members(const Args &a, S &sm, Grid *gr) {
     Ctl *c = a.ctl;
     const unsigned long long t = add_relaxed(&c->members, 1ull);
     uint32_t member = (t & kClosed) ? 0u : 1u;
+    const uint32_t x = xcd_id();
+    if (member) add_relaxed(&a.bar[kBarXcdMembers + (size_t)kBarStride * x], 1ull);
     if (member && t == 0) {
       unsigned long long seen = 1;
       uint64_t t_last = (uint64_t)wall_clock64();
@@ -960,20 +984,50 @@ __device__ bool join_members(const Args &a, S &sm, Grid *gr) {
           __hip_atomic_fetch_or(&c->members, kClosed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       st_relaxed(&c->n_members, (uint32_t)prev);
     }
-    uint32_t n = 0;
+    uint32_t n = 0, xn = 1, nx = 1;
     if (member) {
       while ((n = ld_relaxed(&c->n_members)) == 0) __builtin_amdgcn_s_sleep(1);
       if ((uint32_t)t >= n) member = 0;  // cannot happen: tickets below the closing count are members
+      // every member registers its XCD right after its ticket: wait until all
+      // n have, then the per-XCD counts are final (a bounded wait; past the
+      // barrier time-out the launch is aborted)
+      const uint64_t t0 = (uint64_t)wall_clock64();
+      for (;;) {
+        unsigned long long tot = 0;
+        nx = 0;
+        for (int k = 0; k < kBarXcds; ++k) {
+          const unsigned long long v = ld_relaxed(&a.bar[kBarXcdMembers + (size_t)kBarStride * k]);
+          tot += v;
+          nx += v ? 1u : 0u;
+        }
+        if (tot >= n) break;
+        if ((uint64_t)wall_clock64() - t0 > a.timeout_ticks) {
+          st_relaxed(&c->abort, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      xn = (uint32_t)ld_relaxed(&a.bar[kBarXcdMembers + (size_t)kBarStride * x]);
+      if (xn == 0 || nx == 0) {  // only after an abort: keep the barrier arithmetic defined
+        xn = 1;
+        nx = 1;
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     sm.flag = (int32_t)member;
     sm.ticket = (uint32_t)t;
     sm.members = n;
+    sm.xcd = x;
+    sm.xcd_n = xn;
+    sm.n_xcd = nx;
   }
   __syncthreads();
   const bool member = sm.flag != 0;
   gr->id = sm.ticket;
   gr->n = sm.members;
+  gr->xcd = sm.xcd;
+  gr->xcd_n = sm.xcd_n;
+  gr->n_xcd = sm.n_xcd;
   __syncthreads();
   return member;
 }
