@@ -70,7 +70,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--threshold", type=int, default=None,
-                    help="huge-degree threshold for the ALB run (default: the library's, min(16 x workgroup size, 4096))")
+                    help="huge-degree threshold for the ALB run (default: the library's, m / (20 x workgroups) "
+                         "within [64, 4096])")
     ap.add_argument("--launch", default="auto")
     ap.add_argument("--no-sweep", action="store_true", help="skip the threshold sweep over powers of two")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -67,7 +67,10 @@ typedef enum { ALB_MODE_ALB = 0, ALB_MODE_TWC_ONLY = 1, ALB_MODE_LB_ALL = 2 } al
  * no co-residency is assumed.  AUTO picks PERSISTENT. */
 typedef enum { ALB_LAUNCH_AUTO = 0, ALB_LAUNCH_HOST_LOOP = 1, ALB_LAUNCH_PERSISTENT = 2 } alb_launch;
 
-/* Special values of alb_options.huge_threshold.  ADAPTIVE uses 64 (a
+/* Special values of alb_options.huge_threshold.  DEFAULT is
+ * m / (20 * workgroups) kept within [64, 4096] (m: the graph's edges, or all
+ * edges of a batch's queries; workgroups: the launch's grid), and for BFS and
+ * k-core also the small-round rule of ADAPTIVE.  ADAPTIVE uses 64 (a
  * wavefront's worth of edges) in rounds whose worklist has fewer entries than
  * launched threads, where the TWC phase cannot occupy every workgroup, and the
  * DEFAULT value otherwise. */
@@ -87,9 +90,9 @@ typedef struct {
   uint32_t struct_size;      /* sizeof(alb_options); set by alb_options_init */
   int32_t mode;              /* alb_mode */
   int64_t huge_threshold;    /* ALB mode: degree >= this is huge; ALB_THRESHOLD_DEFAULT (-1) =
-                                min(16 * wg_size, 4096) (four passes of one workgroup over a vertex's edges,
-                                at most 4,096), ALB_THRESHOLD_LAUNCHED (-2) = the launched thread count (the
-                                paper's rule, Section 5) */
+                                m / (20 * workgroups) within [64, 4096] (see above), ALB_THRESHOLD_LAUNCHED
+                                (-2) = the launched thread count (the paper's rule, Section 5),
+                                ALB_THRESHOLD_ADAPTIVE (-3) */
   int32_t wg_size;           /* 0 = 256; one of 64, 256, 1024 */
   int32_t wave_cutoff;       /* TWC wavefront bin: degree >= this (0 = 64) */
   int32_t wg_cutoff;         /* TWC workgroup bin: degree >= this (0 = wg_size) */

@@ -428,11 +428,25 @@ alb_status resolve_options(const alb_options *user, alb_options &o) {
 // The round driver shared by every traversal
 // --------------------------------------------------------------------------
 
-// The default huge threshold: a vertex that would keep one workgroup busy for
-// more than four passes of its edge loop (4 edges per lane each) is huge, up
-// to 4,096 edges -- the best of the measured threshold sweeps on RMAT and
-// Zipf inputs at 256 and 1,024 threads per workgroup.
-int64_t default_threshold(int wg) { return std::min<int64_t>((int64_t)4 * kEdgesPerLanePass * wg, 4096); }
+// The default huge threshold: a vertex is huge when its list is longer than
+// a twentieth of one workgroup's share of all edges (m / workgroups), kept
+// within [64, 4,096].  A list that long would hold one workgroup well past
+// the others in any round that carries a fair part of the graph.  Measured
+// against sweeps of t = 32 ... 4,096 on RMAT scales 12 to 22 at the automatic
+// grid: within 10 % of the best fixed threshold for SSSP at every scale but
+// 16 (scale 22: 4,052, best 2,048-4,096; scale 14: 94, best 64).
+int64_t default_threshold(int64_t edges, int grid) {
+  const int64_t t = edges / (20 * (int64_t)std::max(grid, 1));
+  return std::max<int64_t>(64, std::min<int64_t>(t, 4096));
+}
+
+// Operators whose pushed value does not depend on the source vertex (BFS
+// levels, k-core decrements) take the small-round rule by default as well:
+// kAdaptiveSmall in rounds whose worklist is shorter than the launched
+// threads.  Their cyclic phase needs no per-edge source value, so spreading
+// even short lists over the grid pays in small rounds (RMAT-14 BFS device
+// time 103 vs 170 us, RMAT-22 1.02 vs 1.12 ms against t = 4,096 throughout).
+bool default_small_rounds(OpKind op) { return op == OP_BFS || op == OP_KCORE; }
 
 }  // namespace
 
@@ -612,8 +626,10 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   else if (o.huge_threshold == ALB_THRESHOLD_LAUNCHED)
     threshold = launch == ALB_LAUNCH_PERSISTENT ? -1 : T;  // the launched thread count (known on the device)
   else
-    threshold = default_threshold(wg);
-  const bool adaptive = o.mode == ALB_MODE_ALB && o.huge_threshold == ALB_THRESHOLD_ADAPTIVE;
+    threshold = default_threshold(g->m, grid);
+  const bool adaptive = o.mode == ALB_MODE_ALB &&
+                        (o.huge_threshold == ALB_THRESHOLD_ADAPTIVE ||
+                         (o.huge_threshold == ALB_THRESHOLD_DEFAULT && default_small_rounds(job.op)));
 
   bool dedup = false;
   if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);
@@ -896,7 +912,7 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
   else if (o.huge_threshold == ALB_THRESHOLD_LAUNCHED)
     j.threshold = -1;
   else
-    j.threshold = default_threshold(wg);
+    j.threshold = default_threshold(edges, j.grid);
 
   Args &a = j.a;
   std::memset(&a, 0, sizeof a);
@@ -909,7 +925,11 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
   a.c_wave = o.wave_cutoff;
   a.c_wg = o.wg_cutoff;
   a.dedup = dedup ? 1 : 0;
-  a.adaptive = (!thresholds && o.mode == ALB_MODE_ALB && o.huge_threshold == ALB_THRESHOLD_ADAPTIVE) ? 1 : 0;
+  a.adaptive = (!thresholds && o.mode == ALB_MODE_ALB &&
+                (o.huge_threshold == ALB_THRESHOLD_ADAPTIVE ||
+                 (o.huge_threshold == ALB_THRESHOLD_DEFAULT && default_small_rounds(op))))
+                   ? 1
+                   : 0;
   a.blocked = o.distribution == 1;
   a.max_rounds = max_n + 1;
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
