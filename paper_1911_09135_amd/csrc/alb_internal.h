@@ -10,7 +10,10 @@ namespace alb {
 constexpr int32_t kInf = 0x7fffffff;
 // Edges each lane keeps in flight; one pass of a B-thread workgroup over a
 // vertex's edge list covers kEdgesPerLanePass * B edges.
-constexpr int kEdgesPerLanePass = 4;
+#ifndef ALB_EDGES_PER_LANE
+#define ALB_EDGES_PER_LANE 4
+#endif
+constexpr int kEdgesPerLanePass = ALB_EDGES_PER_LANE;
 // PageRank sums: an fp32 contribution c is added as round(c * 2^60) to a
 // 64-bit integer.  Integer addition is exact and associative, so the sum of a
 // vertex's in-contributions does not depend on the order of the atomics, and
