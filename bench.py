@@ -219,12 +219,19 @@ def main():
         ex = int(np.mean([s["edges_examined"] for s in stats]))
         probe = gather_rate(g.n, ex)
         kernel_rate = ex / (float(np.mean(kms)) * 1e-3)
+        # the same gathers at the graph's own destinations (every edge once,
+        # in CSR order): the label reads alone, without atomics or balancing
+        replay = gather_rate(g.n, 0, idx=torch.from_numpy(g.col.astype(np.int64)).cuda())
         random_access = {"probe": "torch index_select of int64 words at uniform random indices, table = label "
                                   "array (%d words), %d indices" % (g.n, ex),
                          "probe_reads_per_s_g": round(probe / 1e9, 2),
                          "kernel_edges_per_s_g": round(kernel_rate / 1e9, 2),
-                         "frac": round(kernel_rate / probe, 3)}
-        log("uniform random gathers: %.1f G reads/s; kernel %.1f G edges/s" % (probe / 1e9, kernel_rate / 1e9))
+                         "frac": round(kernel_rate / probe, 3),
+                         "csr_order_gather": "the same table gathered at every edge's destination in CSR order",
+                         "csr_order_reads_per_s_g": round(replay / 1e9, 2),
+                         "frac_of_csr_order": round(kernel_rate / replay, 3)}
+        log("uniform random gathers: %.1f G reads/s; destinations in CSR order %.1f G reads/s; kernel %.1f G "
+            "edges/s" % (probe / 1e9, replay / 1e9, kernel_rate / 1e9))
 
     cpu = None
     if not args.no_cpu:
@@ -287,13 +294,16 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def gather_rate(words: int, n_idx: int, reps: int = 5) -> float:
-    """Random 8-byte reads per second that torch's gather sustains from a
-    table of `words` int64 words (uniform random indices, event-timed)."""
+def gather_rate(words: int, n_idx: int, reps: int = 5, idx=None) -> float:
+    """8-byte reads per second that torch's gather sustains from a table of
+    `words` int64 words, at uniform random indices or at the given ones
+    (event-timed)."""
     import torch
 
     table = torch.arange(words, dtype=torch.int64, device="cuda")
-    idx = torch.randint(0, words, (n_idx,), dtype=torch.int64, device="cuda")
+    if idx is None:
+        idx = torch.randint(0, words, (n_idx,), dtype=torch.int64, device="cuda")
+    n_idx = int(idx.numel())
     out = torch.empty(n_idx, dtype=torch.int64, device="cuda")
     for _ in range(2):
         torch.index_select(table, 0, idx, out=out)

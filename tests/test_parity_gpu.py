@@ -326,3 +326,19 @@ def test_worklist_overflow_reported(alb):
     # the same graph still works afterwards
     lv, _ = alb.bfs(dg, 0)
     assert np.array_equal(lv, oracle.bfs(graph("rmat14"), 0))
+
+
+@pytest.mark.parametrize("name", ["rmat14", "zipf16", "hubs", "rand5000"])
+def test_default_threshold_follows_the_graph(alb, name):
+    """The default huge threshold is m / (20 x workgroups) within [64, 4096],
+    and the results under it (with the small-round rule for BFS) are the
+    oracle's."""
+    g = graph(name)
+    dg = device_graph(alb, name)
+    d, st = alb.sssp(dg, 0)
+    grid = st["launched_threads"] // 256
+    assert st["huge_threshold"] == max(64, min(g.m // (20 * grid), 4096))
+    assert np.array_equal(d, oracle.sssp(g, 0))
+    lv, st = alb.bfs(dg, 0)
+    assert st["huge_threshold"] == max(64, min(g.m // (20 * grid), 4096))
+    assert np.array_equal(lv, oracle.bfs(g, 0))
