@@ -464,10 +464,10 @@ def bench_batch(args, alb, gg):
 
 def bench_zipf24(args, alb, gg):
     """The extreme-skew graph: Zipf(1.9) out-degrees capped at 4,194,304,
-    n = 2^24 (~372M edges).  BFS from the highest-degree vertex, CC on the
-    symmetrised graph, PageRank (0.85, 50 iterations), each with the default
-    balancer and TWC only; plus a 2048 x 2048 undirected grid (low skew, high
-    diameter) where the balancer should cost nothing.  Times are the
+    n = 2^24 (~372M edges).  BFS from the highest-degree vertex, CC and k-core
+    (k = 8, 32) on the symmetrised graph, PageRank (0.85, 50 iterations), each
+    with the default balancer and TWC only; plus a 2048 x 2048 undirected grid
+    (low skew, high diameter) where the balancer should cost nothing.  Times are the
     traversal kernels' device time (median of the steps)."""
     import numpy as np
     import torch
@@ -536,6 +536,17 @@ def bench_zipf24(args, alb, gg):
                                            "achieved_gbs": round(b / ms / 1e6, 1),
                                            "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4), "rounds": st["rounds"]}
         log("cc %s: %.3f ms" % (label, ms))
+    # k-core (the paper's kcore) on the same symmetrised graph: peeling from
+    # every vertex with fewer than k neighbours
+    for k in (8, 32):
+        for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+            ms, st = timed(lambda d, kk, out=None, **o: alb.kcore(d, kk, out=out, **o), ds, out, opts, k)
+            b = alb.algorithmic_bytes("kcore", st)
+            res.setdefault("kcore_k%d" % k, {})[label] = {
+                "kernel_ms": round(ms, 3), "edges_per_s_g": round(st["edges_examined"] / ms / 1e6, 3),
+                "achieved_gbs": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+                "rounds": st["rounds"], "core_vertices": int(out.sum().item())}
+            log("kcore k=%d %s: %.3f ms" % (k, label, ms))
     ds.close()
     del g
     gr = gg.grid(2048, 2048).with_weights(5)
@@ -562,7 +573,8 @@ def bench_zipf24(args, alb, gg):
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "zipf1.9_n2^24_cap4194304: bfs, cc, pagerank; grid2048 bfs, sssp", "source": src},
+        "config": {"workload": "zipf1.9_n2^24_cap4194304: bfs, cc, kcore, pagerank; grid2048 bfs, sssp",
+                   "source": src},
         "roofline": {"bound": "hbm", "achieved": bfs["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bfs["frac"], "traffic": None},
         "results": res,

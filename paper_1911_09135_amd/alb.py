@@ -630,12 +630,12 @@ def trace_round(g: Graph, frontier, off=None, **opts) -> dict:
 
 def algorithmic_bytes(kind: str, stats: dict, n: int = 0, iterations: int = 0) -> int:
     """Bytes a push round must move whatever the schedule:
-      bfs, cc:  16 B per active vertex (worklist entry, two offsets, label)
+      bfs, cc, kcore: 16 B per active vertex (worklist entry, two offsets, label)
                  + 8 B per examined edge (column, destination label) + 4 B per push
       sssp:     16 B per active vertex + 12 B per examined edge (adds the weight) + 4 B per push
       pagerank: per iteration 8 B per edge (column, accumulator update) and 24 B per vertex
                 (rank, offsets, accumulator read and clear, rank write)."""
-    if kind in ("bfs", "cc"):
+    if kind in ("bfs", "cc", "kcore"):
         return 16 * stats["frontier_vertices"] + 8 * stats["edges_examined"] + 4 * stats["pushes"]
     if kind == "sssp":
         return 16 * stats["frontier_vertices"] + 12 * stats["edges_examined"] + 4 * stats["pushes"]
