@@ -69,10 +69,11 @@ typedef enum { ALB_LAUNCH_AUTO = 0, ALB_LAUNCH_HOST_LOOP = 1, ALB_LAUNCH_PERSIST
 
 /* Special values of alb_options.huge_threshold.  DEFAULT is
  * m / (20 * workgroups) kept within [64, 4096] (m: the graph's edges, or all
- * edges of a batch's queries; workgroups: the launch's grid), and for BFS and
- * k-core also the small-round rule of ADAPTIVE.  ADAPTIVE uses 64 (a
- * wavefront's worth of edges) in rounds whose worklist has fewer entries than
- * launched threads, where the TWC phase cannot occupy every workgroup, and the
+ * edges of a batch's queries; workgroups: the launch's grid); in rounds whose
+ * worklist has fewer entries than launched threads, where the TWC phase cannot
+ * occupy every workgroup, it is 64 for BFS and k-core and a quarter of that
+ * value (at least 64) for the other operators.  ADAPTIVE uses 64 (a
+ * wavefront's worth of edges) in those rounds for every operator, and the
  * DEFAULT value otherwise. */
 enum { ALB_THRESHOLD_DEFAULT = -1, ALB_THRESHOLD_LAUNCHED = -2, ALB_THRESHOLD_ADAPTIVE = -3 };
 
@@ -373,7 +374,9 @@ alb_status alb_pagerank_pull(alb_graph g, float damping, int32_t iterations, flo
  *   next[...], *nnext  the pushed destinations (every processed edge pushes its
  *                  destination; capacity = sum of the frontier's degrees).
  * `next` may be NULL to skip the copy.  Uses opt->mode, huge_threshold,
- * wg_size, cutoffs, launch and grid_wgs like the traversals do. */
+ * wg_size, cutoffs, launch and grid_wgs like the traversals do, except that
+ * ALB_THRESHOLD_DEFAULT applies its base value to the recorded round whatever
+ * the frontier's size (stats->huge_threshold is the value applied). */
 alb_status alb_trace_round(alb_graph g, const int32_t *frontier, int64_t nf, const alb_options *opt,
                            int8_t *bins, int32_t *work, int64_t *nwork, int64_t *prefix, int32_t *edge_hits,
                            int32_t *edge_thread, int32_t *next, int64_t *nnext, alb_stats *stats);

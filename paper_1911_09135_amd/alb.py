@@ -25,8 +25,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 ALB_E_TIMEOUT, ALB_E_CANCELLED = -7, -8
 ALB_SYMMETRIC, ALB_BUILD_SYMMETRIC, ALB_BUILD_TRANSPOSE = 1, 2, 4
-# m / (20 * workgroups) within [64, 4096] (BFS, k-core: also 64 in rounds smaller than the grid); the launched
-# thread count (the paper's rule); 64 in rounds smaller than the grid, else default
+# m / (20 * workgroups) within [64, 4096], lower in rounds smaller than the grid (BFS, k-core: 64; others: a
+# quarter, at least 64); the launched thread count (the paper's rule); 64 in rounds smaller than the grid, else
+# default
 THRESHOLD_DEFAULT, THRESHOLD_LAUNCHED, THRESHOLD_ADAPTIVE = -1, -2, -3
 GRID_ALL = -1  # grid_wgs: every resident workgroup (0 = automatic)
 MODES = {"alb": 0, "twc": 1, "twc_only": 1, "lb_all": 2}

@@ -440,13 +440,20 @@ int64_t default_threshold(int64_t edges, int grid) {
   return std::max<int64_t>(64, std::min<int64_t>(t, 4096));
 }
 
-// Operators whose pushed value does not depend on the source vertex (BFS
-// levels, k-core decrements) take the small-round rule by default as well:
-// kAdaptiveSmall in rounds whose worklist is shorter than the launched
-// threads.  Their cyclic phase needs no per-edge source value, so spreading
-// even short lists over the grid pays in small rounds (RMAT-14 BFS device
-// time 103 vs 170 us, RMAT-22 1.02 vs 1.12 ms against t = 4,096 throughout).
-bool default_small_rounds(OpKind op) { return op == OP_BFS || op == OP_KCORE; }
+// The default also lowers the threshold in rounds whose worklist is shorter
+// than the launched threads, where a few long lists would hold their
+// workgroups while the rest of the grid idles: to 64 (kAdaptiveSmall) for
+// operators whose pushed value does not depend on the source vertex (BFS
+// levels, k-core decrements: their cyclic phase needs no per-edge source
+// value), and to a quarter of the default, at least 64, for the others.
+// Measured at the automatic grid (device us per query, default without ->
+// with the small-round rule): RMAT-14 BFS 170 -> 103, SSSP 262 -> 251;
+// RMAT-16 SSSP 428 -> 362; RMAT-20 SSSP 1,150 -> 1,112; RMAT-22 BFS 1,121
+// -> 1,017, SSSP 2,318 -> 2,269.
+int64_t default_small_threshold(OpKind op, int64_t threshold) {
+  if (op == OP_BFS || op == OP_KCORE) return kAdaptiveSmall;
+  return std::max<int64_t>(kAdaptiveSmall, threshold / 4);
+}
 
 }  // namespace
 
@@ -627,9 +634,13 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     threshold = launch == ALB_LAUNCH_PERSISTENT ? -1 : T;  // the launched thread count (known on the device)
   else
     threshold = default_threshold(g->m, grid);
+  // (the recorded single round of alb_trace_round keeps the base value)
   const bool adaptive = o.mode == ALB_MODE_ALB &&
                         (o.huge_threshold == ALB_THRESHOLD_ADAPTIVE ||
-                         (o.huge_threshold == ALB_THRESHOLD_DEFAULT && default_small_rounds(job.op)));
+                         (o.huge_threshold == ALB_THRESHOLD_DEFAULT && job.op != OP_RECORD));
+  const int64_t small_threshold = o.huge_threshold == ALB_THRESHOLD_ADAPTIVE
+                                      ? (int64_t)kAdaptiveSmall
+                                      : default_small_threshold(job.op, threshold);
 
   bool dedup = false;
   if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);
@@ -672,6 +683,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.c_wg = o.wg_cutoff;
   a.dedup = dedup ? 1 : 0;
   a.adaptive = adaptive ? 1 : 0;
+  a.small_threshold = small_threshold;
   a.blocked = o.distribution == 1;
   a.identity_first = job.identity_first;
   a.all_rounds = job.all_rounds;
@@ -926,10 +938,11 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
   a.c_wg = o.wg_cutoff;
   a.dedup = dedup ? 1 : 0;
   a.adaptive = (!thresholds && o.mode == ALB_MODE_ALB &&
-                (o.huge_threshold == ALB_THRESHOLD_ADAPTIVE ||
-                 (o.huge_threshold == ALB_THRESHOLD_DEFAULT && default_small_rounds(op))))
+                (o.huge_threshold == ALB_THRESHOLD_ADAPTIVE || o.huge_threshold == ALB_THRESHOLD_DEFAULT))
                    ? 1
                    : 0;
+  a.small_threshold = o.huge_threshold == ALB_THRESHOLD_ADAPTIVE ? (int64_t)kAdaptiveSmall
+                                                                 : default_small_threshold(op, j.threshold);
   a.blocked = o.distribution == 1;
   a.max_rounds = max_n + 1;
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();

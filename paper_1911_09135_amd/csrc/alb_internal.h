@@ -39,9 +39,10 @@ constexpr size_t kBarWords = (size_t)kBarXcdMembers + (size_t)kBarXcds * kBarStr
 // edge of chunk c and the end of that slot's edge range.  The shift is at
 // least kHintMinShift.
 constexpr int kHintMinShift = 10;
-// Adaptive threshold for rounds whose worklist cannot give every launched
-// thread an entry: any vertex of at least a wavefront's worth of edges goes to
-// the cyclic distribution, which keeps every workgroup busy.
+// Threshold of the explicit adaptive rule for rounds whose worklist cannot
+// give every launched thread an entry: any vertex of at least a wavefront's
+// worth of edges goes to the cyclic distribution, which keeps every
+// workgroup busy.
 constexpr int kAdaptiveSmall = 64;
 constexpr int kHintMaxShift = 20;
 // Queries in one batch launch (the output kernel puts one query on each grid row).
@@ -104,7 +105,8 @@ struct Args {
   int32_t c_wave;       // TWC cutoffs
   int32_t c_wg;
   int32_t dedup;        // SSSP / CC: push a vertex at most once per round
-  int32_t adaptive;     // per-round threshold: kAdaptiveSmall when the worklist has fewer entries than threads
+  int32_t adaptive;     // per-round threshold: small_threshold when the worklist has fewer entries than threads
+  int64_t small_threshold;
   int32_t blocked;      // huge edges in contiguous runs per thread instead of cyclically
   int32_t identity_first;  // round 0 works on every vertex (no worklist)
   int32_t all_rounds;      // every round works on every vertex (PageRank)

@@ -931,10 +931,11 @@ __device__ __forceinline__ uint32_t round_size(const Args &a, int r) {
   return c < a.qcap ? c : a.qcap;
 }
 
-// The huge threshold of a round: the configured one, or with the adaptive rule
-// kAdaptiveSmall while the worklist has fewer entries than launched threads.
+// The huge threshold of a round: the configured one, or with the small-round
+// rule small_threshold while the worklist has fewer entries than launched
+// threads.
 __device__ __forceinline__ int64_t round_threshold(const Args &a, uint32_t nF, uint64_t T) {
-  if (a.adaptive && (uint64_t)nF < T) return kAdaptiveSmall;
+  if (a.adaptive && (uint64_t)nF < T) return a.small_threshold;
   return a.threshold;
 }
 
