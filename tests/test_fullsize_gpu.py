@@ -6,6 +6,8 @@
   edges): BFS levels equal to the queue BFS, CC labels equal to union-find,
   PageRank (50 iterations, push and pull) within L1 1e-5 of the fp64 oracle.
   k-core membership on the Zipf graph with 2^20 vertices equal to peeling.
+  BFS and SSSP on the 2048 x 2048 grid (thousands of rounds, two grid
+  barriers each): equal to the oracle's.
 """
 import os
 import time
@@ -168,3 +170,19 @@ def test_sssp_batch_rmat_set_full(alb):
             assert np.array_equal(d, outs[q].cpu().numpy()), ("query", int(q))
         dg.close()
     gs.close()
+
+
+def test_grid2048_bfs_sssp_full(alb):
+    """The low-skew, high-diameter workload of bench.py --workload zipf24:
+    BFS takes 4,095 rounds and SSSP ~4,300, so every barrier's visibility
+    guarantee is exercised thousands of times in one launch."""
+    g = gg.grid(2048, 2048).with_weights(5)
+    dg = alb.Graph(g.off, g.col, g.w)
+    for kind, fn, ref in (("bfs", alb.bfs, oracle.bfs), ("sssp", alb.sssp, oracle.sssp)):
+        want = ref(g, 0)
+        for c in [dict(), dict(mode="twc")]:
+            log("grid2048 %s %s" % (kind, c))
+            got, st = fn(dg, 0, **c)
+            assert st["rounds"] > 4000
+            assert np.array_equal(got, want), (kind, c)
+    dg.close()
