@@ -283,6 +283,11 @@ def main():
         "cpu_baseline": cpu,
         "alb_stats": {k: stats[-1][k] for k in ("frontier_vertices", "edges_examined", "huge_vertices",
                                                   "huge_edges", "pushes")},
+        # the paper's convention (median of the timed queries) and relaxations
+        # (examined edges) per second of kernel time
+        "median_ms_per_query_kernel": round(float(np.median(kms)), 4),
+        "relaxations_per_s_g": round(float(np.mean([s["edges_examined"] for s in stats])) /
+                                     (float(np.mean(kms)) * 1e-3) / 1e9, 2),
     }
     if sweep is not None:
         res["threshold_sweep_gteps"] = sweep
