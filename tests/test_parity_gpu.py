@@ -342,3 +342,30 @@ def test_default_threshold_follows_the_graph(alb, name):
     lv, st = alb.bfs(dg, 0)
     assert st["huge_threshold"] == max(64, min(g.m // (20 * grid), 4096))
     assert np.array_equal(lv, oracle.bfs(g, 0))
+
+
+@pytest.mark.parametrize("threshold", [None, 64, "twc"])
+def test_contended_atomics_fan_in(alb, threshold):
+    """Device-scope atomics under contention: 0 -> k middle vertices -> a few
+    sinks, so that in one round every workgroup's lanes race on the same
+    sink words (SSSP atomic minimum, BFS compare-and-swap, CC on the
+    symmetrised graph); every result must equal the oracle's."""
+    k, sinks = 200_000, 3
+    n = 1 + k + sinks
+    rng = np.random.default_rng(17)
+    mid = np.arange(1, k + 1)
+    src = np.concatenate([np.zeros(k, np.int64), np.repeat(mid, sinks)])
+    dst = np.concatenate([mid, np.tile(np.arange(k + 1, n), k)])
+    w = rng.integers(1, 10_000, size=src.size)  # max(w) * (n - 1) stays below 2^31
+    g = gg.from_edges(n, src, dst, w)
+    opts = {"mode": "twc"} if threshold == "twc" else {"threshold": threshold}
+    dg = alb.Graph(g.off, g.col, g.w)
+    d, _ = alb.sssp(dg, 0, **opts)
+    assert np.array_equal(d, oracle.sssp(g, 0))
+    lv, _ = alb.bfs(dg, 0, **opts)
+    assert np.array_equal(lv, oracle.bfs(g, 0))
+    dg.close()
+    ds = alb.Graph(g.off, g.col, None, build_symmetric=True)
+    lab, _ = alb.cc(ds, **opts)
+    assert np.array_equal(lab, oracle.cc(g))
+    ds.close()
