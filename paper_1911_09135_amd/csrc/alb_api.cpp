@@ -85,26 +85,33 @@ struct Workspace {
 // Workspace of a batch of queries on a graph set: worklists of
 // (query << 32 | vertex) entries, one label per (query, vertex of its graph)
 // and the per-query tables.
+// Bytes of per-query tables in a batch workspace: three int64 (label offset,
+// threshold, label base), an output pointer and two int32 (source, size).
+constexpr size_t kBatchTableBytes = 3 * sizeof(long long) + sizeof(int32_t *) + 2 * sizeof(int32_t);
+
 struct BatchWs {
   long long lab_cap = 0;
   uint32_t qcap = 0, hint_cap = 0;
   int32_t nq_cap = 0;
   bool busy = false;
   unsigned long long *q0 = nullptr, *q1 = nullptr, *word = nullptr, *bar = nullptr;
-  int32_t *out32 = nullptr, *qsrc = nullptr, *qn = nullptr;
+  int32_t *out32 = nullptr;
   int2 *hint = nullptr;
   int4 *huge_rec = nullptr;
-  long long *qoff = nullptr, *qthr = nullptr, *qlbase = nullptr;
-  int32_t **qout = nullptr;
+  // per-query tables (offsets, thresholds, label bases, output pointers,
+  // sources, sizes), kBatchTableBytes per query, and their pinned host mirror:
+  // one copy uploads a batch's tables
+  unsigned char *tab = nullptr, *h_tab = nullptr;
   Ctl *ctl = nullptr;
   Ctl *h_ctl = nullptr;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   size_t bytes = 0;
 
   void release() {
-    void *p[] = {q0, q1, word, bar, out32, hint, qsrc, qn, huge_rec, qoff, qthr, qlbase, qout, ctl};
+    void *p[] = {q0, q1, word, bar, out32, hint, huge_rec, tab, ctl};
     for (void *x : p) (void)hipFree(x);
     if (h_ctl) (void)hipHostFree(h_ctl);
+    if (h_tab) (void)hipHostFree(h_tab);
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);
     *this = BatchWs();
@@ -338,12 +345,8 @@ alb_status bws_fill(BatchWs *w, const BatchNeeds &nd) {
   HIP_TRY(dalloc(&w->bar, kBarWords, w->bytes));
   HIP_TRY(dalloc(&w->word, (size_t)nd.labels, w->bytes));
   HIP_TRY(dalloc(&w->out32, (size_t)nd.labels, w->bytes));
-  HIP_TRY(dalloc(&w->qsrc, (size_t)nd.nq, w->bytes));
-  HIP_TRY(dalloc(&w->qn, (size_t)nd.nq, w->bytes));
-  HIP_TRY(dalloc(&w->qoff, (size_t)nd.nq, w->bytes));
-  HIP_TRY(dalloc(&w->qthr, (size_t)nd.nq, w->bytes));
-  HIP_TRY(dalloc(&w->qlbase, (size_t)nd.nq, w->bytes));
-  HIP_TRY(dalloc(&w->qout, (size_t)nd.nq, w->bytes));
+  HIP_TRY(dalloc(&w->tab, kBatchTableBytes * (size_t)nd.nq, w->bytes));
+  HIP_TRY(hipHostMalloc((void **)&w->h_tab, kBatchTableBytes * (size_t)std::max(nd.nq, 1), hipHostMallocDefault));
   HIP_TRY(dalloc(&w->ctl, 1, w->bytes));
   HIP_TRY(hipHostMalloc((void **)&w->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   for (auto &e : w->ev) HIP_TRY(hipEventCreate(&e));
@@ -972,24 +975,31 @@ alb_status upload_batch(BatchJob &j, BatchWs *ws) {
   a.ctl = ws->ctl;
   if (j.op == OP_BFS) a.level = (int32_t *)ws->word;
   if (j.op == OP_SSSP) a.word = ws->word;
-  a.qoff = ws->qoff;
-  a.qthr = j.per_query_thr ? ws->qthr : nullptr;
-  a.qlbase = ws->qlbase;
-  a.qsrc = ws->qsrc;
-  a.qn = ws->qn;
-  a.qout = ws->qout;
-  std::vector<int32_t *> dst(j.qout);
-  if (!j.o.out_on_device)
-    for (int32_t q = 0; q < j.count; ++q) dst[q] = ws->out32 + j.qlbase[q];
-  const hipStream_t st = j.stream;
+  // the tables of this batch, packed with stride count: int64 arrays first,
+  // then the output pointers, then the int32 arrays (every part stays
+  // aligned to its element size)
   const size_t c = (size_t)j.count;
-  HIP_TRY(hipMemcpyAsync(ws->qoff, j.qoff.data(), sizeof(long long) * c, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws->qthr, j.qthr.data(), sizeof(long long) * c, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws->qlbase, j.qlbase.data(), sizeof(long long) * c, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws->qsrc, j.qsrc.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws->qn, j.qn.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws->qout, dst.data(), sizeof(int32_t *) * c, hipMemcpyHostToDevice, st));
-  // the copies read pageable host vectors: finish them before those can go
+  long long *d_off = (long long *)ws->tab, *h_off = (long long *)ws->h_tab;
+  int32_t **d_out = (int32_t **)(d_off + 3 * c), **h_out = (int32_t **)(h_off + 3 * c);
+  int32_t *d_i32 = (int32_t *)(d_out + c), *h_i32 = (int32_t *)(h_out + c);
+  for (size_t q = 0; q < c; ++q) {
+    h_off[q] = j.qoff[q];
+    h_off[c + q] = j.qthr[q];
+    h_off[2 * c + q] = j.qlbase[q];
+    h_out[q] = j.o.out_on_device ? j.qout[q] : ws->out32 + j.qlbase[q];
+    h_i32[q] = j.qsrc[q];
+    h_i32[c + q] = j.qn[q];
+  }
+  a.qoff = d_off;
+  a.qthr = j.per_query_thr ? d_off + c : nullptr;
+  a.qlbase = d_off + 2 * c;
+  a.qout = d_out;
+  a.qsrc = d_i32;
+  a.qn = d_i32 + c;
+  const hipStream_t st = j.stream;
+  HIP_TRY(hipMemcpyAsync(ws->tab, ws->h_tab, kBatchTableBytes * c, hipMemcpyHostToDevice, st));
+  // the pinned mirror is rewritten by the next batch on this workspace: the
+  // copy finishes first
   HIP_TRY(hipStreamSynchronize(st));
   return ALB_OK;
 }
