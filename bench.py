@@ -89,7 +89,7 @@ def main():
                     help="only run plain device copies of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+        print("bench.py measures one GPU only: there is no multi-GPU path (got --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -246,6 +246,7 @@ def main():
             reps += 1
         assert np.array_equal(ref, dist), "GPU result differs from the oracle"
         cpu = {"value": round(reps * m_reached / cpu_s / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu_model(), "host_cores": os.cpu_count(),
                "sample": "%d full SSSP queries (binary-heap Dijkstra, single thread) on the same graph and "
                          "source, %.2f s in all" % (reps, cpu_s)}
 
@@ -297,6 +298,18 @@ def main():
         res["bfs_small"] = bfs_small
     dg.close()
     print(json.dumps(res), flush=True)
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), for the baseline."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def gather_rate(words: int, n_idx: int, reps: int = 5, idx=None) -> float:

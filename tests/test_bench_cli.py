@@ -1,5 +1,5 @@
 """bench.py's command-line contract, on the CPU: more than one GPU is refused
-with a message (this build measures one GPU), the roofline helpers read the
+with a message (there is no multi-GPU path), the roofline helpers read the
 committed counter summary only when it was taken on the current kernel
 source, and the algorithmic byte model adds up as documented."""
 import json
