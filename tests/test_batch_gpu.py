@@ -218,3 +218,20 @@ def test_single_calls_on_a_set_work_on_the_union(alb, members):
     assert np.array_equal(lv[:n0], oracle.bfs(members[0], 0))
     assert (lv[n0:] == alb.INF).all()
     gs.close()
+
+
+def test_maximum_batch_count(alb):
+    """65,535 queries (the most one launch takes) on a small graph, every
+    result checked; one more query is refused."""
+    p = gg.path(10)
+    gs = alb.GraphSet([p, gg.star(5)], weighted=False)
+    count = 65535
+    mb = (np.arange(count) % 3 == 2).astype(np.int32)
+    src = (np.arange(count) % 5).astype(np.int32)
+    outs, st = alb.bfs_batch(gs, mb, src)
+    refs = {(m, s): oracle.bfs(p if m == 0 else gg.star(5), s) for m in (0, 1) for s in range(5)}
+    for q in range(count):
+        assert np.array_equal(outs[q], refs[(int(mb[q]), int(src[q]))]), q
+    with pytest.raises(alb.AlbError, match="count"):
+        alb.bfs_batch(gs, np.zeros(count + 1, np.int32), np.zeros(count + 1, np.int32))
+    gs.close()
