@@ -56,7 +56,9 @@ def test_sssp_rmat22_full(alb, rmat22w):
     log("oracle dijkstra %.1fs" % (time.time() - t))
     dg = alb.Graph(g.off, g.col, g.w)
     for c in [dict(), dict(threshold=4096), dict(threshold=256), dict(mode="twc"), dict(mode="lb_all"),
-              dict(threshold=4096, launch="host")]:
+              dict(threshold=4096, launch="host"), dict(distribution=1), dict(threshold="adaptive"),
+              dict(threshold="launched"), dict(wg_size=1024), dict(grid_wgs=alb.GRID_ALL), dict(dedup=False),
+              dict(wave_cutoff=32, wg_cutoff=512)]:
         d, st = alb.sssp(dg, s, **c)
         assert np.array_equal(d, ref), c
         log("sssp %s ok: rounds %d, %.2f ms" % (c, st["rounds"], st["device_ms"]))
