@@ -72,7 +72,8 @@ def test_bfs_zipf24_full(alb, zipf24):
     ref = oracle.bfs(g, s)
     log("oracle bfs %.1fs" % (time.time() - t))
     dg = alb.Graph(g.off, g.col)
-    for c in [dict(), dict(threshold=4096), dict(mode="twc"), dict(threshold=4096, launch="host")]:
+    for c in [dict(), dict(threshold=4096), dict(mode="twc"), dict(threshold=4096, launch="host"),
+              dict(distribution=1), dict(mode="lb_all"), dict(threshold="adaptive"), dict(wg_size=1024)]:
         lv, st = alb.bfs(dg, s, **c)
         assert np.array_equal(lv, ref), c
         log("bfs %s ok: rounds %d, huge %d, %.2f ms" % (c, st["rounds"], st["huge_vertices"], st["device_ms"]))
@@ -87,7 +88,7 @@ def test_cc_zipf24_full(alb, zipf24):
     t = time.time()
     dg = alb.Graph(g.off, g.col, None, build_symmetric=True)
     log("symmetrised on the host in %.1fs: m=%d" % (time.time() - t, dg.m))
-    for c in [dict(), dict(threshold=4096)]:
+    for c in [dict(), dict(threshold=4096), dict(mode="twc"), dict(distribution=1), dict(threshold=64)]:
         lab, st = alb.cc(dg, **c)
         assert np.array_equal(lab, ref), c
         log("cc %s ok: rounds %d, %.2f ms" % (c, st["rounds"], st["device_ms"]))
