@@ -166,7 +166,7 @@ def main():
         paper_rule = {"value": round(args.steps * m_reached / s3 / 1e9, 3), "ms_per_step": round(1e3 * s3 / args.steps, 4),
                       "huge_threshold": st3[-1]["huge_threshold"], "huge_vertices": st3[-1]["huge_vertices"]}
 
-    # the paper's threshold study (Section 5.1): 0 and powers of two, plus the
+    # the paper's threshold study (Section 6.1): 0 and powers of two, plus the
     # adaptive rule and LB for every vertex
     sweep = lb_all = blocked = None
     if not args.no_sweep and not args.only_alb:

@@ -262,6 +262,36 @@ def disjoint_copies(g: Graph, k: int) -> Graph:
     return from_edges(g.n * k, ss, dd, ww, name="%sx%d" % (g.name, k))
 
 
+def boundary_path(n: int, back_edges: int, seed: int, hub_back: int = 0) -> Graph:
+    """A directed path 0 -> 1 -> ... -> n-1 whose every edge weighs
+    W = (2^31 - 2) // (n - 1), so that the last vertex lies at distance
+    W * (n - 1) (2^31 - 2 = INT32_MAX - 1 when n - 1 divides it), plus
+    `back_edges` random edges u -> v with u > v and weights uniform in [0, W],
+    and `hub_back` more such edges out of the last vertex (distinct targets).
+    Backward edges cannot shorten the path, so vertex i lies at distance
+    i * W; their candidates from the far end exceed INT32_MAX."""
+    W = (2 ** 31 - 2) // (n - 1)
+    s = np.arange(n - 1)
+    src = [s]
+    dst = [s + 1]
+    wts = [np.full(n - 1, W, np.int64)]
+    a = uniform_ints(back_edges, n, seed, 0).astype(np.int64)
+    b = uniform_ints(back_edges, n, seed, 1).astype(np.int64)
+    keep = a != b
+    hi, lo = np.maximum(a, b)[keep], np.minimum(a, b)[keep]
+    src.append(hi)
+    dst.append(lo)
+    wts.append(uniform_ints(hi.size, W + 1, seed, 2).astype(np.int64))
+    if hub_back:
+        t = np.sort(np.random.Generator(np.random.Philox(seed)).choice(n - 1, size=min(hub_back, n - 1),
+                                                                       replace=False))
+        src.append(np.full(t.size, n - 1, np.int64))
+        dst.append(t.astype(np.int64))
+        wts.append(uniform_ints(t.size, W + 1, seed, 3).astype(np.int64))
+    return from_edges(n, np.concatenate(src), np.concatenate(dst), np.concatenate(wts),
+                      name="boundary_path%d" % n)
+
+
 def hub_graph(n: int, hubs, deg_small: int, seed: int) -> Graph:
     """Vertices in `hubs` (dict vertex -> out-degree) point at distinct random
     targets; every other vertex gets about `deg_small` random out-edges."""

@@ -29,11 +29,15 @@ static inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-/* Counter-based draw: independent 64-bit values addressed by (seed, stream, i). */
-uint64_t gg_draw(uint64_t seed, uint64_t stream, uint64_t i) {
-  uint64_t key = mix64(seed * 0x9e3779b97f4a7c15ULL + stream * 0xd1b54a32d192ed03ULL + 0x632be59bd9b4e019ULL);
-  return mix64(key + (i + 1) * 0x9e3779b97f4a7c15ULL);
+/* Counter-based draw: independent 64-bit values addressed by (seed, stream, i).
+ * The key of a (seed, stream) pair is computed once per loop (draw_key), the
+ * draw itself is one more finaliser call (draw_at). */
+static inline uint64_t draw_key(uint64_t seed, uint64_t stream) {
+  return mix64(seed * 0x9e3779b97f4a7c15ULL + stream * 0xd1b54a32d192ed03ULL + 0x632be59bd9b4e019ULL);
 }
+static inline uint64_t draw_at(uint64_t key, uint64_t i) { return mix64(key + (i + 1) * 0x9e3779b97f4a7c15ULL); }
+
+uint64_t gg_draw(uint64_t seed, uint64_t stream, uint64_t i) { return draw_at(draw_key(seed, stream), i); }
 
 /* Uniform double in [0, 1) with 53 random bits. */
 static inline double u01(uint64_t x) { return (double)(x >> 11) * (1.0 / 9007199254740992.0); }
@@ -64,9 +68,40 @@ void gg_fetch(const gg_graph *g, int32_t *off, int32_t *col) {
   if (g->m) memcpy(col, g->col, sizeof(int32_t) * (size_t)g->m);
 }
 
-static int cmp_i32(const void *a, const void *b) {
-  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
-  return (x > y) - (x < y);
+/* Ascending sort of non-negative int32 values: insertion sort for short rows,
+ * else least-significant-digit radix sort (11-bit digits) through `tmp`. */
+static void sort_row(int32_t *a, int64_t len, int32_t *tmp) {
+  if (len <= 48) {
+    for (int64_t i = 1; i < len; ++i) {
+      int32_t x = a[i];
+      int64_t j = i - 1;
+      while (j >= 0 && a[j] > x) {
+        a[j + 1] = a[j];
+        --j;
+      }
+      a[j + 1] = x;
+    }
+    return;
+  }
+  uint32_t mx = 0;
+  for (int64_t i = 0; i < len; ++i) mx |= (uint32_t)a[i];
+  int32_t *src = a, *dst = tmp;
+  for (int shift = 0; shift < 32 && (mx >> shift) != 0; shift += 11) {
+    int64_t cnt[2048];
+    memset(cnt, 0, sizeof cnt);
+    for (int64_t i = 0; i < len; ++i) cnt[((uint32_t)src[i] >> shift) & 2047u]++;
+    int64_t sum = 0;
+    for (int k = 0; k < 2048; ++k) {
+      int64_t c = cnt[k];
+      cnt[k] = sum;
+      sum += c;
+    }
+    for (int64_t i = 0; i < len; ++i) dst[cnt[((uint32_t)src[i] >> shift) & 2047u]++] = src[i];
+    int32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != a) memcpy(a, src, sizeof(int32_t) * (size_t)len);
 }
 
 /*
@@ -78,20 +113,33 @@ static int cmp_i32(const void *a, const void *b) {
 static gg_graph *finish_rows(int32_t n, const int64_t *raw_off, int32_t *raw) {
   int64_t *keep = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
   if (!keep) return NULL;
-#pragma omp parallel for schedule(dynamic, 1024)
-  for (int64_t v = 0; v < n; ++v) {
-    int32_t *row = raw + raw_off[v];
-    int64_t len = raw_off[v + 1] - raw_off[v];
-    if (len > 1) qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
-    int64_t w = 0;
-    for (int64_t i = 0; i < len; ++i) {
-      int32_t d = row[i];
-      if (d == (int32_t)v) continue;
-      if (w > 0 && row[w - 1] == d) continue;
-      row[w++] = d;
+  int64_t maxlen = 0;
+  for (int64_t v = 0; v < n; ++v) maxlen = raw_off[v + 1] - raw_off[v] > maxlen ? raw_off[v + 1] - raw_off[v] : maxlen;
+  int failed = 0;
+#pragma omp parallel
+  {
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxlen ? maxlen : 1));
+    if (!tmp) {
+#pragma omp atomic write
+      failed = 1;
     }
-    keep[v] = w;
+#pragma omp for schedule(dynamic, 1024)
+    for (int64_t v = 0; v < n; ++v) {
+      int32_t *row = raw + raw_off[v];
+      int64_t len = raw_off[v + 1] - raw_off[v];
+      if (len > 1 && tmp) sort_row(row, len, tmp);
+      int64_t w = 0;
+      for (int64_t i = 0; i < len; ++i) {
+        int32_t d = row[i];
+        if (d == (int32_t)v) continue;
+        if (w > 0 && row[w - 1] == d) continue;
+        row[w++] = d;
+      }
+      keep[v] = w;
+    }
+    free(tmp);
   }
+  if (failed) { free(keep); return NULL; }
   gg_graph *g = (gg_graph *)calloc(1, sizeof(gg_graph));
   if (!g) { free(keep); return NULL; }
   g->n = n;
@@ -121,11 +169,11 @@ static gg_graph *finish_rows(int32_t n, const int64_t *raw_off, int32_t *raw) {
  * four quadrants per bit level with probabilities a, b, c and 1-a-b-c, from
  * the most significant bit down.  Vertex 0 is therefore the hub.
  */
-static inline void rmat_edge(int scale, double a, double ab, double abc, uint64_t seed, uint64_t i,
+static inline void rmat_edge(int scale, double a, double ab, double abc, uint64_t key, uint64_t i,
                              int32_t *s, int32_t *d) {
   uint32_t src = 0, dst = 0;
   for (int l = 0; l < scale; ++l) {
-    double u = u01(gg_draw(seed, 1, i * (uint64_t)scale + (uint64_t)l));
+    double u = u01(draw_at(key, i * (uint64_t)scale + (uint64_t)l));
     uint32_t bs = 0, bd = 0;
     if (u < a) {
     } else if (u < ab) {
@@ -148,29 +196,31 @@ gg_graph *gg_rmat(int scale, int edge_factor, double a, double b, double c, uint
   int32_t n = (int32_t)1 << scale;
   int64_t raw_m = (int64_t)edge_factor * (int64_t)n;
   double ab = a + b, abc = a + b + c;
+  const uint64_t key = draw_key(seed, 1);
   int64_t *raw_off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-  if (!raw_off) return NULL;
-  /* pass 1: raw out-degree per source */
+  int32_t *es = (int32_t *)malloc(sizeof(int32_t) * (size_t)raw_m);
+  int32_t *ed = (int32_t *)malloc(sizeof(int32_t) * (size_t)raw_m);
+  if (!raw_off || !es || !ed) { free(raw_off); free(es); free(ed); return NULL; }
+  /* pass 1: draw every edge, count raw out-degrees per source */
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < raw_m; ++i) {
-    int32_t s, d;
-    rmat_edge(scale, a, ab, abc, seed, (uint64_t)i, &s, &d);
-    __atomic_fetch_add(&raw_off[s + 1], 1, __ATOMIC_RELAXED);
+    rmat_edge(scale, a, ab, abc, key, (uint64_t)i, &es[i], &ed[i]);
+    __atomic_fetch_add(&raw_off[es[i] + 1], 1, __ATOMIC_RELAXED);
   }
   for (int64_t v = 0; v < n; ++v) raw_off[v + 1] += raw_off[v];
   int32_t *raw = (int32_t *)malloc(sizeof(int32_t) * (size_t)raw_m);
   int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-  if (!raw || !cur) { free(raw_off); free(raw); free(cur); return NULL; }
+  if (!raw || !cur) { free(raw_off); free(raw); free(cur); free(es); free(ed); return NULL; }
   memcpy(cur, raw_off, sizeof(int64_t) * (size_t)n);
   /* pass 2: scatter destinations into their rows (row order fixed by the sort below) */
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < raw_m; ++i) {
-    int32_t s, d;
-    rmat_edge(scale, a, ab, abc, seed, (uint64_t)i, &s, &d);
-    int64_t p = __atomic_fetch_add(&cur[s], 1, __ATOMIC_RELAXED);
-    raw[p] = d;
+    int64_t p = __atomic_fetch_add(&cur[es[i]], 1, __ATOMIC_RELAXED);
+    raw[p] = ed[i];
   }
   free(cur);
+  free(es);
+  free(ed);
   gg_graph *g = finish_rows(n, raw_off, raw);
   free(raw_off);
   free(raw);
@@ -227,8 +277,9 @@ static inline int64_t zipf_sample(const zipf_table *z, double u) {
 int gg_zipf_degrees(int32_t n, double s, int64_t cap, uint64_t seed, int64_t *deg) {
   zipf_table z;
   if (zipf_init(&z, s, cap) != 0) return -1;
+  const uint64_t key = draw_key(seed, 2);
 #pragma omp parallel for schedule(static)
-  for (int64_t v = 0; v < n; ++v) deg[v] = zipf_sample(&z, u01(gg_draw(seed, 2, (uint64_t)v)));
+  for (int64_t v = 0; v < n; ++v) deg[v] = zipf_sample(&z, u01(draw_at(key, (uint64_t)v)));
   free(z.cdf);
   return 0;
 }
@@ -246,10 +297,10 @@ gg_graph *gg_zipf(int32_t n, double s, int64_t cap, uint64_t seed) {
   int64_t raw_m = raw_off[n];
   int32_t *raw = (int32_t *)malloc(sizeof(int32_t) * (size_t)(raw_m ? raw_m : 1));
   if (!raw) { free(raw_off); return NULL; }
+  const uint64_t key = draw_key(seed, 3);
 #pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t v = 0; v < n; ++v)
-    for (int64_t p = raw_off[v]; p < raw_off[v + 1]; ++p)
-      raw[p] = (int32_t)below(gg_draw(seed, 3, (uint64_t)p), (uint32_t)n);
+    for (int64_t p = raw_off[v]; p < raw_off[v + 1]; ++p) raw[p] = (int32_t)below(draw_at(key, (uint64_t)p), (uint32_t)n);
   gg_graph *g = finish_rows(n, raw_off, raw);
   free(raw_off);
   free(raw);
@@ -259,8 +310,9 @@ gg_graph *gg_zipf(int32_t n, double s, int64_t cap, uint64_t seed) {
 /* Edge weights: uniform integers in [lo, hi] (inclusive), one draw per CSR position. */
 void gg_uniform_weights(int64_t m, int32_t lo, int32_t hi, uint64_t seed, int32_t *w) {
   uint32_t span = (uint32_t)((int64_t)hi - (int64_t)lo + 1);
+  const uint64_t key = draw_key(seed, 4);
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < m; ++i) w[i] = lo + (int32_t)below(gg_draw(seed, 4, (uint64_t)i), span);
+  for (int64_t i = 0; i < m; ++i) w[i] = lo + (int32_t)below(draw_at(key, (uint64_t)i), span);
 }
 
 /* Uniform integers in [0, n) (source draws and the like). */

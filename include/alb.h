@@ -57,7 +57,7 @@ typedef enum {
  * ALB:      out-degree >= threshold (Algorithm 1).
  * TWC_ONLY: none (threshold above every degree; plain TWC, Section 3).
  * LB_ALL:   every active vertex with at least one edge (threshold 0; the
- *           paper's "D-IrGL (LB)" configuration, Section 5.1). */
+ *           paper's "D-IrGL (LB)" column of Table 3, Section 6.1). */
 typedef enum { ALB_MODE_ALB = 0, ALB_MODE_TWC_ONLY = 1, ALB_MODE_LB_ALL = 2 } alb_mode;
 
 /* Round driver.  HOST_LOOP launches one kernel per phase and reads the
@@ -92,7 +92,8 @@ typedef struct {
   int32_t mode;              /* alb_mode */
   int64_t huge_threshold;    /* ALB mode: degree >= this is huge; ALB_THRESHOLD_DEFAULT (-1) =
                                 m / (20 * workgroups) within [64, 4096] (see above), ALB_THRESHOLD_LAUNCHED
-                                (-2) = the launched thread count (the paper's rule, Section 5),
+                                (-2) = the launched thread count (the paper's rule, Section 4.1;
+                                its values for V100 and P100 in Section 5),
                                 ALB_THRESHOLD_ADAPTIVE (-3) */
   int32_t wg_size;           /* 0 = 256; one of 64, 256, 1024 */
   int32_t wave_cutoff;       /* TWC wavefront bin: degree >= this (0 = 64) */
@@ -128,7 +129,13 @@ typedef struct {
 alb_status alb_options_init(alb_options *opt);
 
 /* Copy a host CSR to the current HIP device and return a handle that owns the
- * device copy.  The caller keeps ownership of the host arrays.  `weights` may
+ * device copy.  The graph is stored as the paper stores it (Section 4.1,
+ * "Search"): compressed sparse rows, so that a vertex's out-edges are the
+ * contiguous range row_offsets[v] .. row_offsets[v+1] of col and its
+ * out-degree is the difference of two offsets -- the inspection of
+ * Algorithm 1 reads exactly that, and Algorithm 2 turns a huge edge's rank
+ * into a CSR position from the owner's first offset.  The caller keeps
+ * ownership of the host arrays.  `weights` may
  * be NULL (then alb_sssp is refused).  Validation follows the conventions
  * above; with weights, max(w) * (n - 1) must be < INT32_MAX (ALB_E_RANGE
  * otherwise).  ALB_BUILD_SYMMETRIC drops the weights. */
@@ -172,7 +179,10 @@ alb_status alb_bfs(alb_graph g, int32_t source, int32_t *level, const alb_option
  * (atomic minimum).  dist[v] = shortest distance, INT32_MAX if unreachable. */
 alb_status alb_sssp(alb_graph g, int32_t source, int32_t *dist, const alb_options *opt, alb_stats *stats);
 
-/* Weakly connected components by min-label propagation (push).  The handle
+/* Connected components, the paper's cc application (Section 5, where it is
+ * listed among the push-style operators): weakly connected components by
+ * min-label propagation, each active vertex offering its label to its
+ * neighbours through an atomic minimum.  The handle
  * must be symmetric (ALB_SYMMETRIC or ALB_BUILD_SYMMETRIC), else
  * ALB_E_INVAL.  label[v] = the smallest vertex id of v's component. */
 alb_status alb_cc(alb_graph g, int32_t *label, const alb_options *opt, alb_stats *stats);
@@ -185,7 +195,9 @@ alb_status alb_cc(alb_graph g, int32_t *label, const alb_options *opt, alb_stats
  * in the k-core, else 0.  k >= 0. */
 alb_status alb_kcore(alb_graph g, int32_t k, int32_t *in_core, const alb_options *opt, alb_stats *stats);
 
-/* PageRank, fp32, push over out-edges, exactly `iterations` synchronous
+/* PageRank, the paper's pr application (Section 5; the paper gives no
+ * formula, so the standard Jacobi form below is used), fp32, here pushed over
+ * out-edges so that the balancer sees out-degree skew, exactly `iterations` synchronous
  * iterations from rank = 1/n:  r'(v) = (1-d)/n + d * (sum over in-edges (u,v)
  * of r(u)/outdeg(u) + D/n), D = total rank of vertices without out-edges.
  * 0 < damping < 1, iterations >= 0. */
@@ -233,7 +245,7 @@ alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const
 alb_status alb_batch_plan_run(alb_plan p, alb_stats *stats);
 alb_status alb_batch_plan_destroy(alb_plan p);
 
-/* Autotuner (not part of the paper's method; its threshold study, Section 5,
+/* Autotuner (not part of the paper's method; its threshold study, Section 6.1,
  * motivates the search space).  Times BFS or SSSP batches of the given
  * sources (1..64) on member `member` of g under candidate settings --
  * workgroup size 256 or 1024, huge threshold 64 or 2^8, 2^10, 2^12, 2^14

@@ -250,6 +250,26 @@ alb_status symmetrise(int32_t n, const int32_t *off, const int32_t *col, std::ve
 // Workspaces
 // --------------------------------------------------------------------------
 
+// Entries of the huge-edge chunk index: one per 2^kHintMinShift huge edges of
+// a round, plus two.  A round's huge edges are at most the worklist capacity
+// times the largest degree (a 32-bit total: a larger one is reported as an
+// overflow by the reservation); when every vertex enters a round's worklist at
+// most once (`unique_edges` >= 0: the edge count of the graph or the batch)
+// they are at most those edges.
+uint32_t hint_entries(uint64_t qcap, int64_t unique_edges, int64_t max_deg) {
+  uint64_t e = std::min<uint64_t>(qcap * (uint64_t)std::max<int64_t>(max_deg, 1), 1ull << 32);
+  if (unique_edges >= 0) e = std::min<uint64_t>(e, (uint64_t)unique_edges);
+  return (uint32_t)((e >> kHintMinShift) + 2);
+}
+
+// The distinct-entry bound of one round's worklist: BFS, k-core and PageRank
+// enter each vertex at most once per round, SSSP and CC with dedup too.
+int64_t dedup_bound(OpKind op, bool dedup, int64_t m) {
+  if (op == OP_SSSP || op == OP_CC) return dedup ? m : -1;
+  if (op == OP_RECORD) return -1;
+  return m;
+}
+
 struct Needs {
   uint32_t qcap;
   uint32_t hint_cap;
@@ -658,7 +678,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   qcap = std::max<uint64_t>(qcap, 1);
   if (qcap > 0xfffffffeULL) qcap = 0xfffffffeULL;
 
-  Needs nd{(uint32_t)qcap, (uint32_t)(((uint64_t)g->m >> kHintMinShift) + 2)};
+  Needs nd{(uint32_t)qcap, hint_entries(qcap, dedup_bound(job.op, dedup, g->m), g->max_deg)};
   Workspace *ws = nullptr;
   alb_status s = ws_acquire(g, nd, &ws);
   if (s != ALB_OK) return s;
@@ -843,6 +863,7 @@ struct BatchJob {
   bool per_query_thr = false;
   long long labels = 0, edges = 0, thr_min = 0;
   int32_t max_n = 0;
+  int32_t max_deg = 0;  // largest out-degree of the queries' members
   uint64_t qcap = 0;
   int grid = 0;
   int64_t threshold = 0;
@@ -890,6 +911,7 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
     labels += n;
     edges += g->mem_m[mb];
     max_n = std::max(max_n, n);
+    j.max_deg = std::max(j.max_deg, g->mem_maxdeg[mb]);
   }
   j.labels = labels;
   j.edges = edges;
@@ -959,7 +981,7 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
 
 BatchNeeds batch_needs(const BatchJob &j) {
   return BatchNeeds{std::max<long long>(j.labels, 1), (uint32_t)j.qcap,
-                    (uint32_t)(((uint64_t)j.edges >> kHintMinShift) + 2), j.count};
+                    hint_entries(j.qcap, j.a.dedup ? j.edges : -1, j.max_deg), j.count};
 }
 
 // Point the job at workspace ws and copy its tables there (stream order).

@@ -149,8 +149,14 @@ struct OpSSSP {  // relaxation: dist[dst] = min(dist[dst], dist[src] + w)
   __device__ __forceinline__ val_t load_src(long long sl, int32_t, uint32_t tag, bool &skip) const {
     return label_of_active(word[sl], tag, skip);
   }
+  // The candidate sv + w saturates at INT32_MAX (the unreached label), which it
+  // then cannot lower.  Both terms are in [0, INT32_MAX], so their sum fits in
+  // 32 unsigned bits.  A sum beyond INT32_MAX - 1 is never a shortest
+  // distance (graph creation bounds those by max(w) * (n - 1)), so dropping
+  // it changes no result.
   __device__ __forceinline__ pre_t prepare(int32_t pos, long long dl, val_t sv) const {
-    return {sv + w[pos], word[dl]};
+    const uint32_t c = (uint32_t)sv + (uint32_t)w[pos];
+    return {(int32_t)min(c, (uint32_t)kInf), word[dl]};
   }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t, int32_t, int32_t,
                                          uint32_t tag) const {

@@ -159,6 +159,33 @@ def test_sssp_closed_forms():
     assert np.array_equal(oracle.sssp(gz, 0), np.zeros(n, dtype=np.int32))
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_sssp_zero_weights_vs_floyd_warshall(seed):
+    """Weights uniform in [0, 2]: zero-weight edges and zero-weight cycles."""
+    g = gg.random_digraph(30, 150, seed).with_weights(seed, 0, 2)
+    assert (g.w == 0).sum() > 10
+    D = floyd_warshall(g)
+    for s in range(g.n):
+        assert np.array_equal(oracle.sssp(g, s), to_int_dist(D[s]))
+    gz = gg.cycle(17, w=np.zeros(17, np.int64))
+    assert np.array_equal(oracle.sssp(gz, 5), np.zeros(17, np.int32))
+
+
+def test_sssp_int32_boundary():
+    """A path whose last vertex lies at INT32_MAX - 1 (62 edges of weight
+    (2^31 - 2) / 62) with backward edges whose candidates exceed INT32_MAX:
+    vertex i at i * W (closed form), and Floyd-Warshall agrees."""
+    g = gg.boundary_path(63, 400, seed=4, hub_back=40)
+    W = (2 ** 31 - 2) // 62
+    assert W * 62 == 2 ** 31 - 2 and int(g.w.max()) == W
+    d = oracle.sssp(g, 0)
+    assert np.array_equal(d.astype(np.int64), np.arange(63, dtype=np.int64) * W)
+    assert int(d[-1]) == 2 ** 31 - 2
+    D = floyd_warshall(g)
+    for s in (0, 1, 31, 62):
+        assert np.array_equal(oracle.sssp(g, s), to_int_dist(D[s]))
+
+
 def check_sssp_invariants(g, s, d):
     src = edge_src(g)
     d64 = d.astype(np.int64)

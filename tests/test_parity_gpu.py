@@ -125,14 +125,10 @@ def test_sssp_matrix(alb, name):
 
 def check_no_dedup(alb, run, ref, g):
     """Without deduplication a vertex can be pushed once per improving edge,
-    so a round's worklist is bounded only by the edges examined: a big
-    capacity is given, and an exceeded one must be reported, never a wrong
-    answer."""
-    try:
-        got = run(dedup=False, threshold=64, worklist_capacity=64 * (g.n + g.m) + 64)
-    except alb.AlbError as e:
-        assert e.status == alb.ALB_E_OVERFLOW
-        return
+    so a round's worklist is bounded only by the edges examined.  With a
+    capacity well above what these graphs push, the run must finish (the
+    huge-edge chunk index grows with the capacity) and equal the oracle."""
+    got = run(dedup=False, threshold=64, worklist_capacity=64 * (g.n + g.m) + 64)
     assert np.array_equal(got, ref)
 
 
