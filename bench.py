@@ -87,6 +87,9 @@ def main():
                     help="only measure plain random 8-byte gathers (the access pattern of the label reads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: leave out the Zipf-2^24, batch and serving summaries")
+    ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each summary measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -114,11 +117,14 @@ def main():
     from paper_1911_09135_amd import alb
 
     if args.workload == "batch":
-        return bench_batch(args, alb, gg)
+        bench_batch(args, alb, gg)
+        return
     if args.workload == "serve":
-        return bench_serve(args, alb, gg)
+        bench_serve(args, alb, gg)
+        return
     if args.workload == "zipf24":
-        return bench_zipf24(args, alb, gg)
+        bench_zipf24(args, alb, gg, cpu=not args.no_cpu)
+        return
 
     t = time.perf_counter()
     g = gg.workload("rmat22w")
@@ -303,6 +309,23 @@ def main():
     if bfs_small is not None:
         res["bfs_small"] = bfs_small
     dg.close()
+    del g
+    if not args.only_alb and not args.no_extras:
+        # the other configurations of the metric, each as a nested summary
+        # with fewer timed steps (the headline above stays `value`)
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup = args.extra_steps, 1
+        t = time.perf_counter()
+        res["zipf24"] = bench_zipf24(sub, alb, gg, emit=False, cpu=not args.no_cpu, kcore=False, grid=False)
+        log("zipf24 summary: %.1fs" % (time.perf_counter() - t))
+        t = time.perf_counter()
+        res["batch"] = bench_batch(sub, alb, gg, emit=False)
+        log("batch summary: %.1fs" % (time.perf_counter() - t))
+        t = time.perf_counter()
+        sub.requests = 1500
+        sub.rates = "100,1000,2000"
+        res["serve"] = bench_serve(sub, alb, gg, emit=False)
+        log("serve summary: %.1fs" % (time.perf_counter() - t))
     print(json.dumps(res), flush=True)
 
 
@@ -371,13 +394,16 @@ def random_probe(args):
     print(json.dumps({"random_probe": res, "indices": n_idx}), flush=True)
 
 
-def bench_batch(args, alb, gg):
+def bench_batch(args, alb, gg, emit=True):
     """256 SSSP queries (query i on graph i mod 64, a random source of
     out-degree > 0) over 64 weighted RMAT graphs of scales drawn from 12..20,
     all resident in HBM.  A step runs every query once: batched = one
-    alb_sssp_batch launch on the graph set; one-at-a-time = 256 alb_sssp calls
-    on the graphs' own handles.  Reported: queries/s of the batched step and
-    per-query latency percentiles of both."""
+    alb_sssp_batch launch on the graph set; plan = the same batch captured
+    once into a HIP graph and replayed (alb_batch_plan_run); one-at-a-time =
+    256 alb_sssp calls on the graphs' own handles.  Reported: queries/s of the
+    batched step, GTEPS over the edges of reached vertices, per-step latency
+    percentiles of the batch and the plan and per-query percentiles of the
+    single calls.  Returns the result line (printed when `emit`)."""
     import numpy as np
     import torch
 
@@ -409,6 +435,29 @@ def bench_batch(args, alb, gg):
         step_s.append(time.perf_counter() - ts)
     sec = time.perf_counter() - t0
     log("batched: %.3f ms/step, %d rounds, kernel %.3f ms" % (1e3 * sec / args.steps, st["rounds"], st["kernel_ms"]))
+    # edges of the vertices each query reached (the GTEPS numerator)
+    m_reached = 0
+    for i, o in enumerate(outs):
+        gi = graphs[int(members[i])]
+        m_reached += int(gi.degrees()[o.cpu().numpy() < alb.INF].sum())
+
+    # the same batch captured into a HIP graph once and replayed
+    plan_outs = [torch.empty_like(o) for o in outs]
+    plan = alb.BatchPlan(gset, "sssp", members, sources, outs=plan_outs, **bopts)
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    plan_s = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        plan.run()
+        torch.cuda.synchronize()
+        plan_s.append(time.perf_counter() - ts)
+    psec = time.perf_counter() - t0
+    plan_same = all(bool(torch.equal(a, b)) for a, b in zip(outs, plan_outs))
+    plan.close()
+    log("plan: %.3f ms/step" % (1e3 * psec / args.steps))
 
     tuned = None
     if args.tune:
@@ -470,11 +519,19 @@ def bench_batch(args, alb, gg):
                    "vertices": int(sum(g.n for g in graphs)), "edges": int(sum(g.m for g in graphs)),
                    "rounds": st["rounds"], "launched_threads": st["launched_threads"],
                    "huge_threshold": st["huge_threshold"]},
-        "gteps": round(args.steps * edges / sec / 1e9, 3),
-        "latency_ms": {"p50": pct(step_s, 50), "p99": pct(step_s, 99)},
+        "gteps": round(args.steps * m_reached / sec / 1e9, 3),
+        "m_reached": m_reached,
+        "gteps_whole_graphs": round(args.steps * edges / sec / 1e9, 3),
+        "latency_ms": {"p50": pct(step_s, 50), "p99": pct(step_s, 99), "per": "whole batch (256 queries)"},
+        "plan": {"value": round(args.steps * q / psec, 1), "unit": "queries/s",
+                 "ms_per_step": round(1e3 * psec / args.steps, 4),
+                 "gteps": round(args.steps * m_reached / psec / 1e9, 3),
+                 "latency_ms": {"p50": pct(plan_s, 50), "p99": pct(plan_s, 99), "per": "whole batch"},
+                 "same_result": plan_same},
         "one_at_a_time": {"value": round(args.steps * q / sec1, 1), "unit": "queries/s",
-                          "gteps": round(args.steps * edges / sec1 / 1e9, 3),
-                          "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99)}, "same_result": same},
+                          "gteps": round(args.steps * m_reached / sec1 / 1e9, 3),
+                          "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99), "per": "query"},
+                          "same_result": same},
         "speedup_vs_one_at_a_time": round(sec1 / sec, 2),
         "autotuned": tuned,
         "batch_stats": {k: st[k] for k in ("frontier_vertices", "edges_examined", "huge_vertices", "huge_edges",
@@ -483,16 +540,21 @@ def bench_batch(args, alb, gg):
     for h in handles:
         h.close()
     gset.close()
-    print(json.dumps(res), flush=True)
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
-def bench_zipf24(args, alb, gg):
+def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True):
     """The extreme-skew graph: Zipf(1.9) out-degrees capped at 4,194,304,
     n = 2^24 (~372M edges).  BFS from the highest-degree vertex, CC and k-core
-    (k = 8, 32) on the symmetrised graph, PageRank (0.85, 50 iterations), each
-    with the default balancer and TWC only; plus a 2048 x 2048 undirected grid
-    (low skew, high diameter) where the balancer should cost nothing.  Times are the
-    traversal kernels' device time (median of the steps)."""
+    (k = 8, 32) on the symmetrised graph, PageRank (0.85, 50 iterations) by
+    push and by pull, each with the default balancer and TWC only; plus a
+    2048 x 2048 undirected grid (low skew, high diameter) where the balancer
+    should cost nothing.  Times are the traversal kernels' device time (median
+    of the steps).  With `cpu`, the oracle's queue BFS on the same graph and
+    source, single thread, as the CPU baseline (and the GPU levels checked
+    against it).  Returns the result line (printed when `emit`)."""
     import numpy as np
     import torch
 
@@ -505,6 +567,9 @@ def bench_zipf24(args, alb, gg):
             ks.append(st["kernel_ms"])
         return float(np.median(ks)), st
 
+    def rates(b, ms):
+        return {"achieved_gbs": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
     res = {}
     t = time.perf_counter()
     g = gg.workload("zipf24")
@@ -514,23 +579,47 @@ def bench_zipf24(args, alb, gg):
     dg = alb.Graph(g.off, g.col)
     out = torch.empty(g.n, dtype=torch.int32, device="cuda")
     alb_opts = {} if args.threshold is None else {"threshold": args.threshold}
+    levels = None
     for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
         ms, st = timed(alb.bfs, dg, out, opts, src)
-        m_r = int(deg[out.cpu().numpy() < alb.INF].sum())
+        lv = out.cpu().numpy()
+        if levels is None:
+            levels = lv
+        m_r = int(deg[lv < alb.INF].sum())
         b = alb.algorithmic_bytes("bfs", st)
-        res.setdefault("bfs", {})[label] = {"kernel_ms": round(ms, 4), "gteps": round(m_r / ms / 1e6, 3),
-                                            "achieved_gbs": round(b / ms / 1e6, 1),
-                                            "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
-                                            "huge_vertices": st["huge_vertices"]}
+        res.setdefault("bfs", {})[label] = dict({"kernel_ms": round(ms, 4), "gteps": round(m_r / ms / 1e6, 3),
+                                                 "huge_vertices": st["huge_vertices"]}, **rates(b, ms))
         log("bfs %s: %.3f ms" % (label, ms))
+    res["bfs"]["twc_same_result"] = bool(np.array_equal(lv, levels))
+    res["bfs"]["alb_over_twc"] = round(res["bfs"]["twc_only"]["kernel_ms"] / res["bfs"]["alb"]["kernel_ms"], 2)
+    m_reached = int(deg[levels < alb.INF].sum())
+    cpu_line = None
+    if cpu:
+        import oracle
+
+        saved = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(saved)})
+        reps, cpu_s = 0, 0.0
+        try:
+            while reps < 4 and (reps == 0 or cpu_s < 8.0):
+                t0 = time.perf_counter()
+                ref = oracle.bfs(g, src)
+                cpu_s += time.perf_counter() - t0
+                reps += 1
+        finally:
+            os.sched_setaffinity(0, saved)
+        res["bfs"]["bit_exact"] = bool(np.array_equal(ref, levels))
+        cpu_line = {"value": round(reps * m_reached / cpu_s / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                    "host_cpu": host_cpu_model(), "host_cores": os.cpu_count(),
+                    "sample": "%d full BFS queries (FIFO queue, single thread pinned to one core) on the same graph "
+                              "and source, %.2f s in all" % (reps, cpu_s)}
+        log("cpu oracle bfs: %.2f s per query" % (cpu_s / reps))
     outf = torch.empty(g.n, dtype=torch.float32, device="cuda")
     for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
         ms, st = timed(alb.pagerank, dg, outf, opts, 0.85, 50)
         b = alb.algorithmic_bytes("pagerank", st, n=g.n, iterations=50)
-        res.setdefault("pagerank", {})[label] = {"kernel_ms": round(ms, 3),
-                                                 "gteps": round(50 * g.m / ms / 1e6, 3),
-                                                 "achieved_gbs": round(b / ms / 1e6, 1),
-                                                 "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        res.setdefault("pagerank", {})[label] = dict({"kernel_ms": round(ms, 3),
+                                                      "gteps": round(50 * g.m / ms / 1e6, 3)}, **rates(b, ms))
         log("pagerank %s: %.3f ms" % (label, ms))
     push_rank = outf.cpu().numpy()
     dg.close()
@@ -541,11 +630,9 @@ def bench_zipf24(args, alb, gg):
     for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
         ms, st = timed(alb.pagerank_pull, dt, outf, opts, 0.85, 50)
         b = alb.algorithmic_bytes("pagerank", st, n=g.n, iterations=50)
-        res.setdefault("pagerank_pull", {})[label] = {"kernel_ms": round(ms, 3),
-                                                      "gteps": round(50 * g.m / ms / 1e6, 3),
-                                                      "achieved_gbs": round(b / ms / 1e6, 1),
-                                                      "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
-                                                      "huge_vertices": st["huge_vertices"]}
+        res.setdefault("pagerank_pull", {})[label] = dict({"kernel_ms": round(ms, 3),
+                                                           "gteps": round(50 * g.m / ms / 1e6, 3),
+                                                           "huge_vertices": st["huge_vertices"]}, **rates(b, ms))
         log("pagerank pull %s: %.3f ms" % (label, ms))
     res["pagerank_pull"]["equals_push"] = bool(np.array_equal(outf.cpu().numpy(), push_rank))
     dt.close()
@@ -555,34 +642,35 @@ def bench_zipf24(args, alb, gg):
     for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
         ms, st = timed(lambda d, out=None, **o: alb.cc(d, out=out, **o), ds, out, opts)
         b = alb.algorithmic_bytes("cc", st)
-        res.setdefault("cc", {})[label] = {"kernel_ms": round(ms, 3),
-                                           "edges_per_s_g": round(st["edges_examined"] / ms / 1e6, 3),
-                                           "achieved_gbs": round(b / ms / 1e6, 1),
-                                           "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4), "rounds": st["rounds"]}
+        res.setdefault("cc", {})[label] = dict({"kernel_ms": round(ms, 3),
+                                                "edges_per_s_g": round(st["edges_examined"] / ms / 1e6, 3),
+                                                "gteps": round(ds.m / ms / 1e6, 3), "rounds": st["rounds"]},
+                                               **rates(b, ms))
         log("cc %s: %.3f ms" % (label, ms))
+    res["cc"]["alb_over_twc"] = round(res["cc"]["twc_only"]["kernel_ms"] / res["cc"]["alb"]["kernel_ms"], 2)
     # k-core (the paper's kcore) on the same symmetrised graph: peeling from
     # every vertex with fewer than k neighbours
-    for k in (8, 32):
+    for k in ((8, 32) if kcore else ()):
         for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
             ms, st = timed(lambda d, kk, out=None, **o: alb.kcore(d, kk, out=out, **o), ds, out, opts, k)
             b = alb.algorithmic_bytes("kcore", st)
-            res.setdefault("kcore_k%d" % k, {})[label] = {
+            res.setdefault("kcore_k%d" % k, {})[label] = dict({
                 "kernel_ms": round(ms, 3), "edges_per_s_g": round(st["edges_examined"] / ms / 1e6, 3),
-                "achieved_gbs": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
-                "rounds": st["rounds"], "core_vertices": int(out.sum().item())}
+                "rounds": st["rounds"], "core_vertices": int(out.sum().item())}, **rates(b, ms))
             log("kcore k=%d %s: %.3f ms" % (k, label, ms))
     ds.close()
     del g
-    gr = gg.grid(2048, 2048).with_weights(5)
-    dgr = alb.Graph(gr.off, gr.col, gr.w)
-    outg = torch.empty(gr.n, dtype=torch.int32, device="cuda")
-    for kind, fn in (("bfs", alb.bfs), ("sssp", alb.sssp)):
-        for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
-            ms, st = timed(fn, dgr, outg, opts, 0)
-            res.setdefault("grid2048_" + kind, {})[label] = {"kernel_ms": round(ms, 3), "rounds": st["rounds"],
-                                                             "huge_vertices": st["huge_vertices"]}
-            log("grid %s %s: %.3f ms" % (kind, label, ms))
-    dgr.close()
+    if grid:
+        gr = gg.grid(2048, 2048).with_weights(5)
+        dgr = alb.Graph(gr.off, gr.col, gr.w)
+        outg = torch.empty(gr.n, dtype=torch.int32, device="cuda")
+        for kind, fn in (("bfs", alb.bfs), ("sssp", alb.sssp)):
+            for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+                ms, st = timed(fn, dgr, outg, opts, 0)
+                res.setdefault("grid2048_" + kind, {})[label] = {"kernel_ms": round(ms, 3), "rounds": st["rounds"],
+                                                                 "huge_vertices": st["huge_vertices"]}
+                log("grid %s %s: %.3f ms" % (kind, label, ms))
+        dgr.close()
     bfs = res["bfs"]["alb"]
     line = {
         "metric": METRIC,
@@ -597,13 +685,17 @@ def bench_zipf24(args, alb, gg):
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "zipf1.9_n2^24_cap4194304: bfs, cc, kcore, pagerank; grid2048 bfs, sssp",
-                   "source": src},
+        "config": {"workload": "zipf1.9_n2^24_cap4194304: bfs, cc, pagerank push and pull%s" %
+                               ((", kcore" if kcore else "") + ("; grid2048 bfs, sssp" if grid else "")),
+                   "source": src, "m_reached": m_reached},
         "roofline": {"bound": "hbm", "achieved": bfs["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bfs["frac"], "traffic": None},
+        "cpu_baseline": cpu_line,
         "results": res,
     }
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 class _BufferPool:
@@ -633,13 +725,16 @@ class _BufferPool:
             self.free[m].append(a)
 
 
-def serve_run(alb, srv, pool, reqs, arrivals):
+def serve_run(alb, srv, pool, reqs, arrivals, keep=()):
     """Submit reqs[i] at arrivals[i] seconds (None: all at once); returns
-    (achieved queries/s, latencies ms, batch sizes, failures)."""
+    (achieved queries/s, latencies ms, batch sizes, failures); the results of
+    the requests whose indices are in `keep` are copied into srv.kept[i]."""
     import threading
 
     import numpy as np
 
+    keep = set(keep)
+    srv.kept = {}
     tickets = [None] * len(reqs)
     ready = threading.Semaphore(0)
     lat, sizes, fails = [], [], [0]
@@ -653,6 +748,8 @@ def serve_run(alb, srv, pool, reqs, arrivals):
                 _, info = srv.wait(t)
                 lat.append(info["latency_ms"])
                 sizes.append(info["batch_size"])
+                if i in keep:
+                    srv.kept[i] = np.array(buf, copy=True)
             except alb.AlbError:
                 fails[0] += 1
             pool.put(m, buf)
@@ -677,7 +774,7 @@ def serve_run(alb, srv, pool, reqs, arrivals):
     return len(reqs) / (done_t[0] - t0), np.asarray(lat), np.asarray(sizes), fails[0]
 
 
-def bench_serve(args, alb, gg):
+def bench_serve(args, alb, gg, emit=True):
     """Serving: 32 device-resident graphs (30 RMAT of scales 14..22 and Zipf
     graphs of 2^20 and 2^23 vertices, weights U[1,100]); requests BFS:SSSP
     1:1, graph uniform, source uniform over vertices with out-edges.  For each
@@ -711,8 +808,26 @@ def bench_serve(args, alb, gg):
     serve_run(alb, batched, pool, warm, None)
     serve_run(alb, single, pool, warm[:50], None)
 
+    # served results checked against the oracle: a sample of the capacity run's and each stream's
+    # requests on the member graphs of at most 2M edges
+    import oracle
+
+    checked = {"requests": 0, "equal": 0}
+
+    def sample(r, k=6):
+        idx = [i for i, (_, m, _) in enumerate(r) if graphs[m].m <= (2 << 20)]
+        return idx[:: max(1, len(idx) // k)][:k]
+
+    def verify(srv, r):
+        for i, got in srv.kept.items():
+            a, m, src = r[i]
+            want = oracle.bfs(graphs[m], src) if a == "bfs" else oracle.sssp(graphs[m], src)
+            checked["requests"] += 1
+            checked["equal"] += int(np.array_equal(got, want))
+
     reqs = make_requests(args.requests, 9)
-    cap, lat, sizes, f = serve_run(alb, batched, pool, reqs, None)
+    cap, lat, sizes, f = serve_run(alb, batched, pool, reqs, None, keep=sample(reqs))
+    verify(batched, reqs)
     log("batched capacity: %.0f queries/s, p50 %.1f ms, p99 %.1f ms, mean batch %.1f" % (
         cap, pct(lat, 50), pct(lat, 99), sizes.mean()))
     n1 = min(args.requests, 2000)
@@ -722,7 +837,8 @@ def bench_serve(args, alb, gg):
     for rate in [float(x) for x in args.rates.split(",")]:
         arr = gg.poisson_arrivals(rate, args.requests, seed=9)
         r = make_requests(args.requests, 10 + int(rate))
-        thr, l, sz, fb = serve_run(alb, batched, pool, r, arr)
+        thr, l, sz, fb = serve_run(alb, batched, pool, r, arr, keep=sample(r))
+        verify(batched, r)
         m1 = min(args.requests, max(200, int(rate * 10)), 2000)
         thr1, l1, _, fs = serve_run(alb, single, pool, r[:m1], arr[:m1])
         rates.append({"rate": rate, "requests": len(r), "achieved": round(thr, 1), "p50_ms": pct(l, 50),
@@ -756,10 +872,13 @@ def bench_serve(args, alb, gg):
         "one_at_a_time": {"value": round(cap1, 1), "unit": "queries/s", "requests": n1,
                           "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99)}, "failed": f1},
         "poisson": rates,
+        "results_checked_against_oracle": checked,
         "server_stats": st,
     }
     gset.close()
-    print(json.dumps(res), flush=True)
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 if __name__ == "__main__":

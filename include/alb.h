@@ -364,6 +364,21 @@ alb_status alb_server_stats_get(alb_server s, alb_server_stats *st);
  * dropped. */
 alb_status alb_server_destroy(alb_server s);
 
+/* One dispatched batch of a server. */
+typedef struct {
+  int32_t lane, algo, batch_size, status;
+  double device_begin_ms; /* its persistent launch on the device wall clock (ms from the device's own origin, */
+  double device_end_ms;   /* the same for every lane): first workgroup joined, last round left; 0 without */
+  double host_begin_ms;   /* dispatch and completion on the host, ms since the server was created */
+  double host_end_ms;
+} alb_batch_record;
+
+/* The server's most recent dispatched batches, oldest first: up to `max`
+ * records into `out`, *count = how many were written.  The server keeps the
+ * last 4096.  Two lanes whose device windows intersect ran on the device at
+ * the same time. */
+alb_status alb_server_batch_log(alb_server s, int32_t max, alb_batch_record *out, int32_t *count);
+
 /* PageRank as the paper's pr does it (pull, Section 5): the same iteration
  * and arguments as alb_pagerank, but every vertex sums its in-neighbours'
  * rank(u)/outdeg(u) over the transposed graph, and the balancer classifies

@@ -14,11 +14,12 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libalb.so")
+# ALB_LIBRARY: another build of the same library (the sanitizer builds)
+LIB_PATH = os.environ.get("ALB_LIBRARY") or os.path.join(_HERE, "libalb.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libalb.so is not built (python -m paper_1911_09135_amd.build); "
-                      "the ALB library has no CPU fallback")
+    raise ImportError("%s is not built (python -m paper_1911_09135_amd.build); the ALB library has no CPU "
+                      "fallback" % LIB_PATH)
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -115,6 +116,13 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "timed_out", "cancelled",
                                               "rejected", "batches", "pending", "running")] + \
                [("busy_ms", ctypes.c_double)]
+
+
+class BatchRecord(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("lane", "algo", "batch_size", "status")] + \
+               [(k, ctypes.c_double) for k in ("device_begin_ms", "device_end_ms", "host_begin_ms", "host_end_ms")]
+
+
 _POpt, _PSt = ctypes.POINTER(Options), ctypes.POINTER(Stats)
 _sig = {
     "alb_options_init": ([_POpt], ctypes.c_int),
@@ -149,6 +157,7 @@ _sig = {
     "alb_server_drain": ([_vp], ctypes.c_int),
     "alb_server_stats_get": ([_vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
     "alb_server_destroy": ([_vp], ctypes.c_int),
+    "alb_server_batch_log": ([_vp, _i32, ctypes.POINTER(BatchRecord), ctypes.POINTER(_i32)], ctypes.c_int),
     "alb_trace_round": ([_vp, _vp, _i64, _POpt, _vp, _vp, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp,
                          ctypes.POINTER(_i64), _PSt], ctypes.c_int),
     "alb_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -531,6 +540,13 @@ class Server:
         st = ServerStats()
         _check(_lib.alb_server_stats_get(self._h, ctypes.byref(st)), "alb_server_stats_get")
         return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def batch_log(self, max_records: int = 4096) -> list:
+        """The most recent dispatched batches, oldest first (alb_server_batch_log)."""
+        buf = (BatchRecord * max(max_records, 1))()
+        n = _i32()
+        _check(_lib.alb_server_batch_log(self._h, max_records, buf, ctypes.byref(n)), "alb_server_batch_log")
+        return [{k: getattr(buf[i], k) for k, _ in BatchRecord._fields_} for i in range(n.value)]
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

@@ -24,27 +24,59 @@ DEVICE += os.environ.get("ALB_DEFINES", "").split()
 SOURCES = [("alb_kernels.hip", DEVICE), ("alb_api.cpp", []), ("alb_server.cpp", [])]
 
 
-def build(verbose: bool = False) -> str:
-    objdir = os.path.join(HERE, "_build")
+# Sanitizer builds of the host runtime (alb_api.cpp, alb_server.cpp): the
+# host C++ files are compiled with the sanitizer, the device file as usual,
+# into _build/libalb_<name>.so (never the product library).  Load it with
+# ALB_LIBRARY=<path> and the sanitizer runtime preloaded (see sanitizer_env).
+SANITIZERS = {"address": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],
+              "thread": ["-fsanitize=thread"]}
+SAN_RUNTIME = {"address": "libclang_rt.asan-x86_64.so", "thread": "libclang_rt.tsan-x86_64.so"}
+
+
+def sanitizer_runtime(name: str) -> str:
+    """Path of the clang sanitizer runtime to preload for a sanitizer build."""
+    res = subprocess.check_output(["/opt/rocm/llvm/bin/clang", "-print-resource-dir"], text=True).strip()
+    for sub in ("lib/linux", "lib/x86_64-unknown-linux-gnu"):
+        p = os.path.join(res, sub, SAN_RUNTIME[name])
+        if os.path.exists(p):
+            return p
+    raise FileNotFoundError(SAN_RUNTIME[name])
+
+
+def build(verbose: bool = False, sanitize: str = "") -> str:
+    objdir = os.path.join(HERE, "_build", sanitize) if sanitize else os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
+    san = SANITIZERS[sanitize] + ["-g", "-fno-omit-frame-pointer"] if sanitize else []
+    lib = os.path.join(HERE, "_build", "libalb_%s.so" % sanitize) if sanitize else LIB
     objs = []
     for src, extra in SOURCES:
         obj = os.path.join(objdir, src + ".o")
+        if sanitize and src.endswith(".hip"):
+            plain = os.path.join(HERE, "_build", src + ".o")
+            if os.path.exists(plain) and os.path.getmtime(plain) >= os.path.getmtime(os.path.join(CSRC, src)):
+                objs.append(plain)  # device files are built without a sanitizer: reuse the product objects
+                continue
         cmd = [HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [HIPCC] + COMMON + san + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-c",
+                                            os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=%s" % ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    tmp = lib + ".tmp%d" % os.getpid()
+    link_san = (san[:1] + ["-shared-libsan"]) if sanitize else []
+    cmd = [HIPCC, "--offload-arch=%s" % ARCH, "-shared", "-fPIC", "-o", tmp] + link_san + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    san = ""
+    for a in sys.argv[1:]:
+        if a.startswith("--sanitize="):
+            san = a.split("=", 1)[1]
+    print(build(verbose="-v" in sys.argv, sanitize=san))

@@ -275,12 +275,28 @@ struct Needs {
   uint32_t hint_cap;
 };
 
+// Fault injection for tests: while ALB_INJECT_ALLOC_FAILURE=1 is in the
+// environment, every device and pinned host allocation of the library fails
+// as if memory were exhausted (without calling the allocator).
+bool alloc_failure_injected() {
+  const char *e = getenv("ALB_INJECT_ALLOC_FAILURE");
+  return e && e[0] == '1' && e[1] == 0;
+}
+
 template <class T>
 hipError_t dalloc(T **p, size_t count, size_t &bytes) {
+  if (alloc_failure_injected()) return hipErrorOutOfMemory;
   size_t b = sizeof(T) * std::max<size_t>(count, 1);
   hipError_t e = hipMalloc((void **)p, b);
   if (e == hipSuccess) bytes += b;
   return e;
+}
+
+// Pinned host memory (the control-block and table mirrors).
+template <class T>
+hipError_t palloc(T **p, size_t bytes) {
+  if (alloc_failure_injected()) return hipErrorOutOfMemory;
+  return hipHostMalloc((void **)p, bytes, hipHostMallocDefault);
 }
 
 alb_status ws_fill(Workspace *w, int32_t n, const Needs &nd) {
@@ -297,7 +313,7 @@ alb_status ws_fill(Workspace *w, int32_t n, const Needs &nd) {
   HIP_TRY(dalloc(&w->rank, (size_t)n, w->bytes));
   HIP_TRY(dalloc(&w->acc, (size_t)n, w->bytes));
   HIP_TRY(dalloc(&w->ctl, 1, w->bytes));
-  HIP_TRY(hipHostMalloc((void **)&w->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  HIP_TRY(palloc(&w->h_ctl, sizeof(Ctl)));
   for (auto &e : w->ev) HIP_TRY(hipEventCreate(&e));
   return ALB_OK;
 }
@@ -366,9 +382,9 @@ alb_status bws_fill(BatchWs *w, const BatchNeeds &nd) {
   HIP_TRY(dalloc(&w->word, (size_t)nd.labels, w->bytes));
   HIP_TRY(dalloc(&w->out32, (size_t)nd.labels, w->bytes));
   HIP_TRY(dalloc(&w->tab, kBatchTableBytes * (size_t)nd.nq, w->bytes));
-  HIP_TRY(hipHostMalloc((void **)&w->h_tab, kBatchTableBytes * (size_t)std::max(nd.nq, 1), hipHostMallocDefault));
+  HIP_TRY(palloc(&w->h_tab, kBatchTableBytes * (size_t)std::max(nd.nq, 1)));
   HIP_TRY(dalloc(&w->ctl, 1, w->bytes));
-  HIP_TRY(hipHostMalloc((void **)&w->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  HIP_TRY(palloc(&w->h_ctl, sizeof(Ctl)));
   for (auto &e : w->ev) HIP_TRY(hipEventCreate(&e));
   return ALB_OK;
 }
@@ -751,7 +767,8 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   } prof;
   if (a.profile && launch == ALB_LAUNCH_PERSISTENT) {
     const size_t nb = sizeof(uint32_t) * (size_t)kTimeline * kProfMembers;
-    HIP_TRY(hipMalloc((void **)&prof.p, nb));
+    size_t pb = 0;
+    HIP_TRY(dalloc(&prof.p, nb / sizeof(uint32_t), pb));
     HIP_TRY(hipMemsetAsync(prof.p, 0, nb, stream));
     a.prof_wg = prof.p;
   }
@@ -1037,10 +1054,21 @@ alb_status enqueue_batch(const BatchJob &j, BatchWs *ws, hipStream_t st) {
   return ALB_OK;
 }
 
+// The device window of the last persistent batch launch of this thread (see
+// alb::last_launch_window).
+struct LaunchWindow {
+  bool valid = false;
+  double begin_ms = 0, end_ms = 0;
+};
+thread_local LaunchWindow g_window;
+
 // After the stream reached the end of enqueue_batch: errors, host outputs, stats.
 alb_status finish_batch(alb_graph g, const BatchJob &j, BatchWs *ws, int32_t *const *outs, alb_stats *st,
                         hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
   const Ctl &c = *ws->h_ctl;
+  g_window.valid = c.t_begin != 0 && c.t_end >= c.t_begin;
+  g_window.begin_ms = (double)c.t_begin / (double)g->clock_khz;
+  g_window.end_ms = (double)c.t_end / (double)g->clock_khz;
   if (c.abort) return abort_error(c);
   if (c.overflow != 0xffffffffu)
     return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %u entries in round %u", j.a.qcap, c.overflow);
@@ -1062,6 +1090,7 @@ alb_status finish_batch(alb_graph g, const BatchJob &j, BatchWs *ws, int32_t *co
 
 alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
                      int32_t *const *outs, const int64_t *thresholds, const alb_options *user, alb_stats *st) {
+  g_window.valid = false;
   BatchJob j;
   alb_status s = prepare_batch(g, op, count, members, sources, outs, thresholds, user, j);
   if (s != ALB_OK) return s;
@@ -1972,6 +2001,13 @@ alb_status set_error(alb_status st, const char *fmt, ...) {
   va_end(ap);
   g_err = buf;
   return st;
+}
+
+bool last_launch_window(double *begin_ms, double *end_ms) {
+  if (!g_window.valid) return false;
+  *begin_ms = g_window.begin_ms;
+  *end_ms = g_window.end_ms;
+  return true;
 }
 
 alb_status batch_resident_workgroups(alb_graph g, int32_t algo, int32_t wg, int *out) {

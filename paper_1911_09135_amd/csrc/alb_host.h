@@ -15,4 +15,10 @@ int auto_grid(int64_t edges, int wg, int resident);
 // `algo` on g's device.
 alb_status batch_resident_workgroups(alb_graph g, int32_t algo, int32_t wg, int *out);
 
+// The device wall-clock window (ms, the device's own origin) of the last
+// persistent launch this thread completed through a batch call: when its
+// first workgroup joined and when it left its last round.  False if that
+// call failed or ran no persistent launch.
+bool last_launch_window(double *begin_ms, double *end_ms);
+
 }  // namespace alb

@@ -78,6 +78,9 @@ struct Ctl {
   // with Args::profile: wall-clock ticks summed over workgroups, per part of
   // the round (see kProf*)
   unsigned long long prof[8];
+  // persistent launch: device wall-clock ticks when its first member joined
+  // and when member 0 left the round loop
+  unsigned long long t_begin, t_end;
 };
 constexpr int kTimeline = 64;
 // With Args::prof_wg: edges each member workgroup processed in each of the

@@ -975,6 +975,7 @@ __device__ bool join_members(const Args &a, S &sm, Grid *gr) {
     if (member && t == 0) {
       unsigned long long seen = 1;
       uint64_t t_last = (uint64_t)wall_clock64();
+      st_relaxed(&c->t_begin, (unsigned long long)t_last);
       for (;;) {
         const unsigned long long cur = ld_relaxed(&c->members);
         if (cur >= (unsigned long long)gridDim.x) break;
@@ -1078,6 +1079,7 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     c->diag_round = 0;
     c->threshold_used = a.threshold;
     for (int k = 0; k < kProfParts; ++k) c->prof[k] = 0;
+    c->t_begin = c->t_end = 0;
     if (source >= 0 && op != OP_RECORD) ((int32_t *)a.q0)[0] = source;
   }
 }
@@ -1115,6 +1117,7 @@ __global__ void k_init_batch(Args a, int op) {
     c->diag_round = 0;
     c->threshold_used = a.threshold;
     for (int k = 0; k < kProfParts; ++k) c->prof[k] = 0;
+    c->t_begin = c->t_end = 0;
   }
 }
 
@@ -1224,6 +1227,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
   if (gr.id == 0 && threadIdx.x == 0) {
     st_relaxed(&a.ctl->rounds, (uint32_t)r);
     st_relaxed(&a.ctl->threshold_used, (long long)a.threshold);
+    st_relaxed(&a.ctl->t_end, (unsigned long long)wall_clock64());
   }
   flush_stats<B, Op>(acc, sm, a.ctl);
 }

@@ -70,6 +70,10 @@ struct alb_server_s {
   bool stop = false;
   int running = 0;  // requests dispatched and not yet completed
   alb_server_stats st{};
+  Clock::time_point t_created = Clock::now();
+  std::vector<alb_batch_record> log;  // ring of the last kLogSize batches
+  size_t log_next = 0;
+  static constexpr size_t kLogSize = 4096;
 
   void complete(Request &r, int32_t status, Clock::time_point now) {
     r.state = kDone;
@@ -170,7 +174,21 @@ struct alb_server_s {
       const Clock::time_point t0 = Clock::now();
       const int32_t status = execute(lane, algo, alone, edges, mb, src, outs);
       const Clock::time_point t1 = Clock::now();
+      alb_batch_record rec{};
+      rec.lane = lane;
+      rec.algo = algo;
+      rec.batch_size = (int32_t)batch.size();
+      rec.status = status;
+      if (cfg.executor || !alb::last_launch_window(&rec.device_begin_ms, &rec.device_end_ms))
+        rec.device_begin_ms = rec.device_end_ms = 0;
+      rec.host_begin_ms = ms_between(t_created, t0);
+      rec.host_end_ms = ms_between(t_created, t1);
       lk.lock();
+      if (log.size() < kLogSize)
+        log.push_back(rec);
+      else
+        log[log_next] = rec;
+      log_next = (log_next + 1) % kLogSize;
       st.busy_ms += ms_between(t0, t1);
       for (uint64_t t : batch) {
         Request &r = reqs[t];
@@ -382,6 +400,19 @@ alb_status alb_server_stats_get(alb_server s, alb_server_stats *st) {
   *st = s->st;
   st->pending = (int64_t)s->pending.size();
   st->running = s->running;
+  return ALB_OK;
+}
+
+alb_status alb_server_batch_log(alb_server s, int32_t max, alb_batch_record *out, int32_t *count) {
+  if (!s || !count || (max > 0 && !out)) return set_error(ALB_E_INVAL, "NULL argument");
+  if (max < 0) return set_error(ALB_E_INVAL, "max must be >= 0");
+  std::lock_guard<std::mutex> lk(s->mu);
+  const size_t have = s->log.size();
+  const size_t k = std::min(have, (size_t)max);
+  // oldest of the most recent k: the ring's write position minus k
+  const size_t start = (s->log_next + have - k) % std::max<size_t>(have, 1);
+  for (size_t i = 0; i < k; ++i) out[i] = s->log[(start + i) % have];
+  *count = (int32_t)k;
   return ALB_OK;
 }
 

@@ -1,0 +1,82 @@
+"""Allocation failure, forced from the host: while ALB_INJECT_ALLOC_FAILURE=1
+is set, every device and pinned allocation the library makes fails as if
+memory were exhausted.  Graph creation, a single query's first workspace, a
+batch's workspace and a captured plan must then return ALB_E_NOMEM (stats
+zeroed, nothing left busy), and once the variable is cleared the same calls
+succeed with the oracle's results."""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def alb():
+    from paper_1911_09135_amd import alb as m
+
+    return m
+
+
+class inject:
+    def __enter__(self):
+        os.environ["ALB_INJECT_ALLOC_FAILURE"] = "1"
+
+    def __exit__(self, *exc):
+        os.environ.pop("ALB_INJECT_ALLOC_FAILURE", None)
+
+
+def test_graph_creation_fails_cleanly(alb):
+    g = gg.rmat(10, 16, seed=3).with_weights(4)
+    with inject():
+        with pytest.raises(alb.AlbError) as ei:
+            alb.Graph(g.off, g.col, g.w)
+    assert ei.value.status == alb.ALB_E_NOMEM
+    with alb.Graph(g.off, g.col, g.w) as dg:
+        d, _ = alb.sssp(dg, 0)
+    assert np.array_equal(d, oracle.sssp(g, 0))
+
+
+def test_first_workspace_fails_then_recovers(alb):
+    g = gg.rmat(11, 16, seed=5).with_weights(6)
+    with alb.Graph(g.off, g.col, g.w) as dg:
+        for call in (lambda: alb.sssp(dg, 0), lambda: alb.bfs(dg, 0), lambda: alb.pagerank(dg, 0.85, 5)):
+            with inject():
+                with pytest.raises(alb.AlbError) as ei:
+                    call()
+            assert ei.value.status == alb.ALB_E_NOMEM
+        # a larger worklist than the cached workspace holds needs a new one
+        d0, _ = alb.sssp(dg, 0)
+        with inject():
+            with pytest.raises(alb.AlbError) as ei:
+                alb.sssp(dg, 0, worklist_capacity=g.n + g.m + 7, dedup=False)
+        assert ei.value.status == alb.ALB_E_NOMEM
+        d1, st = alb.sssp(dg, 0, worklist_capacity=g.n + g.m + 7, dedup=False)
+        assert np.array_equal(d0, oracle.sssp(g, 0)) and np.array_equal(d1, d0)
+        assert st["rounds"] > 0
+        lv, _ = alb.bfs(dg, 0)
+        assert np.array_equal(lv, oracle.bfs(g, 0))
+
+
+def test_batch_and_plan_fail_then_recover(alb):
+    gs_host = [gg.rmat(9, 16, seed=7).with_weights(8), gg.rmat(10, 16, seed=9).with_weights(10)]
+    gs = alb.GraphSet(gs_host)
+    try:
+        members, sources = [0, 1, 1], [0, 0, 3]
+        with inject():
+            with pytest.raises(alb.AlbError) as ei:
+                alb.sssp_batch(gs, members, sources)
+            assert ei.value.status == alb.ALB_E_NOMEM
+            with pytest.raises(alb.AlbError) as ei:
+                alb.BatchPlan(gs, "sssp", members, sources)
+            assert ei.value.status == alb.ALB_E_NOMEM
+        outs, _ = alb.sssp_batch(gs, members, sources)
+        for o, m, s in zip(outs, members, sources):
+            assert np.array_equal(o, oracle.sssp(gs_host[m], s))
+    finally:
+        gs.close()
+

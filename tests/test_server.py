@@ -223,3 +223,22 @@ def test_bad_requests(alb):
         alb.Server(None, lanes=1)  # no graph and no executor
     with pytest.raises(alb.AlbError):
         alb.Server(None, lanes=17, executor=f, member_vertices=[10])
+
+
+def test_batch_log_records_every_batch(alb):
+    f = Fake(delay=0.02)
+    with alb.Server(None, lanes=2, max_batch=4, executor=f, member_vertices=[10, 20]) as srv:
+        tickets = [srv.submit("bfs" if i % 2 else "sssp", i % 2, 1) for i in range(24)]
+        for t in tickets:
+            srv.wait(t)
+        log = srv.batch_log()
+        assert srv.batch_log(3) == log[-3:]
+        assert srv.batch_log(0) == []
+    assert len(log) == len(f.batches)
+    assert sum(r["batch_size"] for r in log) == 24
+    assert all(r["device_begin_ms"] == 0 and r["status"] == 0 for r in log)  # no device with an executor
+    assert all(0 <= r["host_begin_ms"] <= r["host_end_ms"] for r in log)
+    assert {r["lane"] for r in log} == {0, 1}
+    # the two lanes ran batches at the same time on the host
+    assert any(a["lane"] != b["lane"] and a["host_begin_ms"] < b["host_end_ms"] and
+               b["host_begin_ms"] < a["host_end_ms"] for a in log for b in log)

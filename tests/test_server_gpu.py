@@ -88,3 +88,23 @@ def test_small_budget_splits_batches(alb, gset, members):
             out, info = srv.wait(t)
             assert info["batch_size"] <= 2
             assert np.array_equal(out, reference(members, a, m, s))
+
+
+def test_lanes_overlap_on_the_device(alb, gset, members):
+    """Batches of two lanes run on the device at the same time: their
+    persistent launches' device windows (first workgroup joined to last
+    round left, on the device's wall clock) intersect; every result is still
+    the oracle's."""
+    reqs = [("sssp", 0, int(s)) for s in gg.query_sources([members[0]], 64, seed=21)[1]]
+    with alb.Server(gset, lanes=2, max_batch=4, whole_device_when_alone=False) as srv:
+        tickets = [srv.submit(*r) for r in reqs]
+        for t, (a, m, s) in zip(tickets, reqs):
+            out, _ = srv.wait(t)
+            assert np.array_equal(out, reference(members, a, m, s))
+        log = srv.batch_log()
+    assert len(log) >= 2 and {r["lane"] for r in log} == {0, 1}
+    assert all(0 < r["device_begin_ms"] <= r["device_end_ms"] for r in log)
+    pairs = [(a, b) for a in log for b in log if a["lane"] == 0 and b["lane"] == 1 and
+             a["device_begin_ms"] < b["device_end_ms"] and b["device_begin_ms"] < a["device_end_ms"]]
+    print("batches %d, overlapping lane pairs %d" % (len(log), len(pairs)))
+    assert pairs, log
