@@ -179,6 +179,28 @@ alb_status alb_bfs(alb_graph g, int32_t source, int32_t *level, const alb_option
  * (atomic minimum).  dist[v] = shortest distance, INT32_MAX if unreachable. */
 alb_status alb_sssp(alb_graph g, int32_t source, int32_t *dist, const alb_options *opt, alb_stats *stats);
 
+/* alb_sssp for callers that cannot allocate memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation).  Same
+ * result, options and kernels as alb_sssp, but the per-call workspace
+ * (worklists, huge list, chunk index, barrier words, 64-bit label words and
+ * the control block: about 32 bytes per vertex with the default worklist
+ * capacity) lives in one device array of 192 MiB that the library holds on
+ * each GPU it runs on until the process ends; the call allocates no device or
+ * pinned memory and records no event.
+ *  - dist: DEVICE pointer to n int32 (whatever options.out_on_device says),
+ *    written in stream order on options.stream (NULL: the library's stream);
+ *    the call returns after the stream has finished the query.
+ *  - A graph whose workspace does not fit (n above ~6.2M vertices at the
+ *    default capacity, less with a larger options.worklist_capacity or
+ *    dedup = 0) is refused with ALB_E_NOMEM before any device work.
+ *  - Every call on one GPU uses the same array, and it keeps the last call's
+ *    contents (the call initialises what it reads).  Calls from one process
+ *    on one GPU are serialised by a host lock; work that overlapped on the
+ *    device (another process, or a kernel given this memory) would race.
+ *  - stats: as alb_sssp, except that device_ms and kernel_ms are 0 (the call
+ *    is not timed). */
+alb_status alb_sssp_noalloc(alb_graph g, int32_t source, int32_t *dist, const alb_options *opt, alb_stats *stats);
+
 /* Connected components, the paper's cc application (Section 5, where it is
  * listed among the push-style operators): weakly connected components by
  * min-label propagation, each active vertex offering its label to its

@@ -132,6 +132,7 @@ _sig = {
                         ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "alb_bfs": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_sssp": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_sssp_noalloc": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_cc": ([_vp, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_pagerank": ([_vp, _f32, _i32, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_kcore": ([_vp, _i32, _vp, _POpt, _PSt], ctypes.c_int),
@@ -600,6 +601,14 @@ def bfs(g: Graph, source: int, out=None, **opts):
 
 def sssp(g: Graph, source: int, out=None, **opts):
     return _run(_lib.alb_sssp, g, out, np.int32, opts, int(source))
+
+
+def sssp_noalloc(g: Graph, source: int, out, **opts):
+    """alb_sssp_noalloc: SSSP with the workspace in the library's device
+    scratch array; `out` must be a contiguous int32 CUDA tensor of n."""
+    if isinstance(out, np.ndarray) or out is None:
+        raise ValueError("sssp_noalloc writes a device tensor (out)")
+    return _run(_lib.alb_sssp_noalloc, g, out, np.int32, opts, int(source))
 
 
 def cc(g: Graph, out=None, **opts):

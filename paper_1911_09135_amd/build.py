@@ -21,7 +21,7 @@ DEVICE = ["--offload-arch=%s" % ARCH, "-Xclang", "-target-feature", "-Xclang", "
 # extra device-code defines, e.g. ALB_DEFINES="-DALB_WAVES_PER_EU=6"
 DEVICE += os.environ.get("ALB_DEFINES", "").split()
 
-SOURCES = [("alb_kernels.hip", DEVICE), ("alb_api.cpp", []), ("alb_server.cpp", [])]
+SOURCES = [("alb_kernels.hip", DEVICE), ("alb_noalloc.hip", DEVICE), ("alb_api.cpp", []), ("alb_server.cpp", [])]
 
 
 # Sanitizer builds of the host runtime (alb_api.cpp, alb_server.cpp): the

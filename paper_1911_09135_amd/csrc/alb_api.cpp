@@ -626,8 +626,10 @@ void print_skew(const uint32_t *d_counts, int rounds, int members) {
 void fill_stats(alb_stats *st, const Ctl &c, int rounds, int launches, int64_t T, int64_t threshold, hipEvent_t e0,
                 hipEvent_t e1, hipEvent_t e2) {
   float ms_all = 0.f, ms_k = 0.f;
-  (void)hipEventElapsedTime(&ms_all, e0, e2);
-  (void)hipEventElapsedTime(&ms_k, e1, e2);
+  if (e0 && e1 && e2) {  // (untimed without events)
+    (void)hipEventElapsedTime(&ms_all, e0, e2);
+    (void)hipEventElapsedTime(&ms_k, e1, e2);
+  }
   st->rounds = rounds;
   st->kernel_launches = launches;
   st->launched_threads = T;
@@ -641,8 +643,30 @@ void fill_stats(alb_stats *st, const Ctl &c, int rounds, int launches, int64_t T
   st->kernel_ms = ms_k;
 }
 
+// Worklist capacity and chunk-index entries a call needs, and whether it
+// suppresses duplicate pushes.
+Needs job_needs(alb_graph g, const Job &job, const alb_options &o, bool *dedup_out) {
+  bool dedup = false;
+  if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);
+  uint64_t qcap;
+  if (o.worklist_capacity > 0)
+    qcap = (uint64_t)o.worklist_capacity;
+  else if (job.op == OP_BFS || dedup || job.op == OP_PR || job.op == OP_PR_PULL || job.op == OP_KCORE)
+    qcap = (uint64_t)g->n;
+  else
+    qcap = (uint64_t)g->n + (uint64_t)g->m;
+  qcap = std::max<uint64_t>(qcap, std::max<uint64_t>(job.qcap_min, job.nfront0));
+  qcap = std::max<uint64_t>(qcap, 1);
+  if (qcap > 0xfffffffeULL) qcap = 0xfffffffeULL;
+  *dedup_out = dedup;
+  return Needs{(uint32_t)qcap, hint_entries(qcap, dedup_bound(job.op, dedup, g->m), g->max_deg)};
+}
+
+// `fixed`: a workspace laid out by the caller (alb_sssp_noalloc's scratch):
+// no workspace is taken from the pool, no event is recorded and nothing is
+// allocated; its h_ctl may be pageable host memory.
 alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_out, alb_stats *st, WsGuard &guard,
-                   RunOut &ro) {
+                   RunOut &ro, Workspace *fixed = nullptr) {
   HIP_TRY(hipSetDevice(g->device));
   const hipStream_t stream = o.stream ? (hipStream_t)o.stream : g->stream;
   ro.stream = stream;
@@ -682,24 +706,18 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
                                       : default_small_threshold(job.op, threshold);
 
   bool dedup = false;
-  if (job.op == OP_SSSP || job.op == OP_CC) dedup = (o.dedup != 0);
-  uint64_t qcap;
-  if (o.worklist_capacity > 0)
-    qcap = (uint64_t)o.worklist_capacity;
-  else if (job.op == OP_BFS || dedup || job.op == OP_PR || job.op == OP_PR_PULL || job.op == OP_KCORE)
-    qcap = (uint64_t)g->n;
-  else
-    qcap = (uint64_t)g->n + (uint64_t)g->m;
-  qcap = std::max<uint64_t>(qcap, std::max<uint64_t>(job.qcap_min, job.nfront0));
-  qcap = std::max<uint64_t>(qcap, 1);
-  if (qcap > 0xfffffffeULL) qcap = 0xfffffffeULL;
-
-  Needs nd{(uint32_t)qcap, hint_entries(qcap, dedup_bound(job.op, dedup, g->m), g->max_deg)};
-  Workspace *ws = nullptr;
-  alb_status s = ws_acquire(g, nd, &ws);
-  if (s != ALB_OK) return s;
-  guard.g = g;
-  guard.w = ws;
+  const Needs nd = job_needs(g, job, o, &dedup);
+  const uint64_t qcap = nd.qcap;
+  Workspace *ws = fixed;
+  if (fixed) {
+    if (fixed->qcap < nd.qcap || fixed->hint_cap < nd.hint_cap || fixed->n < g->n)
+      return fail(ALB_E_INVAL, "internal: the fixed workspace is smaller than the call needs");
+  } else {
+    alb_status s = ws_acquire(g, nd, &ws);
+    if (s != ALB_OK) return s;
+    guard.g = g;
+    guard.w = ws;
+  }
   ro.ws = ws;
   ro.qcap = (uint32_t)qcap;
 
@@ -730,7 +748,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.round = 0;
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
   a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);  // 10 us without a new member
-  a.profile = getenv("ALB_TIMELINE") ? 1 : 0;
+  a.profile = (getenv("ALB_TIMELINE") && !fixed) ? 1 : 0;
   if (job.op == OP_BFS) a.level = dev_out ? (int32_t *)dev_out : ws->labels;
   if (job.op == OP_SSSP || job.op == OP_CC) {
     a.word = ws->word;
@@ -772,14 +790,14 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     HIP_TRY(hipMemsetAsync(prof.p, 0, nb, stream));
     a.prof_wg = prof.p;
   }
-  HIP_TRY(hipEventRecord(ws->ev[0], stream));
+  if (ws->ev[0]) HIP_TRY(hipEventRecord(ws->ev[0], stream));
   if (job.op == OP_PR_PULL) {
     HIP_TRY(launch_init(OP_PR, a, -1, job.nfront0, stream));
     HIP_TRY(launch_pull_prepare(a, stream));
   } else {
     HIP_TRY(launch_init(job.op, a, job.source, job.nfront0, stream));
   }
-  HIP_TRY(hipEventRecord(ws->ev[1], stream));
+  if (ws->ev[1]) HIP_TRY(hipEventRecord(ws->ev[1], stream));
 
   int launches = 0;
   int rounds = 0;
@@ -818,7 +836,7 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     }
   }
   if (job.op == OP_SSSP || job.op == OP_CC || job.op == OP_KCORE) HIP_TRY(launch_finish(job.op, a, stream));
-  HIP_TRY(hipEventRecord(ws->ev[2], stream));
+  if (ws->ev[2]) HIP_TRY(hipEventRecord(ws->ev[2], stream));
   HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   const Ctl &c = *ws->h_ctl;
@@ -1587,6 +1605,71 @@ alb_status alb_sssp(alb_graph g, int32_t source, int32_t *dist, const alb_option
   job.nfront0 = 1;
   job.max_rounds = g->n + 1;
   s = traverse(g, job, dist, sizeof(int32_t), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+// alb_sssp on the device scratch array: the same job and kernels, with the
+// workspace carved from the scratch and the control block read back into a
+// host stack copy.  One host mutex per device keeps calls from overlapping.
+alb_status alb_sssp_noalloc(alb_graph g, int32_t source, int32_t *dist, const alb_options *opt, alb_stats *stats) {
+  zero_stats(stats);
+  alb_status s = check_graph(g);
+  if (s != ALB_OK) return s;
+  if (!dist) return fail(ALB_E_INVAL, "dist is NULL");
+  if (!g->weighted) return fail(ALB_E_INVAL, "alb_sssp_noalloc needs a graph created with weights");
+  if (source < 0 || source >= g->n) return fail(ALB_E_INVAL, "source %d out of range [0, %d)", source, g->n);
+  alb_options o;
+  if ((s = resolve_options(opt, o)) != ALB_OK) return s;
+  Job job;
+  job.op = OP_SSSP;
+  job.source = source;
+  job.nfront0 = 1;
+  job.max_rounds = g->n + 1;
+  bool dedup = false;
+  const Needs nd = job_needs(g, job, o, &dedup);
+  // the workspace, each part on a 256-byte boundary of the scratch
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t p = at;
+    at += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t p_q0 = take(sizeof(int32_t) * (size_t)nd.qcap);
+  const size_t p_q1 = take(sizeof(int32_t) * (size_t)nd.qcap);
+  const size_t p_rec = take(sizeof(int4) * (size_t)nd.qcap);
+  const size_t p_hint = take(sizeof(int2) * (size_t)nd.hint_cap);
+  const size_t p_bar = take(sizeof(unsigned long long) * kBarWords);
+  const size_t p_word = take(sizeof(unsigned long long) * (size_t)g->n);
+  const size_t p_ctl = take(sizeof(Ctl));
+  if (at > kNoAllocScratchBytes)
+    return fail(ALB_E_NOMEM,
+                "alb_sssp_noalloc: this graph and worklist capacity need %zu bytes of device scratch, the library "
+                "holds %zu (n = %d, worklist capacity %u)",
+                at, kNoAllocScratchBytes, g->n, nd.qcap);
+  if (g->device < 0 || g->device >= 64) return fail(ALB_E_DEVICE, "device %d out of range", g->device);
+  static std::mutex dev_mu[64];
+  std::lock_guard<std::mutex> lk(dev_mu[g->device]);
+  HIP_TRY(hipSetDevice(g->device));
+  void *base = nullptr;
+  HIP_TRY(noalloc_scratch(g->device, &base));
+  unsigned char *b = (unsigned char *)base;
+  Workspace ws;  // views into the scratch (never released)
+  ws.n = g->n;
+  ws.qcap = nd.qcap;
+  ws.hint_cap = nd.hint_cap;
+  ws.q0 = (int32_t *)(b + p_q0);
+  ws.q1 = (int32_t *)(b + p_q1);
+  ws.huge_rec = (int4 *)(b + p_rec);
+  ws.hint = (int2 *)(b + p_hint);
+  ws.bar = (unsigned long long *)(b + p_bar);
+  ws.word = (unsigned long long *)(b + p_word);
+  ws.ctl = (Ctl *)(b + p_ctl);
+  Ctl host_ctl;
+  ws.h_ctl = &host_ctl;
+  WsGuard guard{nullptr, nullptr};
+  RunOut ro;
+  s = run_job(g, job, o, dist, stats, guard, ro, &ws);
   if (s != ALB_OK) zero_stats(stats);
   return s;
 }

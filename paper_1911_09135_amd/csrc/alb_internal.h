@@ -47,6 +47,11 @@ constexpr int kAdaptiveSmall = 64;
 constexpr int kHintMaxShift = 20;
 // Queries in one batch launch (the output kernel puts one query on each grid row).
 constexpr int32_t kMaxBatch = 65535;
+// Bytes of the per-GPU device scratch array that alb_sssp_noalloc carves its
+// workspace from (worklists, huge list, chunk index, barrier words, label
+// words, control block): about 32 bytes per vertex, so graphs of up to ~6.2M
+// vertices with the default worklist capacity.
+constexpr size_t kNoAllocScratchBytes = (size_t)192 << 20;
 
 // Per-call control block in device memory.  Counters rotate by round so that
 // one round can clear the counter two rounds ahead without a separate launch.
@@ -168,5 +173,8 @@ hipError_t batch_occupancy(OpKind op, int wg, int *blocks_per_cu);
 hipError_t launch_init_batch(OpKind op, const Args &a, hipStream_t s);
 hipError_t launch_batch(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_finish_batch(OpKind op, const Args &a, int32_t max_n, hipStream_t s);
+// Device address of this GPU's scratch array (kNoAllocScratchBytes, 256-byte
+// aligned), looked up on the first call for `device` and kept (alb_noalloc.hip).
+hipError_t noalloc_scratch(int device, void **ptr);
 
 }  // namespace alb
