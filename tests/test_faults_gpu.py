@@ -80,3 +80,17 @@ def test_batch_and_plan_fail_then_recover(alb):
     finally:
         gs.close()
 
+
+def test_noalloc_entry_point_needs_no_allocation(alb):
+    import torch
+
+    g = gg.rmat(12, 16, seed=1).with_weights(2)
+    with alb.Graph(g.off, g.col, g.w) as dg:
+        out = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+        alb.sssp_noalloc(dg, 0, out)  # first call on this device: the scratch address is looked up
+        out.fill_(-7)
+        with inject():
+            _, st = alb.sssp_noalloc(dg, 0, out, threshold=64)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.sssp(g, 0))
+        assert st["huge_vertices"] > 0
