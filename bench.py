@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--tune", action="store_true", help="batch: also run with autotuned settings")
     ap.add_argument("--random-probe", action="store_true",
                     help="only measure plain random 8-byte gathers (the access pattern of the label reads)")
+    ap.add_argument("--relax-probe", action="store_true",
+                    help="only measure the edge-relaxation loop alone over RMAT-22's edges, labels in one array "
+                         "or in eight per-XCD destination slices (what a label layout can gain)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (calibrates HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
@@ -112,6 +115,8 @@ def main():
 
     if args.random_probe:
         return random_probe(args)
+    if args.relax_probe:
+        return relax_probe(args)
 
     import graphgen as gg
     from paper_1911_09135_amd import alb
@@ -392,6 +397,90 @@ def random_probe(args):
                                "stream_gbs": round(16 * n_idx / ms / 1e6, 1)}
         log("table %d MB: %.3f ms, %.2f G random reads/s" % (words * 8 >> 20, ms, n_idx / ms / 1e6))
     print(json.dumps({"random_probe": res, "indices": n_idx}), flush=True)
+
+
+def relax_probe(args):
+    """The SSSP edge-relaxation loop alone (paper_1911_09135_amd/csrc/
+    probe_relax.hip): every edge of RMAT-22 once in CSR order, balanced, with
+    no inspection, bins, pushes or barriers; 8-byte label words with an atomic
+    minimum (the traversal's), 8-byte gathers only, and the same with 4-byte
+    labels; labels in one array ("flat") or split into eight destination
+    slices with XCD x relaxing slice x ("sliced": vertex v goes to slice
+    s(v) = the XOR of v's 3-bit digits, which balances RMAT's skewed ids, at
+    index s(v) * ceil(n / 8) + (v >> 3)).  Labels start uniform in [0, 1000)
+    and candidates are w + 880, so about 7 % of edges lower their label, as
+    in the traversal.  Device time per launch (median of 5), G edges/s."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    from paper_1911_09135_amd import build
+
+    lib_path = build.PROBE_LIB
+    if not os.path.exists(lib_path):
+        build.build_probe()
+    lib = ctypes.CDLL(lib_path)
+    vp = ctypes.c_void_p
+    lib.alb_probe_relax.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int, ctypes.c_int32, vp,
+                                    vp, ctypes.c_int, vp]
+    g = gg.workload("rmat22w")
+    n, m = g.n, g.m
+    v = np.arange(n, dtype=np.int64)
+    s_of = np.zeros(n, np.int64)
+    y = v.copy()
+    while y.any():
+        s_of ^= y & 7
+        y >>= 3
+    q = (n + 7) // 8
+    idx = s_of * q + (v >> 3)  # a bijection onto [0, 8q): v = 8 (i mod q) + (s ^ digits-xor of (i mod q))
+    col = g.col.astype(np.int64)
+    order = np.argsort(s_of[col], kind="stable")
+    cnt = np.bincount(s_of[col], minlength=8)
+    list_off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    lab0 = np.random.default_rng(5).integers(0, 1000, n).astype(np.int64)
+    dev = "cuda"
+    flat = (torch.from_numpy(g.col.astype(np.int32)).to(dev), torch.from_numpy(g.w.astype(np.int32)).to(dev))
+    sliced = (torch.from_numpy(idx[col[order]].astype(np.int32)).to(dev),
+              torch.from_numpy(g.w[order].astype(np.int32)).to(dev))
+    lo_d = torch.from_numpy(list_off).to(dev)
+    perm = np.zeros(8 * q, np.int64)
+    perm[idx] = lab0
+    lab = {(0, 8): torch.from_numpy(lab0 << 32).to(dev), (0, 4): torch.from_numpy(lab0.astype(np.int32)).to(dev),
+           (1, 8): torch.from_numpy(perm << 32).to(dev), (1, 4): torch.from_numpy(perm.astype(np.int32)).to(dev)}
+    claim = torch.zeros(8 * 64 * 32, dtype=torch.int64, device=dev)
+    lowered = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    names = {0: "8-byte label, atomic min", 1: "8-byte gather only", 2: "4-byte label, atomic min",
+             3: "4-byte gather only"}
+    res = {}
+    for variant in (0, 1, 2, 3):
+        for sl in (0, 1):
+            src = lab[(sl, 8 if variant < 2 else 4)]
+            work = src.clone()
+            c, w = sliced if sl else flat
+            ts = []
+            for it in range(7):
+                work.copy_(src)
+                claim.zero_()
+                lowered.zero_()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                rc = lib.alb_probe_relax(variant, c.data_ptr(), w.data_ptr(), work.data_ptr(), m, lo_d.data_ptr(),
+                                         sl, 880, claim.data_ptr(), lowered.data_ptr(), 1024, stream)
+                e1.record()
+                torch.cuda.synchronize()
+                if rc != 0:
+                    raise RuntimeError("probe launch failed: %d" % rc)
+                if it >= 2:
+                    ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            key = "%s, %s" % (names[variant], "sliced" if sl else "flat")
+            res[key] = {"ms": round(ms, 4), "g_edges_per_s": round(m / ms / 1e6, 1), "lowered": int(lowered.item())}
+            log("%-40s %.4f ms  %.1f G edges/s" % (key, ms, m / ms / 1e6))
+    print(json.dumps({"relax_probe": res, "graph": "rmat22_ef16_w1-100", "edges": m,
+                      "slice_edge_shares": [round(float(x) / m, 4) for x in cnt]}), flush=True)
 
 
 def bench_batch(args, alb, gg, emit=True):

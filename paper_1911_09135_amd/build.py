@@ -74,6 +74,21 @@ def build(verbose: bool = False, sanitize: str = "") -> str:
     return lib
 
 
+PROBE_LIB = os.path.join(HERE, "libalb_probe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The measurement probe of the edge-relaxation loop (bench.py --relax-probe),
+    a separate library: it is not part of the traversal."""
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + COMMON + DEVICE + ["-shared", os.path.join(CSRC, "probe_relax.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 if __name__ == "__main__":
     san = ""
     for a in sys.argv[1:]:
