@@ -82,7 +82,8 @@ def main():
                          "requests over 32 graphs through the serving loop")
     ap.add_argument("--requests", type=int, default=5000, help="serve: requests per arrival rate")
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates per second")
-    ap.add_argument("--tune", action="store_true", help="batch: also run with autotuned settings")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch: also run with autotuned per-query settings (always in the default line's summary)")
     ap.add_argument("--random-probe", action="store_true",
                     help="only measure plain random 8-byte gathers (the access pattern of the label reads)")
     ap.add_argument("--relax-probe", action="store_true",
@@ -93,6 +94,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: leave out the Zipf-2^24, batch and serving summaries")
     ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each summary measurement")
+    ap.add_argument("--parts", default="bfs,pagerank,pull,cc,kcore,grid",
+                    help="zipf24: the parts to run (profiling runs take one)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -128,7 +131,7 @@ def main():
         bench_serve(args, alb, gg)
         return
     if args.workload == "zipf24":
-        bench_zipf24(args, alb, gg, cpu=not args.no_cpu)
+        bench_zipf24(args, alb, gg, cpu=not args.no_cpu, parts=args.parts)
         return
 
     t = time.perf_counter()
@@ -549,25 +552,32 @@ def bench_batch(args, alb, gg, emit=True):
     log("plan: %.3f ms/step" % (1e3 * psec / args.steps))
 
     tuned = None
-    if args.tune:
+    if args.tune or not emit:
+        # the batch autotuner with per-query thresholds and TWC cutoffs: its
+        # best single setting of the grid beside its per-query result
         t0 = time.perf_counter()
-        topts, thr = alb.autotune_batch(gset, "sssp", members, sources)
+        topts, tuning, uniform_ms, tuned_ms = alb.autotune_batch_tuned(gset, "sssp", members, sources)
         tune_s = time.perf_counter() - t0
+        tuned_outs = [torch.empty_like(o) for o in outs]
         for _ in range(args.warmup):
-            alb.sssp_batch(gset, members, sources, thresholds=thr, outs=outs, **topts)
+            alb.sssp_batch_tuned(gset, members, sources, tuning, outs=tuned_outs, **topts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            _, tst = alb.sssp_batch(gset, members, sources, thresholds=thr, outs=outs, **topts)
+            _, tst = alb.sssp_batch_tuned(gset, members, sources, tuning, outs=tuned_outs, **topts)
         torch.cuda.synchronize()
         tsec = time.perf_counter() - t0
-        vals, cnt = np.unique(thr, return_counts=True)
+        settings = {}
+        for t in tuning:
+            key = "t=%d,wave=%d,wg=%d" % t
+            settings[key] = settings.get(key, 0) + 1
         tuned = {"value": round(args.steps * q / tsec, 1), "unit": "queries/s",
                  "ms_per_step": round(1e3 * tsec / args.steps, 4), "tuning_s": round(tune_s, 2),
-                 "wg_size": topts["wg_size"], "thresholds": {str(int(v)): int(c) for v, c in zip(vals, cnt)},
-                 "kernel_ms": round(tst["kernel_ms"], 4)}
-        log("autotuned: %.3f ms/step (tuning %.1fs), wg %d, thresholds %s" % (
-            1e3 * tsec / args.steps, tune_s, topts["wg_size"], tuned["thresholds"]))
+                 "wg_size": topts["wg_size"], "settings": settings, "kernel_ms": round(tst["kernel_ms"], 4),
+                 "tuner_best_uniform_ms": round(uniform_ms, 4), "tuner_per_query_ms": round(tuned_ms, 4),
+                 "same_result": all(bool(torch.equal(a, b)) for a, b in zip(outs, tuned_outs))}
+        log("autotuned: %.3f ms/step (tuning %.1fs), wg %d, best uniform %.3f ms, per-query %.3f ms, %s" % (
+            1e3 * tsec / args.steps, tune_s, topts["wg_size"], uniform_ms, tuned_ms, settings))
 
     def one_at_a_time(lat):
         for i in range(q):
@@ -634,7 +644,7 @@ def bench_batch(args, alb, gg, emit=True):
     return res
 
 
-def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True):
+def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True, parts=None):
     """The extreme-skew graph: Zipf(1.9) out-degrees capped at 4,194,304,
     n = 2^24 (~372M edges).  BFS from the highest-degree vertex, CC and k-core
     (k = 8, 32) on the symmetrised graph, PageRank (0.85, 50 iterations) by
@@ -659,6 +669,9 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True):
     def rates(b, ms):
         return {"achieved_gbs": round(b / ms / 1e6, 1), "frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
+    parts = set((parts or "bfs,pagerank,pull,cc,kcore,grid").split(","))
+    kcore = kcore and "kcore" in parts
+    grid = grid and "grid" in parts
     res = {}
     t = time.perf_counter()
     g = gg.workload("zipf24")
@@ -668,8 +681,9 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True):
     dg = alb.Graph(g.off, g.col)
     out = torch.empty(g.n, dtype=torch.int32, device="cuda")
     alb_opts = {} if args.threshold is None else {"threshold": args.threshold}
+    modes = (("alb", alb_opts),) if args.only_alb else (("alb", alb_opts), ("twc_only", {"mode": "twc"}))
     levels = None
-    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+    for label, opts in modes if "bfs" in parts else ():
         ms, st = timed(alb.bfs, dg, out, opts, src)
         lv = out.cpu().numpy()
         if levels is None:
@@ -679,11 +693,15 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True):
         res.setdefault("bfs", {})[label] = dict({"kernel_ms": round(ms, 4), "gteps": round(m_r / ms / 1e6, 3),
                                                  "huge_vertices": st["huge_vertices"]}, **rates(b, ms))
         log("bfs %s: %.3f ms" % (label, ms))
-    res["bfs"]["twc_same_result"] = bool(np.array_equal(lv, levels))
-    res["bfs"]["alb_over_twc"] = round(res["bfs"]["twc_only"]["kernel_ms"] / res["bfs"]["alb"]["kernel_ms"], 2)
-    m_reached = int(deg[levels < alb.INF].sum())
+    m_reached = None
+    if "bfs" in parts:
+        if not args.only_alb:
+            res["bfs"]["twc_same_result"] = bool(np.array_equal(lv, levels))
+            res["bfs"]["alb_over_twc"] = round(res["bfs"]["twc_only"]["kernel_ms"] / res["bfs"]["alb"]["kernel_ms"],
+                                               2)
+        m_reached = int(deg[levels < alb.INF].sum())
     cpu_line = None
-    if cpu:
+    if cpu and "bfs" in parts:
         import oracle
 
         saved = os.sched_getaffinity(0)
@@ -704,31 +722,37 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True):
                               "and source, %.2f s in all" % (reps, cpu_s)}
         log("cpu oracle bfs: %.2f s per query" % (cpu_s / reps))
     outf = torch.empty(g.n, dtype=torch.float32, device="cuda")
-    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+    push_rank = None
+    for label, opts in modes if "pagerank" in parts else ():
         ms, st = timed(alb.pagerank, dg, outf, opts, 0.85, 50)
         b = alb.algorithmic_bytes("pagerank", st, n=g.n, iterations=50)
         res.setdefault("pagerank", {})[label] = dict({"kernel_ms": round(ms, 3),
                                                       "gteps": round(50 * g.m / ms / 1e6, 3)}, **rates(b, ms))
         log("pagerank %s: %.3f ms" % (label, ms))
-    push_rank = outf.cpu().numpy()
+        push_rank = outf.cpu().numpy()
     dg.close()
     # the paper's pr: pull over the in-edges, classified by in-degree
-    t = time.perf_counter()
-    dt = alb.Graph(g.off, g.col, build_transpose=True)
-    log("transposed (%.1fs)" % (time.perf_counter() - t))
-    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+    for label, opts in modes if "pull" in parts else ():
+        if label == "alb":
+            t = time.perf_counter()
+            dt = alb.Graph(g.off, g.col, build_transpose=True)
+            log("transposed (%.1fs)" % (time.perf_counter() - t))
         ms, st = timed(alb.pagerank_pull, dt, outf, opts, 0.85, 50)
         b = alb.algorithmic_bytes("pagerank", st, n=g.n, iterations=50)
         res.setdefault("pagerank_pull", {})[label] = dict({"kernel_ms": round(ms, 3),
                                                            "gteps": round(50 * g.m / ms / 1e6, 3),
                                                            "huge_vertices": st["huge_vertices"]}, **rates(b, ms))
         log("pagerank pull %s: %.3f ms" % (label, ms))
-    res["pagerank_pull"]["equals_push"] = bool(np.array_equal(outf.cpu().numpy(), push_rank))
-    dt.close()
-    t = time.perf_counter()
-    ds = alb.Graph(g.off, g.col, build_symmetric=True)
-    log("symmetrised: m=%d (%.1fs)" % (ds.m, time.perf_counter() - t))
-    for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+    if "pull" in parts:
+        if push_rank is not None:
+            res["pagerank_pull"]["equals_push"] = bool(np.array_equal(outf.cpu().numpy(), push_rank))
+        dt.close()
+    ds = None
+    if "cc" in parts or kcore:
+        t = time.perf_counter()
+        ds = alb.Graph(g.off, g.col, build_symmetric=True)
+        log("symmetrised: m=%d (%.1fs)" % (ds.m, time.perf_counter() - t))
+    for label, opts in modes if "cc" in parts else ():
         ms, st = timed(lambda d, out=None, **o: alb.cc(d, out=out, **o), ds, out, opts)
         b = alb.algorithmic_bytes("cc", st)
         res.setdefault("cc", {})[label] = dict({"kernel_ms": round(ms, 3),
@@ -736,31 +760,34 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True):
                                                 "gteps": round(ds.m / ms / 1e6, 3), "rounds": st["rounds"]},
                                                **rates(b, ms))
         log("cc %s: %.3f ms" % (label, ms))
-    res["cc"]["alb_over_twc"] = round(res["cc"]["twc_only"]["kernel_ms"] / res["cc"]["alb"]["kernel_ms"], 2)
+    if "cc" in parts and not args.only_alb:
+        res["cc"]["alb_over_twc"] = round(res["cc"]["twc_only"]["kernel_ms"] / res["cc"]["alb"]["kernel_ms"], 2)
     # k-core (the paper's kcore) on the same symmetrised graph: peeling from
     # every vertex with fewer than k neighbours
     for k in ((8, 32) if kcore else ()):
-        for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+        for label, opts in modes:
             ms, st = timed(lambda d, kk, out=None, **o: alb.kcore(d, kk, out=out, **o), ds, out, opts, k)
             b = alb.algorithmic_bytes("kcore", st)
             res.setdefault("kcore_k%d" % k, {})[label] = dict({
                 "kernel_ms": round(ms, 3), "edges_per_s_g": round(st["edges_examined"] / ms / 1e6, 3),
                 "rounds": st["rounds"], "core_vertices": int(out.sum().item())}, **rates(b, ms))
             log("kcore k=%d %s: %.3f ms" % (k, label, ms))
-    ds.close()
+    if ds is not None:
+        ds.close()
     del g
     if grid:
         gr = gg.grid(2048, 2048).with_weights(5)
         dgr = alb.Graph(gr.off, gr.col, gr.w)
         outg = torch.empty(gr.n, dtype=torch.int32, device="cuda")
         for kind, fn in (("bfs", alb.bfs), ("sssp", alb.sssp)):
-            for label, opts in (("alb", alb_opts), ("twc_only", {"mode": "twc"})):
+            for label, opts in modes:
                 ms, st = timed(fn, dgr, outg, opts, 0)
                 res.setdefault("grid2048_" + kind, {})[label] = {"kernel_ms": round(ms, 3), "rounds": st["rounds"],
                                                                  "huge_vertices": st["huge_vertices"]}
                 log("grid %s %s: %.3f ms" % (kind, label, ms))
         dgr.close()
-    bfs = res["bfs"]["alb"]
+    bfs = res["bfs"]["alb"] if "bfs" in res else {"gteps": None, "kernel_ms": None, "achieved_gbs": None,
+                                                  "frac": None}
     line = {
         "metric": METRIC,
         "value": bfs["gteps"],
@@ -868,8 +895,10 @@ def bench_serve(args, alb, gg, emit=True):
     graphs of 2^20 and 2^23 vertices, weights U[1,100]); requests BFS:SSSP
     1:1, graph uniform, source uniform over vertices with out-edges.  For each
     arrival rate a Poisson stream goes through the serving loop (2 lanes,
-    batches up to 256) and, with fewer requests, through the same loop with
-    one request per batch on one lane (one launch per query).  Latency runs
+    batches up to 256), through the loop with continuous batching inside a
+    launch (join_running: requests join a running launch between rounds) and,
+    with fewer requests, through the loop with one request per batch on one
+    lane (one launch per query).  Latency runs
     from submit to the result in host memory.  `value` is the batched loop's
     throughput with every request queued at once (its capacity)."""
     import numpy as np
@@ -893,9 +922,13 @@ def bench_serve(args, alb, gg, emit=True):
 
     batched = alb.Server(gset, lanes=2, max_batch=256, hbm_budget=32 << 30)
     single = alb.Server(gset, lanes=1, max_batch=1, hbm_budget=32 << 30)
+    # continuous batching inside a launch: requests join a running launch of
+    # their algorithm between rounds and leave when their traversal converges
+    joined = alb.Server(gset, lanes=1, max_batch=512, hbm_budget=32 << 30, join_running=True)
     warm = make_requests(200, 99)
     serve_run(alb, batched, pool, warm, None)
     serve_run(alb, single, pool, warm[:50], None)
+    serve_run(alb, joined, pool, warm, None)
 
     # served results checked against the oracle: a sample of the capacity run's and each stream's
     # requests on the member graphs of at most 2M edges
@@ -922,6 +955,9 @@ def bench_serve(args, alb, gg, emit=True):
     n1 = min(args.requests, 2000)
     cap1, lat1, _, f1 = serve_run(alb, single, pool, reqs[:n1], None)
     log("one-at-a-time capacity: %.0f queries/s" % cap1)
+    capj, latj, _, fj = serve_run(alb, joined, pool, reqs, None, keep=sample(reqs))
+    verify(joined, reqs)
+    log("joining capacity: %.0f queries/s, p50 %.1f ms, p99 %.1f ms" % (capj, pct(latj, 50), pct(latj, 99)))
     rates = []
     for rate in [float(x) for x in args.rates.split(",")]:
         arr = gg.poisson_arrivals(rate, args.requests, seed=9)
@@ -930,15 +966,23 @@ def bench_serve(args, alb, gg, emit=True):
         verify(batched, r)
         m1 = min(args.requests, max(200, int(rate * 10)), 2000)
         thr1, l1, _, fs = serve_run(alb, single, pool, r[:m1], arr[:m1])
+        thrj, lj, _, fjr = serve_run(alb, joined, pool, r, arr, keep=sample(r))
+        verify(joined, r)
         rates.append({"rate": rate, "requests": len(r), "achieved": round(thr, 1), "p50_ms": pct(l, 50),
                       "p99_ms": pct(l, 99), "mean_batch": round(float(sz.mean()), 2), "failed": fb,
+                      "join_running": {"achieved": round(thrj, 1), "p50_ms": pct(lj, 50), "p99_ms": pct(lj, 99),
+                                       "failed": fjr},
                       "one_at_a_time": {"requests": m1, "achieved": round(thr1, 1), "p50_ms": pct(l1, 50),
                                         "p99_ms": pct(l1, 99), "failed": fs}})
-        log("rate %6.0f/s: batched %.0f/s p50 %.2f p99 %.2f ms (batch %.1f); one-at-a-time %.0f/s p50 %.2f p99 %.2f" % (
-            rate, thr, pct(l, 50), pct(l, 99), sz.mean(), thr1, pct(l1, 50), pct(l1, 99)))
+        log("rate %6.0f/s: batched %.0f/s p50 %.2f p99 %.2f ms (batch %.1f); joining %.0f/s p50 %.2f p99 %.2f; "
+            "one-at-a-time %.0f/s p50 %.2f p99 %.2f" % (rate, thr, pct(l, 50), pct(l, 99), sz.mean(), thrj,
+                                                       pct(lj, 50), pct(lj, 99), thr1, pct(l1, 50), pct(l1, 99)))
     st = batched.stats()
+    stj = joined.stats()
+    launches_j = len(joined.batch_log())
     batched.close()
     single.close()
+    joined.close()
     res = {
         "metric": METRIC,
         "value": round(cap, 1),
@@ -960,6 +1004,9 @@ def bench_serve(args, alb, gg, emit=True):
         "failed": f,
         "one_at_a_time": {"value": round(cap1, 1), "unit": "queries/s", "requests": n1,
                           "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99)}, "failed": f1},
+        "join_running": {"value": round(capj, 1), "unit": "queries/s", "requests": len(reqs),
+                         "latency_ms": {"p50": pct(latj, 50), "p99": pct(latj, 99)}, "failed": fj,
+                         "launches": launches_j, "completed": stj["completed"]},
         "poisson": rates,
         "results_checked_against_oracle": checked,
         "server_stats": st,

@@ -247,6 +247,24 @@ alb_status alb_bfs_batch(alb_graph g, int32_t count, const int32_t *members, con
 alb_status alb_sssp_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
                           int32_t *const *dists, const int64_t *thresholds, const alb_options *opt, alb_stats *stats);
 
+/* Balancer settings of one query of a batch: its huge threshold (Algorithm
+ * 1's test, >= 0) and its TWC bin cutoffs (Section 3; >= 1): wavefront bin
+ * from wave_cutoff edges, workgroup bin from wg_cutoff edges. */
+typedef struct {
+  int64_t huge_threshold;
+  int32_t wave_cutoff;
+  int32_t wg_cutoff;
+} alb_query_tuning;
+
+/* alb_bfs_batch / alb_sssp_batch with per-query settings: tuning[count]
+ * (mode ALB only), e.g. from alb_autotune_batch_tuned.  Otherwise as those. */
+alb_status alb_bfs_batch_tuned(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                               int32_t *const *levels, const alb_query_tuning *tuning, const alb_options *opt,
+                               alb_stats *stats);
+alb_status alb_sssp_batch_tuned(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                                int32_t *const *dists, const alb_query_tuning *tuning, const alb_options *opt,
+                                alb_stats *stats);
+
 /* Traversals that batches, plans and the autotuner accept. */
 typedef enum { ALB_ALGO_BFS = 0, ALB_ALGO_SSSP = 1 } alb_algo;
 
@@ -264,6 +282,10 @@ typedef struct alb_plan_s *alb_plan;
 alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
                                  const int32_t *sources, int32_t *const *outs, const int64_t *thresholds,
                                  const alb_options *opt, alb_plan *out);
+/* A plan with per-query settings (as alb_sssp_batch_tuned). */
+alb_status alb_batch_plan_create_tuned(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                                       const int32_t *sources, int32_t *const *outs, const alb_query_tuning *tuning,
+                                       const alb_options *opt, alb_plan *out);
 alb_status alb_batch_plan_run(alb_plan p, alb_stats *stats);
 alb_status alb_batch_plan_destroy(alb_plan p);
 
@@ -292,6 +314,19 @@ alb_status alb_autotune(alb_graph g, int32_t algo, int32_t member, int32_t nsour
 alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
                               const int32_t *sources, const alb_options *base, alb_options *tuned,
                               int64_t *thresholds);
+
+/* Autotuner for a batch with per-query bin cutoffs: the search of
+ * alb_autotune_batch, then for the same degree-signature groups (most edges
+ * first, up to 8) the TWC cutoff pairs (wave, workgroup) = (32, w), (128, w),
+ * (64, 2w), (64, 4w) around the default (64, w) for that group alone, w the
+ * tuned workgroup size, each kept if the batch gets at least 1 % faster.
+ * Fills tuning[count] and the workgroup size in *tuned; *uniform_ms (if not
+ * NULL) gets the batch's median device time at the best single setting of the
+ * grid (one threshold, default cutoffs, for every query) and *tuned_ms (if not
+ * NULL) at the returned per-query settings.  Not cached. */
+alb_status alb_autotune_batch_tuned(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                                    const int32_t *sources, const alb_options *base, alb_options *tuned,
+                                    alb_query_tuning *tuning, double *uniform_ms, double *tuned_ms);
 
 /* Forget every cached tuning result. */
 alb_status alb_autotune_reset(void);
@@ -334,7 +369,17 @@ typedef struct {
   const int32_t *member_vertices; /* ... and each member's vertex count (copied) */
   int32_t whole_device_when_alone; /* a batch that starts while no other lane runs uses every resident
                                       workgroup instead of its lane's share (1 = on, the default) */
-  int32_t reserved[7];
+  int32_t join_running;      /* 1: continuous batching inside a launch.  A lane keeps one persistent launch
+                                running; requests join it at the next round boundary as soon as a query slot
+                                (max_batch per launch, at most 1024) and label memory (the lane's share of
+                                hbm_budget) are free, and leave it as soon as their own traversal has
+                                converged.  BFS and SSSP requests share a launch (BFS runs as shortest paths
+                                with unit weights: same levels).  With lanes = 1 the launch may use the whole
+                                device, else the lane's share.  The launch ends after join_idle_us without work.
+                                Needs the GPU (no executor).  0 (default): a batch is fixed when its launch
+                                starts. */
+  int32_t join_idle_us;      /* join_running: idle time before a launch ends; 0 = 500 us */
+  int32_t reserved[5];
 } alb_server_config;
 
 typedef struct {

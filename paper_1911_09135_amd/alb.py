@@ -97,7 +97,9 @@ class ServerConfig(ctypes.Structure):
         ("n_members", ctypes.c_int32),
         ("member_vertices", ctypes.POINTER(ctypes.c_int32)),
         ("whole_device_when_alone", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("join_running", ctypes.c_int32),
+        ("join_idle_us", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -116,6 +118,10 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "timed_out", "cancelled",
                                               "rejected", "batches", "pending", "running")] + \
                [("busy_ms", ctypes.c_double)]
+
+
+class QueryTuning(ctypes.Structure):
+    _fields_ = [("huge_threshold", ctypes.c_int64), ("wave_cutoff", ctypes.c_int32), ("wg_cutoff", ctypes.c_int32)]
 
 
 class BatchRecord(ctypes.Structure):
@@ -143,6 +149,11 @@ _sig = {
                               ctypes.c_int),
     "alb_bfs_batch": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
     "alb_sssp_batch": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_bfs_batch_tuned": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_sssp_batch_tuned": ([_vp, _i32, _vp, _vp, _vp, _vp, _POpt, _PSt], ctypes.c_int),
+    "alb_batch_plan_create_tuned": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp, _POpt, ctypes.POINTER(_vp)], ctypes.c_int),
+    "alb_autotune_batch_tuned": ([_vp, _i32, _i32, _vp, _vp, _POpt, _POpt, _vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "alb_batch_plan_create": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp, _POpt, ctypes.POINTER(_vp)], ctypes.c_int),
     "alb_batch_plan_run": ([_vp, _PSt], ctypes.c_int),
     "alb_batch_plan_destroy": ([_vp], ctypes.c_int),
@@ -321,7 +332,17 @@ class GraphSet(Graph):
             self.members.append((a.value, b.value, c.value))
 
 
-def _run_batch(fn, gs: GraphSet, members, sources, thresholds, outs, opts: dict):
+def _tuning_array(tuning, q: int):
+    """A ctypes array of alb_query_tuning from a list of (threshold, wave cutoff, wg cutoff)."""
+    if len(tuning) != q:
+        raise ValueError("one tuning entry per query")
+    arr = (QueryTuning * max(q, 1))()
+    for i, (t, cw, cg) in enumerate(tuning):
+        arr[i].huge_threshold, arr[i].wave_cutoff, arr[i].wg_cutoff = int(t), int(cw), int(cg)
+    return arr
+
+
+def _run_batch(fn, gs: GraphSet, members, sources, thresholds, outs, opts: dict, tuning=None):
     members = np.ascontiguousarray(members, np.int32)
     sources = np.ascontiguousarray(sources, np.int32)
     if members.shape != sources.shape or members.ndim != 1:
@@ -335,11 +356,16 @@ def _run_batch(fn, gs: GraphSet, members, sources, thresholds, outs, opts: dict)
     thr = None if thresholds is None else np.ascontiguousarray(thresholds, np.int64)
     if thr is not None and thr.shape != (q,):
         raise ValueError("one threshold per query")
+    per_query = None
+    if tuning is not None:
+        per_query = ctypes.cast(_tuning_array(tuning, q), _vp)
+    elif thr is not None:
+        per_query = thr.ctypes.data
     ptr_arr = (_vp * max(q, 1))(*ptrs)
     o = make_options(out_on_device=dev, **opts)
     st = Stats()
-    _check(fn(gs.handle, q, members.ctypes.data, sources.ctypes.data, ctypes.cast(ptr_arr, _vp),
-              None if thr is None else thr.ctypes.data, ctypes.byref(o), ctypes.byref(st)), fn.__name__)
+    _check(fn(gs.handle, q, members.ctypes.data, sources.ctypes.data, ctypes.cast(ptr_arr, _vp), per_query,
+              ctypes.byref(o), ctypes.byref(st)), fn.__name__)
     return outs, st.as_dict()
 
 
@@ -370,7 +396,8 @@ class BatchPlan:
     """A batch captured once into a HIP graph and replayed by run()
     (alb_batch_plan_create).  Outputs stay bound to the plan."""
 
-    def __init__(self, gs: GraphSet, algo: str, members, sources, thresholds=None, outs=None, **opts):
+    def __init__(self, gs: GraphSet, algo: str, members, sources, thresholds=None, outs=None, tuning=None,
+                 **opts):
         members = np.ascontiguousarray(members, np.int32)
         sources = np.ascontiguousarray(sources, np.int32)
         if members.shape != sources.shape or members.ndim != 1:
@@ -384,10 +411,17 @@ class BatchPlan:
         self._ptrs = (_vp * max(len(ptrs), 1))(*ptrs)
         o = make_options(out_on_device=dev, **opts)
         h = _vp()
-        _check(_lib.alb_batch_plan_create(gs.handle, ALGOS[algo], members.shape[0], members.ctypes.data,
-                                          sources.ctypes.data, ctypes.cast(self._ptrs, _vp),
-                                          None if thr is None else thr.ctypes.data, ctypes.byref(o),
-                                          ctypes.byref(h)), "alb_batch_plan_create")
+        if tuning is not None:
+            tarr = _tuning_array(tuning, members.shape[0])
+            _check(_lib.alb_batch_plan_create_tuned(gs.handle, ALGOS[algo], members.shape[0], members.ctypes.data,
+                                                    sources.ctypes.data, ctypes.cast(self._ptrs, _vp),
+                                                    ctypes.cast(tarr, _vp), ctypes.byref(o), ctypes.byref(h)),
+                   "alb_batch_plan_create_tuned")
+        else:
+            _check(_lib.alb_batch_plan_create(gs.handle, ALGOS[algo], members.shape[0], members.ctypes.data,
+                                              sources.ctypes.data, ctypes.cast(self._ptrs, _vp),
+                                              None if thr is None else thr.ctypes.data, ctypes.byref(o),
+                                              ctypes.byref(h)), "alb_batch_plan_create")
         self._h = h
         self._gs = gs  # the graph must outlive the plan
 
@@ -461,6 +495,36 @@ def sssp_batch(gs: GraphSet, members, sources, thresholds=None, outs=None, **opt
     return _run_batch(_lib.alb_sssp_batch, gs, members, sources, thresholds, outs, opts)
 
 
+def bfs_batch_tuned(gs: GraphSet, members, sources, tuning, outs=None, **opts):
+    """bfs_batch with per-query (threshold, wave cutoff, workgroup cutoff) triples."""
+    return _run_batch(_lib.alb_bfs_batch_tuned, gs, members, sources, None, outs, opts, tuning=tuning)
+
+
+def sssp_batch_tuned(gs: GraphSet, members, sources, tuning, outs=None, **opts):
+    """sssp_batch with per-query (threshold, wave cutoff, workgroup cutoff) triples."""
+    return _run_batch(_lib.alb_sssp_batch_tuned, gs, members, sources, None, outs, opts, tuning=tuning)
+
+
+def autotune_batch_tuned(gs: GraphSet, algo: str, members, sources, **opts):
+    """Per-query thresholds and TWC cutoffs for a batch (alb_autotune_batch_tuned).
+    Returns (options dict, list of (threshold, wave cutoff, wg cutoff), best
+    uniform-setting ms, tuned ms)."""
+    members = np.ascontiguousarray(members, np.int32)
+    sources = np.ascontiguousarray(sources, np.int32)
+    q = members.shape[0]
+    base = make_options(**opts)
+    tuned = Options()
+    arr = (QueryTuning * max(q, 1))()
+    u_ms, t_ms = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.alb_autotune_batch_tuned(gs.handle, ALGOS[algo], q, members.ctypes.data, sources.ctypes.data,
+                                         ctypes.byref(base), ctypes.byref(tuned), ctypes.cast(arr, _vp),
+                                         ctypes.byref(u_ms), ctypes.byref(t_ms)), "alb_autotune_batch_tuned")
+    d = _opts_dict(tuned)
+    for k in ("threshold", "wave_cutoff", "wg_cutoff"):
+        d.pop(k)
+    return d, [(arr[i].huge_threshold, arr[i].wave_cutoff, arr[i].wg_cutoff) for i in range(q)], u_ms.value, t_ms.value
+
+
 class Server:
     """Request loop over a graph set (alb_server_create).  submit() queues a
     BFS / SSSP request and returns its ticket; wait(ticket) blocks until the
@@ -472,11 +536,13 @@ class Server:
 
     def __init__(self, gs: Optional[GraphSet] = None, lanes: int = 2, max_batch: int = 256, max_wait_us: int = 0,
                  hbm_budget: int = 0, executor=None, member_vertices=None, whole_device_when_alone: bool = True,
-                 **opts):
+                 join_running: bool = False, join_idle_us: int = 0, **opts):
         cfg = ServerConfig()
         _check(_lib.alb_server_config_init(ctypes.byref(cfg)), "alb_server_config_init")
         cfg.lanes, cfg.max_batch, cfg.max_wait_us, cfg.hbm_budget = lanes, max_batch, max_wait_us, hbm_budget
         cfg.whole_device_when_alone = 1 if whole_device_when_alone else 0
+        cfg.join_running = 1 if join_running else 0
+        cfg.join_idle_us = int(join_idle_us)
         cfg.options = make_options(**opts)
         if gs is not None:
             self.member_n = [m[0] for m in gs.members]

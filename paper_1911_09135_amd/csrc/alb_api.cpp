@@ -86,8 +86,9 @@ struct Workspace {
 // (query << 32 | vertex) entries, one label per (query, vertex of its graph)
 // and the per-query tables.
 // Bytes of per-query tables in a batch workspace: three int64 (label offset,
-// threshold, label base), an output pointer and two int32 (source, size).
-constexpr size_t kBatchTableBytes = 3 * sizeof(long long) + sizeof(int32_t *) + 2 * sizeof(int32_t);
+// threshold, label base), an output pointer and four int32 (source, size,
+// wavefront and workgroup cutoffs).
+constexpr size_t kBatchTableBytes = 3 * sizeof(long long) + sizeof(int32_t *) + 4 * sizeof(int32_t);
 
 struct BatchWs {
   long long lab_cap = 0;
@@ -532,14 +533,15 @@ uint64_t barrier_timeout_ms() {
 std::mutex g_res_mu;
 std::map<std::tuple<int, int, int>, int> g_res;
 
-alb_status resident_workgroups(alb_graph g, OpKind op, int wg, int *out, bool batch = false) {
-  const auto key = std::make_tuple(g->device, (int)op + (batch ? 256 : 0), wg);
+alb_status resident_workgroups(alb_graph g, OpKind op, int wg, int *out, bool batch = false, bool open = false) {
+  const auto key = std::make_tuple(g->device, (int)op + (batch ? 256 : 0) + (open ? 512 : 0), wg);
   std::lock_guard<std::mutex> lk(g_res_mu);
   auto it = g_res.find(key);
   if (it == g_res.end()) {
     int per_cu = 0;
-    HIP_TRY(batch ? batch_occupancy(op, wg, &per_cu)
-                  : op == OP_PR_PULL ? pull_occupancy(wg, &per_cu) : persistent_occupancy(op, wg, &per_cu));
+    HIP_TRY(open    ? open_occupancy(op, wg, &per_cu)
+            : batch ? batch_occupancy(op, wg, &per_cu)
+                    : op == OP_PR_PULL ? pull_occupancy(wg, &per_cu) : persistent_occupancy(op, wg, &per_cu));
     if (per_cu < 1) return fail(ALB_E_DEVICE, "persistent kernel does not fit on a CU with wg_size %d", wg);
     it = g_res.emplace(key, per_cu * g->cus).first;
   }
@@ -895,7 +897,8 @@ struct BatchJob {
   std::vector<long long> qoff, qthr, qlbase;
   std::vector<int32_t> qsrc, qn;
   std::vector<int32_t *> qout;  // filled once the workspace is known
-  bool per_query_thr = false;
+  std::vector<int32_t> qcut;    // per query: wavefront and workgroup bin cutoffs
+  bool per_query_thr = false, per_query_cut = false;
   long long labels = 0, edges = 0, thr_min = 0;
   int32_t max_n = 0;
   int32_t max_deg = 0;  // largest out-degree of the queries' members
@@ -906,8 +909,10 @@ struct BatchJob {
   Args a;
 };
 
+// `cutoffs`: per query the wavefront and workgroup bin cutoffs ([2q], [2q + 1]), or null.
 alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
-                         int32_t *const *outs, const int64_t *thresholds, const alb_options *user, BatchJob &j) {
+                         int32_t *const *outs, const int64_t *thresholds, const int32_t *cutoffs,
+                         const alb_options *user, BatchJob &j) {
   if (!g) return fail(ALB_E_INVAL, "graph handle is NULL");
   if (count < 1 || count > kMaxBatch) return fail(ALB_E_INVAL, "count %d not in [1, %d]", count, kMaxBatch);
   if (!members || !sources || !outs) return fail(ALB_E_INVAL, "members, sources and outs must not be NULL");
@@ -917,6 +922,10 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
   if (s != ALB_OK) return s;
   if (o.launch == ALB_LAUNCH_HOST_LOOP) return fail(ALB_E_UNSUPPORTED, "batches run as one persistent launch only");
   if (thresholds && o.mode != ALB_MODE_ALB) return fail(ALB_E_INVAL, "per-query thresholds need mode ALB");
+  if (cutoffs)
+    for (int32_t q = 0; q < count; ++q)
+      if (cutoffs[2 * q] < 1 || cutoffs[2 * q + 1] < 1)
+        return fail(ALB_E_INVAL, "cutoffs of query %d must be >= 1", q);
   j.op = op;
   j.count = count;
   const int32_t nmem = (int32_t)g->mem_n.size();
@@ -927,6 +936,8 @@ alb_status prepare_batch(alb_graph g, OpKind op, int32_t count, const int32_t *m
   j.qn.resize(count);
   j.qout.assign(outs, outs + count);
   j.per_query_thr = thresholds != nullptr;
+  j.per_query_cut = cutoffs != nullptr;
+  if (cutoffs) j.qcut.assign(cutoffs, cutoffs + 2 * (size_t)count);
   long long labels = 0, edges = 0, thr_min = LLONG_MAX;
   int32_t max_n = 0;
   for (int32_t q = 0; q < count; ++q) {
@@ -1046,6 +1057,8 @@ alb_status upload_batch(BatchJob &j, BatchWs *ws) {
     h_out[q] = j.o.out_on_device ? j.qout[q] : ws->out32 + j.qlbase[q];
     h_i32[q] = j.qsrc[q];
     h_i32[c + q] = j.qn[q];
+    h_i32[2 * c + 2 * q] = j.per_query_cut ? j.qcut[2 * q] : j.o.wave_cutoff;
+    h_i32[2 * c + 2 * q + 1] = j.per_query_cut ? j.qcut[2 * q + 1] : j.o.wg_cutoff;
   }
   a.qoff = d_off;
   a.qthr = j.per_query_thr ? d_off + c : nullptr;
@@ -1053,6 +1066,7 @@ alb_status upload_batch(BatchJob &j, BatchWs *ws) {
   a.qout = d_out;
   a.qsrc = d_i32;
   a.qn = d_i32 + c;
+  a.qcut = j.per_query_cut ? d_i32 + 2 * c : nullptr;
   const hipStream_t st = j.stream;
   HIP_TRY(hipMemcpyAsync(ws->tab, ws->h_tab, kBatchTableBytes * c, hipMemcpyHostToDevice, st));
   // the pinned mirror is rewritten by the next batch on this workspace: the
@@ -1106,11 +1120,28 @@ alb_status finish_batch(alb_graph g, const BatchJob &j, BatchWs *ws, int32_t *co
   return ALB_OK;
 }
 
+// Per-query tuning records as threshold and cutoff arrays.
+alb_status split_tuning(int32_t count, const alb_query_tuning *tuning, std::vector<int64_t> &thr,
+                        std::vector<int32_t> &cut) {
+  if (!tuning) return fail(ALB_E_INVAL, "tuning is NULL");
+  if (count < 1 || count > kMaxBatch) return fail(ALB_E_INVAL, "count %d not in [1, %d]", count, kMaxBatch);
+  thr.resize((size_t)count);
+  cut.resize(2 * (size_t)count);
+  for (int32_t q = 0; q < count; ++q) {
+    thr[(size_t)q] = tuning[q].huge_threshold;
+    cut[2 * (size_t)q] = tuning[q].wave_cutoff;
+    cut[2 * (size_t)q + 1] = tuning[q].wg_cutoff;
+  }
+  return ALB_OK;
+}
+
+
 alb_status run_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
-                     int32_t *const *outs, const int64_t *thresholds, const alb_options *user, alb_stats *st) {
+                     int32_t *const *outs, const int64_t *thresholds, const int32_t *cutoffs, const alb_options *user,
+                     alb_stats *st) {
   g_window.valid = false;
   BatchJob j;
-  alb_status s = prepare_batch(g, op, count, members, sources, outs, thresholds, user, j);
+  alb_status s = prepare_batch(g, op, count, members, sources, outs, thresholds, cutoffs, user, j);
   if (s != ALB_OK) return s;
   BatchWs *ws = nullptr;
   s = bws_acquire(g, batch_needs(j), &ws);
@@ -1169,12 +1200,13 @@ TuneKey tune_key(alb_graph g, OpKind op, int32_t member) {
 // Median device time (3 runs after a warm-up) of a batch under options o and
 // optional per-query thresholds; outputs go to the workspace's staging area.
 alb_status time_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
-                      const int64_t *thresholds, const alb_options &o, BatchWs *ws, double *ms) {
+                      const int64_t *thresholds, const int32_t *cutoffs, const alb_options &o, BatchWs *ws,
+                      double *ms) {
   std::vector<int32_t *> outs((size_t)count, (int32_t *)ws);  // placeholders, replaced below
   alb_options oo = o;
   oo.out_on_device = 1;
   BatchJob j;
-  alb_status s = prepare_batch(g, op, count, members, sources, outs.data(), thresholds, &oo, j);
+  alb_status s = prepare_batch(g, op, count, members, sources, outs.data(), thresholds, cutoffs, &oo, j);
   if (s != ALB_OK) return s;
   const BatchNeeds nd = batch_needs(j);
   if (ws->lab_cap < nd.labels || ws->qcap < nd.qcap || ws->hint_cap < nd.hint_cap || ws->nq_cap < nd.nq)
@@ -1203,7 +1235,7 @@ alb_status time_batch(alb_graph g, OpKind op, int32_t count, const int32_t *memb
 alb_status time_candidate(alb_graph g, OpKind op, int32_t member, int32_t k, const int32_t *sources,
                           const alb_options &o, BatchWs *ws, double *ms) {
   std::vector<int32_t> mb((size_t)k, member);
-  return time_batch(g, op, k, mb.data(), sources, nullptr, o, ws, ms);
+  return time_batch(g, op, k, mb.data(), sources, nullptr, nullptr, o, ws, ms);
 }
 
 // A workspace big enough for `count` queries of this batch.
@@ -1214,7 +1246,7 @@ alb_status batch_scratch(alb_graph g, OpKind op, int32_t count, const int32_t *m
   probe.wg_size = 1024;
   BatchJob pj;
   std::vector<int32_t *> dummy((size_t)count, (int32_t *)&pj);
-  alb_status s = prepare_batch(g, op, count, members, sources, dummy.data(), nullptr, &probe, pj);
+  alb_status s = prepare_batch(g, op, count, members, sources, dummy.data(), nullptr, nullptr, &probe, pj);
   if (s != ALB_OK) return s;
   s = bws_fill(ws, batch_needs(pj));
   if (s != ALB_OK) {
@@ -1840,7 +1872,7 @@ alb_status alb_trace_round(alb_graph g, const int32_t *frontier, int64_t nf, con
 alb_status alb_bfs_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
                          int32_t *const *levels, const int64_t *thresholds, const alb_options *opt, alb_stats *stats) {
   zero_stats(stats);
-  alb_status s = run_batch(g, OP_BFS, count, members, sources, levels, thresholds, opt, stats);
+  alb_status s = run_batch(g, OP_BFS, count, members, sources, levels, thresholds, nullptr, opt, stats);
   if (s != ALB_OK) zero_stats(stats);
   return s;
 }
@@ -1848,7 +1880,31 @@ alb_status alb_bfs_batch(alb_graph g, int32_t count, const int32_t *members, con
 alb_status alb_sssp_batch(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
                           int32_t *const *dists, const int64_t *thresholds, const alb_options *opt, alb_stats *stats) {
   zero_stats(stats);
-  alb_status s = run_batch(g, OP_SSSP, count, members, sources, dists, thresholds, opt, stats);
+  alb_status s = run_batch(g, OP_SSSP, count, members, sources, dists, thresholds, nullptr, opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_bfs_batch_tuned(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                               int32_t *const *levels, const alb_query_tuning *tuning, const alb_options *opt,
+                               alb_stats *stats) {
+  zero_stats(stats);
+  std::vector<int64_t> thr;
+  std::vector<int32_t> cut;
+  alb_status s = split_tuning(count, tuning, thr, cut);
+  if (s == ALB_OK) s = run_batch(g, OP_BFS, count, members, sources, levels, thr.data(), cut.data(), opt, stats);
+  if (s != ALB_OK) zero_stats(stats);
+  return s;
+}
+
+alb_status alb_sssp_batch_tuned(alb_graph g, int32_t count, const int32_t *members, const int32_t *sources,
+                                int32_t *const *dists, const alb_query_tuning *tuning, const alb_options *opt,
+                                alb_stats *stats) {
+  zero_stats(stats);
+  std::vector<int64_t> thr;
+  std::vector<int32_t> cut;
+  alb_status s = split_tuning(count, tuning, thr, cut);
+  if (s == ALB_OK) s = run_batch(g, OP_SSSP, count, members, sources, dists, thr.data(), cut.data(), opt, stats);
   if (s != ALB_OK) zero_stats(stats);
   return s;
 }
@@ -1876,62 +1932,46 @@ alb_status alb_autotune(alb_graph g, int32_t algo, int32_t member, int32_t nsour
   return ALB_OK;
 }
 
-alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
-                              const int32_t *sources, const alb_options *base, alb_options *tuned,
-                              int64_t *thresholds) {
-  if (!g || !tuned || !thresholds || !members || !sources) return fail(ALB_E_INVAL, "NULL argument");
-  if (algo != ALB_ALGO_BFS && algo != ALB_ALGO_SSSP) return fail(ALB_E_UNSUPPORTED, "algo %d cannot be tuned", algo);
-  if (count < 1 || count > kMaxBatch) return fail(ALB_E_INVAL, "count %d not in [1, %d]", count, kMaxBatch);
-  alb_options b;
-  alb_status s = resolve_options(base, b);
-  if (s != ALB_OK) return s;
-  const OpKind op = algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP;
-  const int32_t nmem = (int32_t)g->mem_n.size();
-  for (int32_t q = 0; q < count; ++q)
-    if (members[q] < 0 || members[q] >= nmem) return fail(ALB_E_INVAL, "members[%d] out of range", q);
-  // the batch's members grouped by degree signature; the cache key is the
-  // batch's multiset of signatures
+}  // extern "C"
+
+namespace {
+
+// The batch autotuner's search (see alb_autotune_batch): stage 1 times one
+// threshold for every query over the paper's plateau and both workgroup
+// sizes; stage 2 moves the threshold of each of the largest degree-signature
+// groups 4x down or up.  With `cutoffs`, stage 3 then tries other TWC cutoff
+// pairs per group.  A change must gain at least 1 %.
+struct BatchTune {
+  int32_t wg = 256;
+  std::map<TuneKey, int64_t> thr;
+  std::map<TuneKey, std::pair<int32_t, int32_t>> cut;  // (wave, workgroup) cutoffs
+  double uniform_ms = 0, best_ms = 0;
+};
+
+alb_status tune_batch(alb_graph g, OpKind op, int32_t count, const int32_t *members, const int32_t *sources,
+                      const alb_options &b, bool cutoffs, BatchTune *out) {
   std::map<TuneKey, std::vector<int32_t>> groups;  // signature -> queries
   std::map<TuneKey, int64_t> group_edges;
+  std::vector<TuneKey> key((size_t)count);
   for (int32_t q = 0; q < count; ++q) {
-    const TuneKey k = tune_key(g, op, members[q]);
-    groups[k].push_back(q);
-    group_edges[k] += g->mem_m[members[q]];
-  }
-  std::vector<TuneKey> sig;
-  for (auto &kv : groups)
-    for (size_t i = 0; i < kv.second.size(); ++i) sig.push_back(kv.first);
-  const auto ckey = std::make_pair((int)op, sig);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_batch.find(ckey);
-    if (it != g_tune_batch.end()) {
-      b.mode = ALB_MODE_ALB;
-      b.wg_size = it->second.first;
-      b.wave_cutoff = 64;
-      b.wg_cutoff = b.wg_size;
-      b.huge_threshold = ALB_THRESHOLD_DEFAULT;
-      std::map<TuneKey, int64_t> thr = it->second.second;
-      for (int32_t q = 0; q < count; ++q) thresholds[q] = thr[tune_key(g, op, members[q])];
-      *tuned = b;
-      return ALB_OK;
-    }
+    key[(size_t)q] = tune_key(g, op, members[q]);
+    groups[key[(size_t)q]].push_back(q);
+    group_edges[key[(size_t)q]] += g->mem_m[members[q]];
   }
   BatchWs ws;
-  s = batch_scratch(g, op, count, members, sources, b, &ws);
+  alb_status s = batch_scratch(g, op, count, members, sources, b, &ws);
   if (s != ALB_OK) return s;
   std::vector<int64_t> thr((size_t)count);
-  auto run = [&](int32_t wg, double *ms) {
+  std::vector<int32_t> cut(2 * (size_t)count);
+  auto run = [&](int32_t wg, bool with_cut, double *ms) {
     alb_options o = b;
     o.mode = ALB_MODE_ALB;
     o.wg_size = wg;
     o.wave_cutoff = 64;
     o.wg_cutoff = wg;
     o.grid_wgs = 0;
-    return time_batch(g, op, count, members, sources, thr.data(), o, &ws, ms);
+    return time_batch(g, op, count, members, sources, thr.data(), with_cut ? cut.data() : nullptr, o, &ws, ms);
   };
-  // stage 1: one threshold for every query, over the paper's plateau
-  // (2^8 .. 2^18, every factor of 4 up to 2^14) and both workgroup sizes
   static const int32_t wgs[] = {256, 1024};
   static const int64_t thrs[] = {256, 1024, 4096, 16384};
   double best = 1e30;
@@ -1941,7 +1981,7 @@ alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const in
     for (int64_t t : thrs) {
       std::fill(thr.begin(), thr.end(), t);
       double ms = 0;
-      s = run(wg, &ms);
+      s = run(wg, false, &ms);
       if (s != ALB_OK) break;
       if (ms < best) {
         best = ms;
@@ -1951,45 +1991,151 @@ alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const in
     }
     if (s != ALB_OK) break;
   }
-  // stage 2: per degree signature, largest edge share first (at most 8
-  // groups), try a threshold 4x lower and 4x higher for that group alone; a
-  // change must gain at least 1 %
+  out->uniform_ms = best;
   std::map<TuneKey, int64_t> gthr;
-  for (auto &kv : groups) gthr[kv.first] = best_t;
-  if (s == ALB_OK) {
-    std::vector<std::pair<int64_t, TuneKey>> order;
-    for (auto &kv : group_edges) order.push_back({-kv.second, kv.first});
-    std::sort(order.begin(), order.end());
+  std::map<TuneKey, std::pair<int32_t, int32_t>> gcut;
+  for (auto &kv : groups) {
+    gthr[kv.first] = best_t;
+    gcut[kv.first] = {64, best_wg};
+  }
+  std::vector<std::pair<int64_t, TuneKey>> order;
+  for (auto &kv : group_edges) order.push_back({-kv.second, kv.first});
+  std::sort(order.begin(), order.end());
+  auto fill = [&] {
+    for (int32_t q = 0; q < count; ++q) {
+      thr[(size_t)q] = gthr[key[(size_t)q]];
+      cut[2 * (size_t)q] = gcut[key[(size_t)q]].first;
+      cut[2 * (size_t)q + 1] = gcut[key[(size_t)q]].second;
+    }
+  };
+  for (size_t gi = 0; gi < order.size() && gi < 8 && s == ALB_OK; ++gi) {
+    const TuneKey &k = order[gi].second;
+    const int64_t cur = gthr[k];
+    for (int64_t t : {cur / 4, cur * 4}) {
+      if (t < 64 || t > ((int64_t)1 << 20)) continue;
+      const int64_t keep = gthr[k];
+      gthr[k] = t;
+      fill();
+      double ms = 0;
+      s = run(best_wg, false, &ms);
+      if (s != ALB_OK) break;
+      if (ms < 0.99 * best)
+        best = ms;
+      else
+        gthr[k] = keep;
+    }
+  }
+  if (cutoffs) {
     for (size_t gi = 0; gi < order.size() && gi < 8 && s == ALB_OK; ++gi) {
       const TuneKey &k = order[gi].second;
-      const int64_t cur = gthr[k];
-      for (int64_t t : {cur / 4, cur * 4}) {
-        if (t < 64 || t > ((int64_t)1 << 20)) continue;
-        for (int32_t q = 0; q < count; ++q) thr[q] = gthr[tune_key(g, op, members[q])];
-        for (int32_t q : groups[k]) thr[q] = t;
+      const std::pair<int32_t, int32_t> cands[] = {{32, best_wg}, {128, best_wg}, {64, 2 * best_wg}, {64, 4 * best_wg}};
+      for (const auto &c : cands) {
+        const auto keep = gcut[k];
+        gcut[k] = c;
+        fill();
         double ms = 0;
-        s = run(best_wg, &ms);
+        s = run(best_wg, true, &ms);
         if (s != ALB_OK) break;
-        if (ms < 0.99 * best) {
+        if (ms < 0.99 * best)
           best = ms;
-          gthr[k] = t;
-        }
+        else
+          gcut[k] = keep;
       }
     }
   }
   ws.release();
   if (s != ALB_OK) return s;
+  out->wg = best_wg;
+  out->thr = gthr;
+  out->cut = gcut;
+  out->best_ms = best;
+  return ALB_OK;
+}
+
+alb_status check_tune_args(alb_graph g, int32_t algo, int32_t count, const int32_t *members, const int32_t *sources) {
+  if (!g || !members || !sources) return fail(ALB_E_INVAL, "NULL argument");
+  if (algo != ALB_ALGO_BFS && algo != ALB_ALGO_SSSP) return fail(ALB_E_UNSUPPORTED, "algo %d cannot be tuned", algo);
+  if (count < 1 || count > kMaxBatch) return fail(ALB_E_INVAL, "count %d not in [1, %d]", count, kMaxBatch);
+  const int32_t nmem = (int32_t)g->mem_n.size();
+  for (int32_t q = 0; q < count; ++q)
+    if (members[q] < 0 || members[q] >= nmem) return fail(ALB_E_INVAL, "members[%d] out of range", q);
+  return ALB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+alb_status alb_autotune_batch(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                              const int32_t *sources, const alb_options *base, alb_options *tuned,
+                              int64_t *thresholds) {
+  if (!tuned || !thresholds) return fail(ALB_E_INVAL, "NULL argument");
+  alb_status s = check_tune_args(g, algo, count, members, sources);
+  if (s != ALB_OK) return s;
+  alb_options b;
+  s = resolve_options(base, b);
+  if (s != ALB_OK) return s;
+  const OpKind op = algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP;
+  // cached by the batch's multiset of member signatures
+  std::vector<TuneKey> sig;
+  for (int32_t q = 0; q < count; ++q) sig.push_back(tune_key(g, op, members[q]));
+  std::sort(sig.begin(), sig.end());
+  const auto ckey = std::make_pair((int)op, sig);
+  std::pair<int32_t, std::map<TuneKey, int64_t>> res;
+  bool cached = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_batch[ckey] = std::make_pair(best_wg, gthr);
+    auto it = g_tune_batch.find(ckey);
+    if (it != g_tune_batch.end()) {
+      res = it->second;
+      cached = true;
+    }
+  }
+  if (!cached) {
+    BatchTune bt;
+    s = tune_batch(g, op, count, members, sources, b, false, &bt);
+    if (s != ALB_OK) return s;
+    res = std::make_pair(bt.wg, bt.thr);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_batch[ckey] = res;
   }
   b.mode = ALB_MODE_ALB;
-  b.wg_size = best_wg;
+  b.wg_size = res.first;
   b.wave_cutoff = 64;
-  b.wg_cutoff = best_wg;
+  b.wg_cutoff = res.first;
   b.huge_threshold = ALB_THRESHOLD_DEFAULT;
-  for (int32_t q = 0; q < count; ++q) thresholds[q] = gthr[tune_key(g, op, members[q])];
+  for (int32_t q = 0; q < count; ++q) thresholds[q] = res.second[tune_key(g, op, members[q])];
   *tuned = b;
+  return ALB_OK;
+}
+
+alb_status alb_autotune_batch_tuned(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                                    const int32_t *sources, const alb_options *base, alb_options *tuned,
+                                    alb_query_tuning *tuning, double *uniform_ms, double *tuned_ms) {
+  if (!tuned || !tuning) return fail(ALB_E_INVAL, "NULL argument");
+  alb_status s = check_tune_args(g, algo, count, members, sources);
+  if (s != ALB_OK) return s;
+  alb_options b;
+  s = resolve_options(base, b);
+  if (s != ALB_OK) return s;
+  const OpKind op = algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP;
+  BatchTune bt;
+  s = tune_batch(g, op, count, members, sources, b, true, &bt);
+  if (s != ALB_OK) return s;
+  b.mode = ALB_MODE_ALB;
+  b.wg_size = bt.wg;
+  b.wave_cutoff = 64;
+  b.wg_cutoff = bt.wg;
+  b.huge_threshold = ALB_THRESHOLD_DEFAULT;
+  for (int32_t q = 0; q < count; ++q) {
+    const TuneKey k = tune_key(g, op, members[q]);
+    tuning[q].huge_threshold = bt.thr[k];
+    tuning[q].wave_cutoff = bt.cut[k].first;
+    tuning[q].wg_cutoff = bt.cut[k].second;
+  }
+  *tuned = b;
+  if (uniform_ms) *uniform_ms = bt.uniform_ms;
+  if (tuned_ms) *tuned_ms = bt.best_ms;
   return ALB_OK;
 }
 
@@ -2000,9 +2146,13 @@ alb_status alb_autotune_reset(void) {
   return ALB_OK;
 }
 
-alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
-                                 const int32_t *sources, int32_t *const *outs, const int64_t *thresholds,
-                                 const alb_options *opt, alb_plan *out) {
+}  // extern "C"
+
+namespace {
+
+alb_status plan_create(alb_graph g, int32_t algo, int32_t count, const int32_t *members, const int32_t *sources,
+                       int32_t *const *outs, const int64_t *thresholds, const int32_t *cutoffs,
+                       const alb_options *opt, alb_plan *out) {
   if (!out) return fail(ALB_E_INVAL, "output handle pointer is NULL");
   *out = nullptr;
   if (algo != ALB_ALGO_BFS && algo != ALB_ALGO_SSSP) return fail(ALB_E_UNSUPPORTED, "algo %d cannot be batched", algo);
@@ -2016,7 +2166,7 @@ alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const
     return st;
   };
   alb_status s = prepare_batch(g, algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP, count, members, sources, outs, thresholds,
-                               opt, p->j);
+                               cutoffs, opt, p->j);
   if (s != ALB_OK) return bail(s);
   p->g = g;
   p->outs.assign(outs, outs + count);
@@ -2043,6 +2193,27 @@ alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const
   g->plans.fetch_add(1);
   *out = p;
   return ALB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+alb_status alb_batch_plan_create(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                                 const int32_t *sources, int32_t *const *outs, const int64_t *thresholds,
+                                 const alb_options *opt, alb_plan *out) {
+  return plan_create(g, algo, count, members, sources, outs, thresholds, nullptr, opt, out);
+}
+
+alb_status alb_batch_plan_create_tuned(alb_graph g, int32_t algo, int32_t count, const int32_t *members,
+                                       const int32_t *sources, int32_t *const *outs, const alb_query_tuning *tuning,
+                                       const alb_options *opt, alb_plan *out) {
+  if (out) *out = nullptr;
+  std::vector<int64_t> thr;
+  std::vector<int32_t> cut;
+  alb_status s = split_tuning(count, tuning, thr, cut);
+  if (s != ALB_OK) return s;
+  return plan_create(g, algo, count, members, sources, outs, thr.data(), cut.data(), opt, out);
 }
 
 alb_status alb_batch_plan_run(alb_plan p, alb_stats *stats) {
@@ -2099,5 +2270,267 @@ alb_status batch_resident_workgroups(alb_graph g, int32_t algo, int32_t wg, int 
   HIP_TRY(hipSetDevice(g->device));
   return resident_workgroups(g, algo == ALB_ALGO_BFS ? OP_BFS : OP_SSSP, wg, out, true);
 }
+
+// --------------------------------------------------------------------------
+// Continuous serving: one lane's persistent launch that queries join between
+// rounds (k_open), its workspace and the rings shared with it.
+// --------------------------------------------------------------------------
+
+struct OpenLane {
+  alb_graph g = nullptr;
+  alb_options o;
+  OpKind op = OP_BFS;  // of the current launch
+  int wg = 256, grid = 1, grid_cap = 1;
+  int64_t max_m = 0;
+  int32_t slots = 0;
+  long long label_cap = 0;
+  uint64_t qcap = 0;
+  uint32_t hint_cap = 0;
+  int64_t threshold = 0, small_threshold = 0;
+  bool adaptive = false;
+  // device
+  unsigned long long *q0 = nullptr, *q1 = nullptr, *word = nullptr, *bar = nullptr;
+  int4 *huge_rec = nullptr;
+  int2 *hint = nullptr;
+  long long *qoff = nullptr, *qlbase = nullptr;
+  int32_t *qsrc = nullptr, *qn = nullptr, *q_last = nullptr, *q_active = nullptr, *q_admit = nullptr;
+  int32_t *q_conv = nullptr;  // finished slots per round
+  int32_t *q_unit = nullptr;  // per slot: BFS (unit weights)
+  Ctl *ctl = nullptr;
+  // pinned host
+  OpenShared *sh = nullptr;     // coherent: read and written while the launch runs
+  OpenShared *sh_dev = nullptr; // its device address
+  Ctl *h_ctl = nullptr;
+  // int32 labels of finished queries at their label indices: written by the
+  // launch (over the bus) into pinned host memory, read by the host without
+  // any copy command, so nothing waits behind the running launch
+  int32_t *out = nullptr, *out_dev = nullptr;
+  unsigned long long published = 0, completed = 0;
+  size_t bytes = 0;
+};
+
+void open_lane_destroy(OpenLane *L) {
+  if (!L) return;
+  void *d[] = {L->q0, L->q1, L->word, L->bar, L->huge_rec, L->hint, L->qoff, L->qlbase, L->qsrc, L->qn,
+               L->q_last, L->q_active, L->q_admit, L->q_conv, L->q_unit, L->ctl};
+  for (void *x : d) (void)hipFree(x);
+  if (L->sh) (void)hipHostFree(L->sh);
+  if (L->h_ctl) (void)hipHostFree(L->h_ctl);
+  if (L->out) (void)hipHostFree(L->out);
+  delete L;
+}
+
+alb_status open_lane_create(alb_graph g, const alb_options &o, int32_t slots, long long label_cap, int grid_cap,
+                            OpenLane **out) {
+  *out = nullptr;
+  if (!g) return fail(ALB_E_INVAL, "graph handle is NULL");
+  if (slots < 1 || slots > kOpenRing) return fail(ALB_E_INVAL, "slots must be in [1, %d]", kOpenRing);
+  if (label_cap < 1 || label_cap > 0xfffffffeLL) return fail(ALB_E_INVAL, "label capacity out of range");
+  OpenLane *L = new (std::nothrow) OpenLane();
+  if (!L) return fail(ALB_E_NOMEM, "host allocation failed");
+  auto bail = [&](alb_status st) {
+    open_lane_destroy(L);
+    return st;
+  };
+  L->g = g;
+  L->o = o;
+  L->wg = o.wg_size ? o.wg_size : 256;
+  L->grid_cap = grid_cap;
+  L->slots = slots;
+  L->label_cap = label_cap;
+  L->qcap = (uint64_t)label_cap;  // every (slot, vertex) enters a round's worklist at most once
+  if (!supported_wg(L->wg)) return bail(fail(ALB_E_UNSUPPORTED, "wg_size %d not built", L->wg));
+  if (hipSetDevice(g->device) != hipSuccess) return bail(fail(ALB_E_DEVICE, "hipSetDevice failed"));
+  int32_t max_n = 1;
+  int32_t max_deg = 1;
+  int64_t max_m = 0;
+  for (size_t i = 0; i < g->mem_n.size(); ++i) {
+    max_n = std::max(max_n, g->mem_n[i]);
+    max_deg = std::max(max_deg, g->mem_maxdeg[i]);
+    max_m = std::max(max_m, g->mem_m[i]);
+  }
+  // one round's huge edges stay below 2^32 (the host admits queries while
+  // their members' edges sum below that)
+  L->hint_cap = hint_entries(L->qcap, 0xfffffffeLL, max_deg);
+  L->max_m = max_m;
+  hipError_t e;
+  const size_t S = (size_t)slots;
+  if ((e = dalloc(&L->q0, L->qcap, L->bytes)) != hipSuccess || (e = dalloc(&L->q1, L->qcap, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->huge_rec, L->qcap, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->hint, L->hint_cap, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->bar, kBarWords, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->word, (size_t)label_cap, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->qoff, S, L->bytes)) != hipSuccess || (e = dalloc(&L->qlbase, S, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->qsrc, S, L->bytes)) != hipSuccess || (e = dalloc(&L->qn, S, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->q_last, S, L->bytes)) != hipSuccess || (e = dalloc(&L->q_active, S, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->q_admit, 2 * (size_t)kOpenRing, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->q_conv, 2 * (size_t)kOpenRing, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->q_unit, S, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->ctl, 1, L->bytes)) != hipSuccess)
+    return bail(fail(e == hipErrorOutOfMemory ? ALB_E_NOMEM : ALB_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e)));
+  if (alloc_failure_injected()) return bail(fail(ALB_E_NOMEM, "hipHostMalloc: out of memory"));
+  if ((e = hipHostMalloc((void **)&L->sh, sizeof(OpenShared), hipHostMallocCoherent | hipHostMallocMapped)) !=
+          hipSuccess ||
+      (e = hipHostMalloc((void **)&L->h_ctl, sizeof(Ctl), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&L->out, sizeof(int32_t) * (size_t)label_cap,
+                         hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
+    return bail(fail(e == hipErrorOutOfMemory ? ALB_E_NOMEM : ALB_E_DEVICE, "hipHostMalloc: %s",
+                     hipGetErrorString(e)));
+  std::memset((void *)L->sh, 0, sizeof(OpenShared));
+  if ((e = hipHostGetDevicePointer((void **)&L->sh_dev, L->sh, 0)) != hipSuccess ||
+      (e = hipHostGetDevicePointer((void **)&L->out_dev, L->out, 0)) != hipSuccess)
+    return bail(fail(ALB_E_DEVICE, "hipHostGetDevicePointer: %s", hipGetErrorString(e)));
+  *out = L;
+  return ALB_OK;
+}
+
+// Start a launch on stream s (the previous one, if any, has ended): clear
+// the rings and the device state, then the persistent kernel.
+alb_status open_lane_start(OpenLane *L, hipStream_t s, double idle_us, int64_t edges) {
+  alb_graph g = L->g;
+  HIP_TRY(hipSetDevice(g->device));
+  L->op = OP_SSSP;  // BFS queries run as unit-weight shortest paths beside the SSSP ones
+  int resident = 0;
+  alb_status st = resident_workgroups(g, L->op, L->wg, &resident, false, true);
+  if (st != ALB_OK) return st;
+  // the automatic grid of the work queued when the launch starts, at most
+  // the lane's share: a grid barrier costs more the more workgroups join
+  // it, and a stream of small queries wants few
+  L->grid = std::max(1, std::min(auto_grid(std::max<int64_t>(edges, 1), L->wg, resident), L->grid_cap));
+  const alb_options &o = L->o;
+  if (o.mode == ALB_MODE_TWC_ONLY)
+    L->threshold = INT64_MAX;
+  else if (o.mode == ALB_MODE_LB_ALL)
+    L->threshold = 0;
+  else if (o.huge_threshold >= 0)
+    L->threshold = o.huge_threshold;
+  else if (o.huge_threshold == ALB_THRESHOLD_LAUNCHED)
+    L->threshold = -1;
+  else
+    L->threshold = default_threshold(L->max_m, L->grid);
+  L->adaptive = o.mode == ALB_MODE_ALB &&
+                (o.huge_threshold == ALB_THRESHOLD_ADAPTIVE || o.huge_threshold == ALB_THRESHOLD_DEFAULT);
+  L->small_threshold = o.huge_threshold == ALB_THRESHOLD_ADAPTIVE ? (int64_t)kAdaptiveSmall
+                                                                  : default_small_threshold(L->op, L->threshold);
+  std::memset((void *)L->sh, 0, sizeof(OpenShared));
+  L->published = L->completed = 0;
+  Args a;
+  std::memset(&a, 0, sizeof a);
+  a.off = g->d_off;
+  a.col = g->d_col;
+  a.w = g->d_w;
+  a.n = g->n;
+  a.qcap = (uint32_t)L->qcap;
+  a.q0 = L->q0;
+  a.q1 = L->q1;
+  a.huge_rec = L->huge_rec;
+  a.hint = L->hint;
+  a.hint_cap = L->hint_cap;
+  a.bar = L->bar;
+  a.ctl = L->ctl;
+  a.threshold = L->threshold;
+  a.c_wave = 64;
+  a.c_wg = L->wg;
+  a.dedup = 1;
+  a.adaptive = L->adaptive ? 1 : 0;
+  a.small_threshold = L->small_threshold;
+  a.max_rounds = INT32_MAX;
+  a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
+  a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);
+  a.word = L->word;
+  a.nq = L->slots;
+  a.qoff = L->qoff;
+  a.qlbase = L->qlbase;
+  a.qsrc = L->qsrc;
+  a.qn = L->qn;
+  a.nlabels = L->label_cap;
+  a.open = L->sh_dev;
+  a.q_last = L->q_last;
+  a.q_active = L->q_active;
+  a.q_admit = L->q_admit;
+  a.q_conv = L->q_conv;
+  a.q_unit = L->q_unit;
+  a.open_out = L->out_dev;
+  a.nslots = L->slots;
+  a.idle_ticks = (uint64_t)std::max(1.0, idle_us * (double)g->clock_khz / 1000.0);
+  HIP_TRY(launch_init_open(a, s));
+  HIP_TRY(launch_open(L->op, L->wg, L->grid, a, s));
+  return ALB_OK;
+}
+
+bool open_lane_running(OpenLane *L, hipStream_t s) {
+  (void)L;
+  return hipStreamQuery(s) == hipErrorNotReady;
+}
+
+// Requests the launch has not taken yet.
+uint64_t open_lane_backlog(OpenLane *L) {
+  const uint64_t head = __atomic_load_n(&L->sh->head, __ATOMIC_ACQUIRE);
+  return L->published - head;
+}
+
+// Publish one request into `slot`, its labels at [lbase, lbase + n).
+alb_status open_lane_publish(OpenLane *L, int32_t algo, int32_t slot, int32_t member, int32_t source,
+                             long long lbase) {
+  alb_graph g = L->g;
+  if (member < 0 || member >= (int32_t)g->mem_n.size()) return fail(ALB_E_INVAL, "member out of range");
+  if (algo == ALB_ALGO_SSSP && !g->weighted) return fail(ALB_E_INVAL, "SSSP needs a graph set created with weights");
+  if (L->published - __atomic_load_n(&L->sh->head, __ATOMIC_ACQUIRE) >= (uint64_t)kOpenRing)
+    return fail(ALB_E_INVAL, "request ring full");
+  OpenReq &q = L->sh->req[L->published % kOpenRing];
+  q.slot = slot;
+  q.unit = algo == ALB_ALGO_BFS ? 1 : 0;
+  q.src = g->mem_vbase[member] + source;
+  q.n = g->mem_n[member];
+  q.qoff = lbase - g->mem_vbase[member];
+  q.lbase = lbase;
+  ++L->published;
+  __atomic_store_n(&L->sh->tail, L->published, __ATOMIC_RELEASE);
+  return ALB_OK;
+}
+
+// Slots whose query finished since the last call (at most max of them).
+int32_t open_lane_poll(OpenLane *L, int32_t *slots, int32_t max) {
+  const uint64_t done = __atomic_load_n(&L->sh->done, __ATOMIC_ACQUIRE);
+  int32_t k = 0;
+  while (L->completed < done && k < max) {
+    slots[k++] = __atomic_load_n(&L->sh->fin[L->completed % kOpenRing], __ATOMIC_RELAXED);
+    ++L->completed;
+  }
+  return k;
+}
+
+// Copy a finished query's labels (n of them from lbase) into the caller's
+// host array.
+// A finished query's int32 labels (n of them from lbase, already in pinned
+// host memory) into the caller's host array.
+void open_lane_copy_out(OpenLane *L, long long lbase, int32_t n, int32_t *out) {
+  std::memcpy(out, L->out + lbase, sizeof(int32_t) * (size_t)n);
+}
+
+// After the launch's stream has finished: its status, and its device window.
+alb_status open_lane_finish(OpenLane *L, hipStream_t s, double *begin_ms, double *end_ms) {
+  HIP_TRY(hipMemcpyAsync(L->h_ctl, L->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const Ctl &c = *L->h_ctl;
+  *begin_ms = (double)c.t_begin / (double)L->g->clock_khz;
+  *end_ms = (double)c.t_end / (double)L->g->clock_khz;
+  if (c.abort) return abort_error(c);
+  if (c.overflow != 0xffffffffu)
+    return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %llu entries in round %u",
+                (unsigned long long)L->qcap, c.overflow);
+  return ALB_OK;
+}
+
+void open_lane_stop(OpenLane *L) { __atomic_store_n(&L->sh->stop, 1u, __ATOMIC_RELEASE); }
+
+int32_t open_lane_untaken(OpenLane *L, int32_t *slots, int32_t max) {
+  const uint64_t head = __atomic_load_n(&L->sh->head, __ATOMIC_ACQUIRE);
+  int32_t k = 0;
+  for (uint64_t i = head; i < L->published && k < max; ++i) slots[k++] = L->sh->req[i % kOpenRing].slot;
+  return k;
+}
+
+static_assert(kOpenMaxSlots == kOpenRing, "the server's slot bound is the rings' size");
 
 }  // namespace alb

@@ -53,6 +53,32 @@ constexpr int32_t kMaxBatch = 65535;
 // vertices with the default worklist capacity.
 constexpr size_t kNoAllocScratchBytes = (size_t)192 << 20;
 
+// Continuous serving (alb_server with join_running): requests join a running
+// persistent batch launch between rounds; BFS and SSSP queries share it (BFS
+// as shortest paths with unit weights, whose distances are the levels).  The
+// host publishes requests in a ring of pinned, coherent host memory; the
+// launch takes them at the end of a round's first phase into free query
+// slots (label ranges assigned by the host) and publishes the slots whose
+// query has finished in a second ring.
+constexpr int kOpenRing = 1024;  // entries of each ring; also the most slots of one launch
+struct OpenReq {
+  int32_t slot;    // query slot in [0, slots)
+  int32_t src;     // source vertex (graph-set id)
+  int32_t n;       // vertices of its member
+  int32_t unit;    // 1: BFS (every edge weighs 1), 0: SSSP with the graph's weights
+  long long qoff;  // label index of (slot, vertex v) = qoff + v
+  long long lbase; // first label index of the slot (= qoff + member base)
+};
+struct OpenShared {
+  alignas(256) unsigned long long tail;  // requests published (host)
+  alignas(256) unsigned long long head;  // requests taken (device)
+  alignas(256) unsigned long long done;  // completions published (device)
+  alignas(256) uint32_t stop;            // host: end the launch as soon as no query is active
+  alignas(256) uint32_t live;            // device: 1 while the launch runs its rounds
+  alignas(256) OpenReq req[kOpenRing];   // request i at req[i % kOpenRing]
+  int32_t fin[kOpenRing];                // slot of completion i at fin[i % kOpenRing]
+};
+
 // Per-call control block in device memory.  Counters rotate by round so that
 // one round can clear the counter two rounds ahead without a separate launch.
 struct Ctl {
@@ -86,6 +112,18 @@ struct Ctl {
   // persistent launch: device wall-clock ticks when its first member joined
   // and when member 0 left the round loop
   unsigned long long t_begin, t_end;
+  // continuous serving (member 0's bookkeeping): requests taken, slots
+  // admitted in round r, its exit decision and the slots it converts
+  // (finished in round r - 1), each at [r & 1] (a slow member may still read
+  // round r's entry while member 0 writes round r + 1's), completions
+  // published, active slots and the start of the current idle spell
+  alignas(256) unsigned long long open_head;
+  uint32_t admit_n[2];
+  uint32_t open_exit[2];
+  uint32_t conv_n[2];
+  unsigned long long open_done;
+  uint32_t open_active;
+  unsigned long long idle_since;
 };
 constexpr int kTimeline = 64;
 // With Args::prof_wg: edges each member workgroup processed in each of the
@@ -146,8 +184,21 @@ struct Args {
   const long long *qlbase; // first label index of query q
   const int32_t *qsrc;     // source vertex of query q (graph-set vertex id)
   const int32_t *qn;       // vertex count of query q's graph
+  const int32_t *qcut;     // per-query TWC cutoffs: wavefront bin at [2q], workgroup bin at [2q + 1], or null
   int32_t *const *qout;    // output array of query q
   long long nlabels;       // labels of all queries
+  // continuous serving: the shared rings (pinned host memory, device
+  // address), per-slot round of the last worklist entry, active flags, and
+  // how long an idle launch waits for work
+  OpenShared *open;
+  int32_t *q_last;
+  int32_t *q_active;
+  int32_t *q_admit;     // [2][kOpenRing]: slots admitted in round r ([r & 1])
+  int32_t *q_unit;      // per slot: 1 = a BFS query, run as shortest paths with unit weights
+  int32_t *q_conv;      // [2][kOpenRing]: slots whose labels round r writes to open_out ([r & 1])
+  int32_t *open_out;    // int32 labels of finished queries, at the slot's label indices
+  int32_t nslots;
+  uint64_t idle_ticks;
 };
 
 // Host-callable launchers (alb_kernels.hip).  All return the launch status.
@@ -173,6 +224,13 @@ hipError_t batch_occupancy(OpKind op, int wg, int *blocks_per_cu);
 hipError_t launch_init_batch(OpKind op, const Args &a, hipStream_t s);
 hipError_t launch_batch(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
 hipError_t launch_finish_batch(OpKind op, const Args &a, int32_t max_n, hipStream_t s);
+// Continuous serving: clear the control block, barrier words and slot flags
+// (no query yet), then the persistent launch that admits queries from
+// Args::open between rounds until it is idle for Args::idle_ticks or asked to
+// stop (BFS and SSSP).
+hipError_t launch_init_open(const Args &a, hipStream_t s);
+hipError_t launch_open(OpKind op, int wg, int grid, const Args &a, hipStream_t s);
+hipError_t open_occupancy(OpKind op, int wg, int *blocks_per_cu);
 // Device address of this GPU's scratch array (kNoAllocScratchBytes, 256-byte
 // aligned), looked up on the first call for `device` and kept (alb_noalloc.hip).
 hipError_t noalloc_scratch(int device, void **ptr);

@@ -101,7 +101,7 @@ struct OpBFS {
   __device__ __forceinline__ val_t load_src(long long, int32_t, uint32_t tag, bool &) const {
     return (int32_t)tag - 1;
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t) const { return {level[dl]}; }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const { return {level[dl]}; }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
     if (p.cur != kInf) return false;
@@ -154,13 +154,24 @@ struct OpSSSP {  // relaxation: dist[dst] = min(dist[dst], dist[src] + w)
   // 32 unsigned bits.  A sum beyond INT32_MAX - 1 is never a shortest
   // distance (graph creation bounds those by max(w) * (n - 1)), so dropping
   // it changes no result.
-  __device__ __forceinline__ pre_t prepare(int32_t pos, long long dl, val_t sv) const {
+  __device__ __forceinline__ pre_t prepare(int32_t pos, long long dl, val_t sv, int32_t) const {
     const uint32_t c = (uint32_t)sv + (uint32_t)w[pos];
     return {(int32_t)min(c, (uint32_t)kInf), word[dl]};
   }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t, int32_t, int32_t,
                                          uint32_t tag) const {
     return lower_word(&word[dl], p.cand, p.cur, tag, dedup);
+  }
+};
+
+// Continuous serving: BFS and SSSP queries in one launch.  A query slot
+// flagged unit relaxes every edge with weight 1, so its distances are BFS
+// levels; the others use the graph's weights.
+struct OpServe : OpSSSP {
+  const int32_t *unit;  // per query slot
+  __device__ __forceinline__ pre_t prepare(int32_t pos, long long dl, val_t sv, int32_t q) const {
+    const uint32_t c = (uint32_t)sv + (unit[q] ? 1u : (uint32_t)w[pos]);
+    return {(int32_t)min(c, (uint32_t)kInf), word[dl]};
   }
 };
 
@@ -175,7 +186,7 @@ struct OpCC {  // min-label propagation
   __device__ __forceinline__ val_t load_src(long long sl, int32_t, uint32_t tag, bool &skip) const {
     return label_of_active(word[sl], tag, skip);
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t) const { return {word[dl]}; }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const { return {word[dl]}; }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t tag) const {
     return lower_word(&word[dl], sv, p.cur, tag, dedup);
@@ -198,7 +209,7 @@ struct OpKCore {
     if (tag == 1u) skip = deg >= k;
     return 0;
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t) const { return {}; }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t, int32_t) const { return {}; }
   __device__ __forceinline__ bool commit(const pre_t &, int32_t, long long dl, val_t, int32_t, int32_t,
                                          uint32_t) const {
     return __hip_atomic_fetch_add(&rem[dl], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k;
@@ -214,7 +225,7 @@ struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact 
   __device__ __forceinline__ val_t load_src(long long sl, int32_t deg, uint32_t, bool &) const {
     return rank[sl] / (float)deg;
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t) const { return {}; }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t, int32_t) const { return {}; }
   __device__ __forceinline__ bool commit(const pre_t &, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
     add_relaxed(&acc[dl], to_fix(sv));
@@ -229,7 +240,7 @@ struct OpRecord {  // counts each processed edge and the thread that took it; pu
   int32_t *hits;
   int32_t *thread_of;
   __device__ __forceinline__ val_t load_src(long long, int32_t, uint32_t, bool &) const { return 0; }
-  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t) const { return {}; }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long, val_t, int32_t) const { return {}; }
   __device__ __forceinline__ bool commit(const pre_t &, int32_t pos, long long, val_t, int32_t, int32_t gt,
                                          uint32_t) const {
     add_relaxed(&hits[pos], 1);
@@ -244,6 +255,15 @@ template <>
 OpBFS make_op<OpBFS>(const Args &a) { return OpBFS{a.level}; }
 template <>
 OpSSSP make_op<OpSSSP>(const Args &a) { return OpSSSP{a.word, a.w, a.dedup}; }
+template <>
+OpServe make_op<OpServe>(const Args &a) {
+  OpServe o;
+  o.word = a.word;
+  o.w = a.w;
+  o.dedup = a.dedup;
+  o.unit = a.q_unit;
+  return o;
+}
 template <>
 OpCC make_op<OpCC>(const Args &a) { return OpCC{a.word, a.dedup}; }
 template <>
@@ -499,7 +519,7 @@ __device__ __forceinline__ void edges(const bool (&act)[kU], const int32_t (&pos
       dl[u] = act[u] ? dst[u] : 0;
   }
 #pragma unroll
-  for (int u = 0; u < kU; ++u) pre[u] = op.prepare(act[u] ? pos[u] : 0, dl[u], sv[u]);
+  for (int u = 0; u < kU; ++u) pre[u] = op.prepare(act[u] ? pos[u] : 0, dl[u], sv[u], src[u]);
   bool p[kU];
 #pragma unroll
   for (int u = 0; u < kU; ++u) p[u] = act[u] && op.commit(pre[u], pos[u], dl[u], sv[u], src[u], gt, tag);
@@ -622,17 +642,31 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
     const bool mine = tid < (int)C && i < nF;
     int32_t v = -1, beg = 0, deg = 0, q = 0;  // q: the entry's query (batch)
     int64_t thr = threshold;
+    int32_t c_wave = a.c_wave, c_wg = a.c_wg;  // TWC cutoffs (a batch's queries may have their own)
     if (mine) {
       if constexpr (M) {
         const unsigned long long e = F[i];
         v = (int32_t)(uint32_t)e;
         q = (int32_t)(e >> 32);
         if (a.qthr) thr = a.qthr[q];
+        if (a.qcut) {
+          c_wave = a.qcut[2 * q];
+          c_wg = a.qcut[2 * q + 1];
+        }
       } else {
         v = F ? F[i] : (int32_t)i;
       }
       beg = a.off[v];
       deg = a.off[v + 1] - beg;
+    }
+    if constexpr (M) {
+      // continuous serving: this round had an entry of query slot q (one
+      // store per run of equal slots in the wavefront)
+      if (a.q_last) {
+        const int32_t qq = mine ? q : -1;
+        const int32_t prev = __shfl_up(qq, 1);
+        if (mine && (lane == 0 || prev != qq)) st_relaxed(&a.q_last[qq], (int32_t)round);
+      }
     }
     V sv = V(0);
     if (deg > 0) {
@@ -646,7 +680,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
     const bool huge = v >= 0 && deg > 0 && (int64_t)deg >= thr;
     reserve_huge(huge, M ? q : v, beg, deg, to_bits(sv), a, round, hctr, hs, acc);
     if constexpr (Op::kRecord) {
-      if (mine) a.bins[i] = (int8_t)(huge ? 3 : deg >= a.c_wg ? 2 : deg >= a.c_wave ? 1 : 0);
+      if (mine) a.bins[i] = (int8_t)(huge ? 3 : deg >= c_wg ? 2 : deg >= c_wave ? 1 : 0);
     }
     if constexpr (Op::kPR) {
       if (v >= 0 && deg == 0) acc.dangling += to_fix(a.rank[v]);
@@ -660,7 +694,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
     for (;;) {
       if (tid == 0) sm.owner = -1;
       __syncthreads();
-      if (deg > 0 && deg >= a.c_wg) sm.owner = tid;  // any one claimant wins
+      if (deg > 0 && deg >= c_wg) sm.owner = tid;  // any one claimant wins
       __syncthreads();
       const int32_t o = sm.owner;
       if (o < 0) break;
@@ -693,7 +727,7 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
     prof_mark(a, acc, kProfWgBin, pt);
     // wavefront bin: one wavefront strides one vertex's edges
     for (;;) {
-      const unsigned long long mm = __ballot(deg > 0 && deg >= a.c_wave);
+      const unsigned long long mm = __ballot(deg > 0 && deg >= c_wave);
       if (mm == 0ull) break;
       const int ld = __ffsll(mm) - 1;
       const int32_t ob = __shfl(beg, ld), od = __shfl(deg, ld), ov = __shfl(M ? q : v, ld);
@@ -1233,6 +1267,246 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
 }
 
 // ---------------------------------------------------------------------------
+// Continuous serving: one persistent batch launch that queries join between
+// rounds.  Round r is two phases, as a batch's:
+//   phase 1  inspection and TWC over round r's worklist (recording, per
+//            slot, that it had an entry this round); workgroup 0 then takes
+//            the requests the host has published into their slots (tables
+//            only) and decides whether the launch ends;
+//   -------- grid barrier
+//   phase 2  workgroup 0 marks the active slots without an entry this round
+//            as finished (their labels have been final since round r - 1);
+//            every member initialises the newly admitted slots' labels and
+//            writes the labels of the slots finished in round r - 1 to
+//            open_out as int32; workgroup 0 appends the new sources to round
+//            r + 1's worklist; then the cyclic phase of round r;
+//   -------- grid barrier
+//   workgroup 0 publishes the slots converted this round to the host.
+// A request published while others are on the device thus starts at the
+// next round boundary, beside them.  Everything member 0 decides for round r
+// (admissions, exit) sits in [r & 1] entries: with only two barriers per
+// round a slow member may still read round r's entry while member 0 already
+// writes round r + 1's.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T ld_sys(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <class T>
+__device__ __forceinline__ void st_sys(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Workgroup 0, thread 0, at the end of round r's phase 1: take the published
+// requests (at most the ring's size; the host bounds them by its free slots)
+// into their slots' tables, list them for phase 2 (admit_n[r & 1]), and
+// decide whether the launch ends after this round's first barrier.
+__device__ void open_admit(const Args &a, int r, uint32_t nF) {
+  Ctl *c = a.ctl;
+  OpenShared *sh = a.open;
+  const unsigned long long tail = ld_sys(&sh->tail);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the entries below were written before the tail
+  const unsigned long long head = c->open_head;
+  int32_t *admit = a.q_admit + (size_t)(r & 1) * kOpenRing;
+  uint32_t k = 0;
+  for (unsigned long long i = head; i < tail && k < (uint32_t)kOpenRing; ++i, ++k) {
+    OpenReq *q = &sh->req[i % kOpenRing];
+    const int32_t slot = ld_sys(&q->slot);
+    if (slot < 0 || slot >= a.nslots) {  // cannot happen with a well-formed ring: stop taking requests
+      flag_overflow(c, r);
+      break;
+    }
+    admit[k] = slot;
+    ((long long *)a.qoff)[slot] = ld_sys(&q->qoff);
+    ((long long *)a.qlbase)[slot] = ld_sys(&q->lbase);
+    ((int32_t *)a.qsrc)[slot] = ld_sys(&q->src);
+    ((int32_t *)a.qn)[slot] = ld_sys(&q->n);
+    a.q_unit[slot] = ld_sys(&q->unit);
+    a.q_last[slot] = r;  // not finished in this round's phase 2: its source is in round r + 1's worklist
+    a.q_active[slot] = 1;
+  }
+  c->open_head = head + k;
+  st_sys(&sh->head, head + k);
+  c->admit_n[r & 1] = k;
+  c->open_active += k;
+  uint32_t ex = 0;
+  const bool idle = k == 0 && nF == 0 && c->open_active == 0 && c->conv_n[r & 1] == 0;
+  if (!idle) {
+    c->idle_since = 0;
+  } else {
+    const uint64_t now = (uint64_t)wall_clock64();
+    if (ld_sys(&sh->stop)) ex = 1;
+    if (c->idle_since == 0) c->idle_since = now;
+    else if (now - c->idle_since > a.idle_ticks) ex = 1;
+    __builtin_amdgcn_s_sleep(8);  // idle: poll the ring less often
+  }
+  c->open_exit[r & 1] = ex;
+}
+
+// Workgroup 0 after round r's first barrier: an active slot without an
+// entry in round r's worklist has finished.  It is listed for round r + 1's
+// conversion (q_conv[(r + 1) & 1], conv_n[(r + 1) & 1]).
+template <int B>
+__device__ void open_complete(const Args &a, int r, uint32_t *s_cnt) {
+  Ctl *c = a.ctl;
+  int32_t *list = a.q_conv + (size_t)((r + 1) & 1) * kOpenRing;
+  if (threadIdx.x == 0) *s_cnt = 0;
+  __syncthreads();
+  for (int32_t q = threadIdx.x; q < a.nslots; q += B) {
+    if (a.q_active[q] && ld_relaxed(&a.q_last[q]) != r) {
+      a.q_active[q] = 0;
+      list[atomicAdd(s_cnt, 1u)] = q;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c->conv_n[(r + 1) & 1] = *s_cnt;
+    c->open_active -= *s_cnt;
+  }
+  __syncthreads();
+}
+
+// Every member in round r's phase 2: the slots admitted in round r get their
+// labels (INF, the source 0); the slots finished in round r - 1 get theirs
+// written to open_out as int32 (SSSP: the distance half of the label word;
+// BFS: the level).  Workgroup 0 then appends the new sources to round
+// r + 1's worklist.
+template <class Op>
+__device__ void open_prepare(const Args &a, Grid gr, int B, int r, uint32_t k, uint32_t nc) {
+  const int32_t *admit = a.q_admit + (size_t)(r & 1) * kOpenRing;
+  for (uint32_t i = 0; i < k; ++i) {
+    const int32_t slot = admit[i];
+    const long long base = a.qlbase[slot];
+    const long long sl = a.qoff[slot] + a.qsrc[slot];
+    const int32_t n = a.qn[slot];
+    for (int32_t v = (int32_t)(gr.id * B + threadIdx.x); v < n; v += (int32_t)(gr.n * B)) {
+      const long long l = base + v;
+      if constexpr (std::is_same<Op, OpBFS>::value)
+        a.level[l] = l == sl ? 0 : kInf;
+      else
+        a.word[l] = l == sl ? 0ull : (unsigned long long)(uint32_t)kInf << 32;
+    }
+  }
+  const int32_t *conv = a.q_conv + (size_t)(r & 1) * kOpenRing;
+  for (uint32_t i = 0; i < nc; ++i) {
+    const int32_t slot = conv[i];
+    const long long base = a.qlbase[slot];
+    const int32_t n = a.qn[slot];
+    for (int32_t v = (int32_t)(gr.id * B + threadIdx.x); v < n; v += (int32_t)(gr.n * B)) {
+      if constexpr (std::is_same<Op, OpBFS>::value)
+        a.open_out[base + v] = a.level[base + v];
+      else
+        a.open_out[base + v] = (int32_t)(a.word[base + v] >> 32);
+    }
+  }
+  if (k && gr.id == 0 && threadIdx.x == 0) {
+    unsigned long long *F = (unsigned long long *)(((r + 1) & 1) ? a.q1 : a.q0);
+    const uint32_t at = add_relaxed(&a.ctl->qcount[(r + 1) % 3], k);  // beside the cyclic phase's pushes
+    for (uint32_t i = 0; i < k; ++i) {
+      const int32_t slot = admit[i];
+      if (at + i < a.qcap)
+        F[at + i] = ((unsigned long long)(uint32_t)slot << 32) | (uint32_t)a.qsrc[slot];
+      else
+        flag_overflow(a.ctl, r);
+    }
+  }
+}
+
+// Workgroup 0, thread 0, after round r's second barrier: the slots converted
+// in round r go to the completion ring after a system-scope release, so
+// that their int32 labels are in memory when the host copies them.
+__device__ void open_publish(const Args &a, int r, uint32_t nc) {
+  Ctl *c = a.ctl;
+  OpenShared *sh = a.open;
+  const int32_t *list = a.q_conv + (size_t)(r & 1) * kOpenRing;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  for (uint32_t j = 0; j < nc; ++j) st_sys(&sh->fin[(c->open_done + j) % kOpenRing], list[j]);
+  c->open_done += nc;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  st_sys(&sh->done, c->open_done);
+}
+
+template <int B, class Op>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER_EU))) void k_open(Args a, Op op) {
+  __shared__ Smem<B, Op, true> sm;
+  __shared__ uint32_t s_cnt;
+  Acc acc;
+  Grid gr;
+  if (!join_members(a, sm, &gr)) return;
+  if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;
+  if (gr.id == 0 && threadIdx.x == 0) st_sys(&a.open->live, 1u);
+  unsigned long long epoch = 0;
+  int r = 0;
+  for (;; ++r) {
+    if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;
+    const uint32_t nF = round_size(a, r);
+    if (gr.id == 0 && threadIdx.x == 0) clear_ahead(a, r);
+    Entry<true> *qn = round_next<true>(a, r);
+    uint32_t *qn_cnt = &a.ctl->qcount[(r + 1) % 3];
+    const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
+    const uint32_t hs = hint_shift(thr);
+    if (nF)
+      phase_twc<B, Op, true>(a, op, sm, gr, r, round_frontier<true>(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1],
+                             thr, hs, acc);
+    if (gr.id == 0 && threadIdx.x == 0) open_admit(a, r, nF);
+    if (!grid_barrier(a, sm, gr, epoch, r)) break;
+    if (ld_relaxed(&a.ctl->open_exit[r & 1])) break;
+    if (gr.id == 0) open_complete<B>(a, r, &s_cnt);
+    const uint32_t k = ld_relaxed(&a.ctl->admit_n[r & 1]);
+    const uint32_t nc = ld_relaxed(&a.ctl->conv_n[r & 1]);
+    open_prepare<Op>(a, gr, B, r, k, nc);
+    const unsigned long long hc = nF ? ld_relaxed(&a.ctl->huge[r & 1]) : 0ull;
+    if ((hc >> 32) != 0) phase_lb<B, Op, true>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+    if (!grid_barrier(a, sm, gr, epoch, r)) break;
+    if (nc && gr.id == 0 && threadIdx.x == 0) open_publish(a, r, nc);
+  }
+  if (gr.id == 0 && threadIdx.x == 0) {
+    st_relaxed(&a.ctl->rounds, (uint32_t)r);
+    st_relaxed(&a.ctl->threshold_used, (long long)a.threshold);
+    st_relaxed(&a.ctl->t_end, (unsigned long long)wall_clock64());
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    st_sys(&a.open->live, 0u);
+  }
+  flush_stats<B, Op>(acc, sm, a.ctl);
+}
+
+// Continuous serving set-up: control block, barrier words, slot flags.
+__global__ void k_init_open(Args a) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (size_t i = t; i < kBarWords; i += stride) a.bar[i] = 0ull;
+  for (size_t i = t; i < (size_t)a.nslots; i += stride) {
+    a.q_active[i] = 0;
+    a.q_last[i] = -1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl *c = a.ctl;
+    c->qcount[0] = c->qcount[1] = c->qcount[2] = 0;
+    c->chunk[0] = c->chunk[1] = c->chunk[2] = 0;
+    c->overflow = 0xffffffffu;
+    c->huge[0] = c->huge[1] = 0;
+    c->abort = 0;
+    c->rounds = 0;
+    c->st_frontier = c->st_edges_twc = c->st_edges_lb = c->st_huge_v = c->st_pushes = 0;
+    c->dangling[0] = c->dangling[1] = 0;
+    c->members = 0;
+    c->n_members = 0;
+    c->diag_seen = c->diag_target = 0;
+    c->diag_round = 0;
+    c->threshold_used = a.threshold;
+    for (int k = 0; k < kProfParts; ++k) c->prof[k] = 0;
+    c->t_begin = c->t_end = 0;
+    c->open_head = 0;
+    c->admit_n[0] = c->admit_n[1] = 0;
+    c->open_done = 0;
+    c->open_active = 0;
+    c->open_exit[0] = c->open_exit[1] = 0;
+    c->conv_n[0] = c->conv_n[1] = 0;
+    c->idle_since = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Pull PageRank (the paper's pr, Section 5): each vertex v sums its
 // in-neighbours' contributions c(u) = rank(u) / outdeg(u) over the transposed
 // graph, so no atomic touches a destination label except for the edges of
@@ -1542,6 +1816,28 @@ struct BatchOccF {
   }
 };
 
+// continuous serving: one operator for BFS and SSSP queries (OP_SSSP)
+template <int B, class Op>
+struct OpenF {
+  static hipError_t run(int grid, const Args *a, hipStream_t s) {
+    if constexpr (std::is_same<Op, OpSSSP>::value) {
+      hipLaunchKernelGGL((k_open<B, OpServe>), dim3(grid), dim3(B), 0, s, *a, make_op<OpServe>(*a));
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+};
+template <int B, class Op>
+struct OpenOccF {
+  static hipError_t run(int *blocks) {
+    if constexpr (std::is_same<Op, OpSSSP>::value)
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_open<B, OpServe>, B, 0);
+    else
+      return hipErrorInvalidValue;
+  }
+};
+
 template <template <int, class> class F, int B, typename... Xs>
 hipError_t by_op(OpKind op, Xs... xs) {
   switch (op) {
@@ -1635,6 +1931,15 @@ hipError_t pull_occupancy(int wg, int *blocks_per_cu) {
   }
   return hipErrorInvalidValue;
 }
+
+hipError_t launch_init_open(const Args &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_open, dim3(64), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_open(OpKind op, int wg, int grid, const Args &a, hipStream_t s) {
+  return by_wg<OpenF>(op, wg, grid, &a, s);
+}
+hipError_t open_occupancy(OpKind op, int wg, int *blocks_per_cu) { return by_wg<OpenOccF>(op, wg, blocks_per_cu); }
 
 hipError_t launch_pull_pr(int wg, int grid, const Args &a, hipStream_t s) {
   switch (wg) {

@@ -7,7 +7,9 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <list>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -35,6 +37,8 @@ constexpr int64_t kMaxPositions = 0xffffffffLL;
 struct Request {
   int32_t algo = 0, member = 0, source = 0;
   int32_t *out = nullptr;
+  int32_t slot = -1;      // continuous batching: its query slot and labels in the lane's launch
+  long long lbase = 0;
   size_t footprint = 0;
   int64_t edges = 0;  // edges of its member
   Clock::time_point t_submit, t_dispatch, t_done, deadline;
@@ -46,6 +50,40 @@ struct Request {
 double ms_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::milli>(b - a).count();
 }
+
+// First-fit ranges of a lane's label memory (continuous batching).
+struct Arena {
+  std::map<long long, long long> free;  // start -> length, disjoint, merged
+  explicit Arena(long long cap) {
+    if (cap > 0) free[0] = cap;
+  }
+  long long take(long long n) {
+    for (auto it = free.begin(); it != free.end(); ++it) {
+      if (it->second >= n) {
+        const long long at = it->first, rest = it->second - n;
+        free.erase(it);
+        if (rest > 0) free[at + n] = rest;
+        return at;
+      }
+    }
+    return -1;
+  }
+  void give(long long at, long long n) {
+    auto it = free.emplace(at, n).first;
+    auto nx = std::next(it);
+    if (nx != free.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free.erase(nx);
+    }
+    if (it != free.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free.erase(it);
+      }
+    }
+  }
+};
 
 }  // namespace
 
@@ -107,7 +145,227 @@ struct alb_server_s {
                                 : alb_sssp_batch(g, n, mb.data(), src.data(), outs.data(), nullptr, &o, nullptr);
   }
 
+  void log_batch(const alb_batch_record &rec) {
+    if (log.size() < kLogSize)
+      log.push_back(rec);
+    else
+      log[log_next] = rec;
+    log_next = (log_next + 1) % kLogSize;
+  }
+
+  // Continuous batching: keep one persistent launch of one algorithm
+  // running; queued requests of that algorithm join it between rounds while
+  // a slot and label memory are free, and complete as soon as their own
+  // traversal has converged.  The launch ends by itself when idle.
+  void lane_main_join(int lane) {
+    const long long cap = (long long)(lane_budget / kBytesPerVertex);
+    const int32_t nslots = std::min(cfg.max_batch, alb::kOpenMaxSlots);
+    alb::OpenLane *L = nullptr;
+    // a single lane takes the whole device, several share it
+    const int grid_cap = cfg.lanes == 1 ? grid_all[ALB_ALGO_SSSP] : grid[ALB_ALGO_SSSP];
+    const alb_status cst = alb::open_lane_create(g, cfg.options, nslots, std::max<long long>(cap, 1), grid_cap, &L);
+    Arena arena(cap);
+    std::vector<uint64_t> slot_ticket((size_t)nslots, 0);
+    std::vector<char> in_use((size_t)nslots, 0);
+    std::vector<int32_t> free_slots;
+    for (int32_t q = nslots - 1; q >= 0; --q) free_slots.push_back(q);
+    std::vector<int32_t> done((size_t)nslots);
+    const double idle_us = cfg.join_idle_us > 0 ? (double)cfg.join_idle_us : 500.0;
+    int64_t *edges_in_launch = nullptr;
+    auto release = [&](Request &r) {
+      if (edges_in_launch) *edges_in_launch -= r.edges;
+      arena.give(r.lbase, member_n[r.member]);
+      free_slots.push_back(r.slot);
+      in_use[(size_t)r.slot] = 0;
+      r.slot = -1;
+    };
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      expire(Clock::now());
+      if (pending.empty()) {
+        if (stop) break;
+        continue;
+      }
+      if (cst != ALB_OK) {  // the lane has no device workspace: fail what it would have run
+        fail_pending(-1, cst, Clock::now());
+        continue;
+      }
+      ++busy_lanes;
+      ++st.batches;
+      int64_t queued_edges = 0;  // sizes the launch's grid
+      {
+        int32_t cnt = 0;
+        for (uint64_t t : pending)
+          if (cnt++ < nslots) queued_edges += reqs[t].edges;
+      }
+      lk.unlock();
+      const Clock::time_point t0 = Clock::now();
+      const alb_status ls = alb::open_lane_start(L, streams[lane], idle_us, queued_edges);
+      lk.lock();
+      if (ls != ALB_OK) {
+        fail_pending(-1, ls, Clock::now());
+        --busy_lanes;
+        continue;
+      }
+      int32_t admitted = 0;
+      int64_t active_edges = 0;  // edges of the members of the queries in the launch (one round's bound)
+      edges_in_launch = &active_edges;
+      for (;;) {
+        // checked first: a launch seen ended has published every completion
+        const bool alive = alb::open_lane_running(L, streams[lane]);
+        // admit queued requests (BFS and SSSP alike), in order, while a
+        // slot, label memory and ring room are free
+        std::vector<Request> todo;
+        expire(Clock::now());
+        if (alive) {
+          uint64_t room = (uint64_t)alb::kOpenMaxSlots - alb::open_lane_backlog(L);
+          for (auto it = pending.begin(); it != pending.end() && !free_slots.empty() && room > 0;) {
+            Request &r = reqs[*it];
+            if (active_edges + r.edges >= kMaxPositions) break;  // one round's huge edges stay 32-bit
+            const long long at = arena.take(member_n[r.member]);
+            if (at < 0) break;  // wait for memory: later requests do not overtake
+            active_edges += r.edges;
+            r.slot = free_slots.back();
+            free_slots.pop_back();
+            in_use[(size_t)r.slot] = 1;
+            r.lbase = at;
+            r.state = kRunning;
+            r.t_dispatch = Clock::now();
+            slot_ticket[(size_t)r.slot] = *it;
+            todo.push_back(r);
+            ++running;
+            ++admitted;
+            --room;
+            it = pending.erase(it);
+          }
+        }
+        lk.unlock();
+        std::vector<std::pair<uint64_t, alb_status>> fin;
+        for (const Request &r : todo) {
+          const alb_status ps = alb::open_lane_publish(L, r.algo, r.slot, r.member, r.source, r.lbase);
+          if (ps != ALB_OK) fin.emplace_back(slot_ticket[(size_t)r.slot], ps);  // never published
+        }
+        // completions: each finished query's labels (already in pinned host
+        // memory) into its request's array
+        const int32_t k = alb::open_lane_poll(L, done.data(), nslots);
+        for (int32_t i = 0; i < k; ++i) {
+          const int32_t q = done[(size_t)i];
+          if (q < 0 || q >= nslots || !in_use[(size_t)q]) continue;
+          const uint64_t t = slot_ticket[(size_t)q];
+          lk.lock();
+          const Request r = reqs[t];
+          lk.unlock();
+          alb::open_lane_copy_out(L, r.lbase, member_n[r.member], r.out);
+          fin.emplace_back(t, ALB_OK);
+        }
+        lk.lock();
+        const Clock::time_point now = Clock::now();
+        for (auto &f : fin) {
+          Request &r = reqs[f.first];
+          release(r);
+          r.batch_size = admitted;
+          r.lane = lane;
+          --running;
+          complete(r, f.second, now);
+        }
+        if (!fin.empty()) cv_done.notify_all();
+        if (!alive) break;
+        if (stop) alb::open_lane_stop(L);
+        if (pending.empty() && fin.empty() && todo.empty()) cv_work.wait_for(lk, std::chrono::microseconds(50));
+      }
+      // the launch has ended: its status; requests it never took go back to
+      // the front of the queue, any it still held fail
+      lk.unlock();
+      double db = 0, de = 0;
+      const alb_status fs = alb::open_lane_finish(L, streams[lane], &db, &de);
+      std::vector<int32_t> untaken((size_t)nslots);
+      const int32_t nu = alb::open_lane_untaken(L, untaken.data(), nslots);
+      const Clock::time_point t1 = Clock::now();
+      lk.lock();
+      std::vector<char> back((size_t)nslots, 0);
+      for (int32_t i = 0; i < nu; ++i)
+        if (untaken[(size_t)i] >= 0 && untaken[(size_t)i] < nslots) back[(size_t)untaken[(size_t)i]] = 1;
+      for (int32_t i = nu - 1; i >= 0; --i) {  // keep their order at the front
+        const int32_t q = untaken[(size_t)i];
+        if (q < 0 || q >= nslots || !in_use[(size_t)q]) continue;
+        const uint64_t t = slot_ticket[(size_t)q];
+        Request &r = reqs[t];
+        release(r);
+        --running;
+        --admitted;
+        if (fs == ALB_OK) {
+          r.state = kPending;
+          pending.push_front(t);
+        } else {
+          complete(r, fs, t1);
+        }
+      }
+      int32_t lost = 0;
+      for (int32_t q = 0; q < nslots; ++q) {
+        if (!in_use[(size_t)q]) continue;
+        Request &r = reqs[slot_ticket[(size_t)q]];
+        release(r);
+        r.batch_size = admitted;
+        r.lane = lane;
+        --running;
+        complete(r, fs != ALB_OK ? fs : ALB_E_DEVICE, t1);
+        ++lost;
+      }
+      (void)back;
+      if (lost || nu) cv_done.notify_all();
+      edges_in_launch = nullptr;
+      alb_batch_record rec{};
+      rec.lane = lane;
+      rec.algo = -1;  // BFS and SSSP alike
+      rec.batch_size = admitted;
+      rec.status = fs;
+      rec.device_begin_ms = fs == ALB_OK ? db : 0;
+      rec.device_end_ms = fs == ALB_OK ? de : 0;
+      rec.host_begin_ms = ms_between(t_created, t0);
+      rec.host_end_ms = ms_between(t_created, t1);
+      log_batch(rec);
+      st.busy_ms += ms_between(t0, t1);
+      --busy_lanes;
+      cv_work.notify_all();
+    }
+    lk.unlock();
+    alb::open_lane_destroy(L);
+  }
+
+  void expire(Clock::time_point now) {
+    bool any = false;
+    for (auto it = pending.begin(); it != pending.end();) {
+      Request &r = reqs[*it];
+      if (r.deadline <= now) {
+        complete(r, ALB_E_TIMEOUT, now);
+        it = pending.erase(it);
+        any = true;
+      } else {
+        ++it;
+      }
+    }
+    if (any) cv_done.notify_all();
+  }
+
+  void fail_pending(int32_t algo, alb_status status, Clock::time_point now) {  // algo -1: every request
+    for (auto it = pending.begin(); it != pending.end();) {
+      Request &r = reqs[*it];
+      if (algo < 0 || r.algo == algo) {
+        complete(r, status, now);
+        it = pending.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    cv_done.notify_all();
+  }
+
   void lane_main(int lane) {
+    if (cfg.join_running) {
+      lane_main_join(lane);
+      return;
+    }
     std::vector<uint64_t> batch;
     std::vector<int32_t> mb, src;
     std::vector<int32_t *> outs;
@@ -184,11 +442,7 @@ struct alb_server_s {
       rec.host_begin_ms = ms_between(t_created, t0);
       rec.host_end_ms = ms_between(t_created, t1);
       lk.lock();
-      if (log.size() < kLogSize)
-        log.push_back(rec);
-      else
-        log[log_next] = rec;
-      log_next = (log_next + 1) % kLogSize;
+      log_batch(rec);
       st.busy_ms += ms_between(t0, t1);
       for (uint64_t t : batch) {
         Request &r = reqs[t];
@@ -234,6 +488,10 @@ alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_ser
   if (cfg.lanes < 1 || cfg.lanes > 16) return set_error(ALB_E_INVAL, "lanes must be in [1, 16]");
   if (cfg.max_batch < 1 || cfg.max_batch > 65535) return set_error(ALB_E_INVAL, "max_batch must be in [1, 65535]");
   if (cfg.max_wait_us < 0 || cfg.hbm_budget < 0) return set_error(ALB_E_INVAL, "negative max_wait_us or budget");
+  if (cfg.join_running != 0 && cfg.join_running != 1) return set_error(ALB_E_INVAL, "join_running must be 0 or 1");
+  if (cfg.join_running && (cfg.executor || !g))
+    return set_error(ALB_E_INVAL, "join_running needs the GPU: a graph and no executor");
+  if (cfg.join_idle_us < 0) return set_error(ALB_E_INVAL, "join_idle_us must be >= 0");
   alb_server s = new (std::nothrow) alb_server_s();
   if (!s) return set_error(ALB_E_NOMEM, "host allocation failed");
   s->g = g;

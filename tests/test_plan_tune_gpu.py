@@ -119,3 +119,40 @@ def test_autotune_batch(alb, gset, members, queries, kind):
     fn = alb.bfs_batch if kind == "bfs" else alb.sssp_batch
     outs, _ = fn(gset, mb, src, thresholds=thr, **opts)
     assert same(outs, expected(members, kind, mb, src))
+
+
+@pytest.mark.parametrize("kind", ["bfs", "sssp"])
+def test_per_query_cutoffs(alb, gset, members, queries, kind):
+    """Per-query thresholds and TWC cutoffs, eager and as a plan: extreme
+    cutoffs (everything in one bin) and mixed ones, all equal to the oracle;
+    invalid cutoffs are refused."""
+    mb, src = queries
+    ref = expected(members, kind, mb, src)
+    cand = [(64, 64, 256), (1 << 30, 1, 1), (1 << 30, 1 << 30, 1 << 30), (0, 64, 256), (256, 32, 512),
+            (4096, 128, 1024), (1, 1 << 30, 2)]
+    tuning = [cand[i % len(cand)] for i in range(len(mb))]
+    fn = alb.bfs_batch_tuned if kind == "bfs" else alb.sssp_batch_tuned
+    outs, st = fn(gset, mb, src, tuning)
+    assert same(outs, ref)
+    assert st["huge_threshold"] == -1
+    for extreme in [(64, 1, 1), (64, 1 << 30, 1 << 30)]:
+        outs, _ = fn(gset, mb, src, [extreme] * len(mb))
+        assert same(outs, ref), extreme
+    plan = alb.BatchPlan(gset, kind, mb, src, tuning=tuning)
+    for _ in range(2):
+        res, _ = plan.run()
+        assert same(res, ref)
+    plan.close()
+    with pytest.raises(alb.AlbError) as ei:
+        fn(gset, mb, src, [(64, 0, 256)] * len(mb))
+    assert ei.value.status == alb.ALB_E_INVAL
+
+
+def test_autotune_batch_with_cutoffs(alb, gset, members, queries):
+    mb, src = queries
+    opts, tuning, uniform_ms, tuned_ms = alb.autotune_batch_tuned(gset, "sssp", mb, src)
+    assert len(tuning) == len(mb)
+    assert all(t >= 0 and cw >= 1 and cg >= 1 for t, cw, cg in tuning)
+    assert 0 < tuned_ms <= uniform_ms  # kept settings only ever gain
+    outs, _ = alb.sssp_batch_tuned(gset, mb, src, tuning, **opts)
+    assert same(outs, expected(members, "sssp", mb, src))

@@ -242,3 +242,11 @@ def test_batch_log_records_every_batch(alb):
     # the two lanes ran batches at the same time on the host
     assert any(a["lane"] != b["lane"] and a["host_begin_ms"] < b["host_end_ms"] and
                b["host_begin_ms"] < a["host_end_ms"] for a in log for b in log)
+
+
+def test_join_running_needs_the_gpu(alb):
+    with pytest.raises(alb.AlbError) as ei:
+        alb.Server(None, lanes=1, executor=Fake(), member_vertices=[10], join_running=True)
+    assert ei.value.status == alb.ALB_E_INVAL
+    with pytest.raises(alb.AlbError):
+        alb.Server(None, lanes=1, executor=Fake(), member_vertices=[10], join_idle_us=-1)

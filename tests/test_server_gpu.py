@@ -108,3 +108,47 @@ def test_lanes_overlap_on_the_device(alb, gset, members):
              a["device_begin_ms"] < b["device_end_ms"] and b["device_begin_ms"] < a["device_end_ms"]]
     print("batches %d, overlapping lane pairs %d" % (len(log), len(pairs)))
     assert pairs, log
+
+
+@pytest.mark.parametrize("lanes,max_batch", [(1, 64), (2, 256)])
+def test_join_running_matches_oracle(alb, gset, members, lanes, max_batch):
+    """Continuous batching inside a launch: every result equals the oracle's."""
+    reqs = requests(members, 150, seed=30 + lanes)
+    with alb.Server(gset, lanes=lanes, max_batch=max_batch, join_running=True) as srv:
+        tickets = [srv.submit(a, m, s) for a, m, s in reqs]
+        for t, (a, m, s) in zip(tickets, reqs):
+            out, info = srv.wait(t)
+            assert np.array_equal(out, reference(members, a, m, s)), (a, m, s)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+
+
+def test_requests_join_a_running_launch(alb, gset, members):
+    """Requests submitted while a launch is on the device join it between
+    rounds: two waves of SSSP requests, the second submitted after the first
+    has completed but while the launch is still running (a long idle window),
+    are served by ONE launch that admitted all of them; results equal the
+    oracle's, also for a slot reused by the second wave."""
+    import time
+
+    srcs = gg.query_sources([members[0]], 24, seed=41)[1]
+    wave1 = [("sssp", 0, int(s)) for s in srcs[:12]]
+    wave2 = [("sssp", 0, int(s)) for s in srcs[12:]] + [("sssp", 2, 5), ("sssp", 4, 0)]
+    with alb.Server(gset, lanes=1, max_batch=16, join_running=True, join_idle_us=2_000_000) as srv:
+        t1 = [srv.submit(*r) for r in wave1]
+        for t, r in zip(t1, wave1):
+            out, _ = srv.wait(t)
+            assert np.array_equal(out, reference(members, *r))
+        time.sleep(0.05)
+        assert srv.batch_log() == []  # the launch is still running (its record is written when it ends)
+        t2 = [srv.submit(*r) for r in wave2]
+        for t, r in zip(t2, wave2):
+            out, info = srv.wait(t)
+            assert np.array_equal(out, reference(members, *r))
+        deadline = time.time() + 10
+        while not srv.batch_log() and time.time() < deadline:
+            time.sleep(0.05)
+        log = srv.batch_log()
+    assert len(log) == 1, log
+    assert log[0]["batch_size"] == len(wave1) + len(wave2) and log[0]["status"] == 0
+    assert 0 < log[0]["device_begin_ms"] < log[0]["device_end_ms"]
