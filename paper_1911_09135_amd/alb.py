@@ -21,6 +21,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("%s is not built (python -m paper_1911_09135_amd.build); the ALB library has no CPU "
                       "fallback" % LIB_PATH)
 
+# torch, where installed, is loaded before the library: its HIP runtime then
+# serves the library as well.  Loaded the other way round, the library's
+# runtime comes first and torch finds no GPU in the same process.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 ALB_OK, ALB_E_INVAL, ALB_E_NOMEM, ALB_E_DEVICE, ALB_E_RANGE, ALB_E_OVERFLOW, ALB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6

@@ -2280,7 +2280,7 @@ struct OpenLane {
   alb_graph g = nullptr;
   alb_options o;
   OpKind op = OP_BFS;  // of the current launch
-  int wg = 256, grid = 1, grid_cap = 1;
+  int wg = 256, grid = 1, grid_cap = 1, resident = 1;
   int64_t max_m = 0;
   int32_t slots = 0;
   long long label_cap = 0;
@@ -2393,6 +2393,7 @@ alb_status open_lane_start(OpenLane *L, hipStream_t s, double idle_us, int64_t e
   int resident = 0;
   alb_status st = resident_workgroups(g, L->op, L->wg, &resident, false, true);
   if (st != ALB_OK) return st;
+  L->resident = resident;
   // the automatic grid of the work queued when the launch starts, at most
   // the lane's share: a grid barrier costs more the more workgroups join
   // it, and a stream of small queries wants few
@@ -2523,6 +2524,12 @@ alb_status open_lane_finish(OpenLane *L, hipStream_t s, double *begin_ms, double
 }
 
 void open_lane_stop(OpenLane *L) { __atomic_store_n(&L->sh->stop, 1u, __ATOMIC_RELEASE); }
+
+int open_lane_grid(const OpenLane *L) { return L->grid; }
+
+int open_lane_grid_for(const OpenLane *L, int64_t edges) {
+  return std::max(1, std::min(auto_grid(std::max<int64_t>(edges, 1), L->wg, L->resident), L->grid_cap));
+}
 
 int32_t open_lane_untaken(OpenLane *L, int32_t *slots, int32_t max) {
   const uint64_t head = __atomic_load_n(&L->sh->head, __ATOMIC_ACQUIRE);

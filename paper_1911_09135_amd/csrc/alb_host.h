@@ -47,5 +47,10 @@ int32_t open_lane_poll(OpenLane *L, int32_t *slots, int32_t max);
 void open_lane_copy_out(OpenLane *L, long long lbase, int32_t n, int32_t *out);
 alb_status open_lane_finish(OpenLane *L, hipStream_t s, double *begin_ms, double *end_ms);
 void open_lane_stop(OpenLane *L);
+// The running launch's workgroups, and those the automatic grid gives a
+// query of `edges` edges within the lane's share: a query that wants more
+// than the launch has waits for a launch of its own size.
+int open_lane_grid(const OpenLane *L);
+int open_lane_grid_for(const OpenLane *L, int64_t edges);
 
 }  // namespace alb

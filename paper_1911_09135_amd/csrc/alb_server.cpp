@@ -218,11 +218,19 @@ struct alb_server_s {
         // slot, label memory and ring room are free
         std::vector<Request> todo;
         expire(Clock::now());
+        bool regrid = false;
         if (alive) {
           uint64_t room = (uint64_t)alb::kOpenMaxSlots - alb::open_lane_backlog(L);
           for (auto it = pending.begin(); it != pending.end() && !free_slots.empty() && room > 0;) {
             Request &r = reqs[*it];
             if (active_edges + r.edges >= kMaxPositions) break;  // one round's huge edges stay 32-bit
+            // a query that wants a bigger grid than the launch was started
+            // with would run on too few workgroups: the launch ends once it
+            // has finished what it holds and the next one is sized for it
+            if (alb::open_lane_grid_for(L, r.edges) > alb::open_lane_grid(L)) {
+              regrid = true;
+              break;
+            }
             const long long at = arena.take(member_n[r.member]);
             if (at < 0) break;  // wait for memory: later requests do not overtake
             active_edges += r.edges;
@@ -271,8 +279,9 @@ struct alb_server_s {
         }
         if (!fin.empty()) cv_done.notify_all();
         if (!alive) break;
-        if (stop) alb::open_lane_stop(L);
-        if (pending.empty() && fin.empty() && todo.empty()) cv_work.wait_for(lk, std::chrono::microseconds(50));
+        if (stop || regrid) alb::open_lane_stop(L);
+        // nothing taken or finished: wait for a request or the next poll
+        if (fin.empty() && todo.empty()) cv_work.wait_for(lk, std::chrono::microseconds(50));
       }
       // the launch has ended: its status; requests it never took go back to
       // the front of the queue, any it still held fail

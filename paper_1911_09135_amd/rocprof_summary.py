@@ -3,12 +3,16 @@
     python -m paper_1911_09135_amd.rocprof_summary stats DIR
     python -m paper_1911_09135_amd.rocprof_summary traffic --fetch DIR --write DIR \
         --copy-fetch DIR --copy-write DIR --kernel k_persistent --out profiles/traffic_X.json
+    python -m paper_1911_09135_amd.rocprof_summary overlap DIR --kernel k_persistent
 
 `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over the
 counter's instances) into bytes per launch of the named kernel, each scaled by
 what the same counter reads for a plain device copy of known size (bench.py
 --copy-calibration), and records the hash of the kernel source the counters
 were taken on (bench.py reports the traffic only while that hash matches).
+`overlap` reads the kernel trace and reports, for the dispatches whose name
+holds the given text, how long two or more of them ran at the same time on
+the device (several serving lanes' launches on their own streams).
 """
 from __future__ import annotations
 
@@ -90,6 +94,43 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_k
     }
 
 
+def kernel_intervals(d: str, substr: str):
+    """[(start ns, end ns, stream id), ...] of the traced dispatches whose
+    kernel name contains `substr`, in start order."""
+    rows = list(csv.DictReader(open(_find(d, "kernel_trace.csv"))))
+    out = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), int(r["Stream_Id"])) for r in rows
+           if substr in r["Kernel_Name"]]
+    return sorted(out)
+
+
+def overlap(intervals):
+    """Time with at least one and with at least two of the intervals running,
+    the most running at once, and the dispatches per stream (a sweep over the
+    start and end points; an end at the same instant as a start counts first)."""
+    ev = []
+    for b, e, _ in intervals:
+        if e > b:
+            ev.append((b, 1))
+            ev.append((e, -1))
+    ev.sort(key=lambda x: (x[0], x[1]))
+    busy = two = 0
+    depth = peak = 0
+    prev = None
+    for t, d in ev:
+        if prev is not None:
+            if depth >= 1:
+                busy += t - prev
+            if depth >= 2:
+                two += t - prev
+        depth += d
+        peak = max(peak, depth)
+        prev = t
+    per_stream = collections.Counter(s for _, _, s in intervals)
+    return {"dispatches": len(intervals), "streams": dict(sorted(per_stream.items())),
+            "kernel_ns_summed": sum(max(e - b, 0) for b, e, _ in intervals), "busy_ns": busy,
+            "two_or_more_ns": two, "most_at_once": peak}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -103,12 +144,17 @@ def main():
     t.add_argument("--kernel", required=True)
     t.add_argument("--copy-mib", type=int, default=1024)
     t.add_argument("--out")
+    o = sub.add_parser("overlap")
+    o.add_argument("dir")
+    o.add_argument("--kernel", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         print("| Kernel | Calls | Average ns | Min ns | Max ns | % |")
         print("|---|---|---|---|---|---|")
         for name, calls, avg, mn, mx, pct in kernel_stats(a.dir):
             print("| %s | %d | %.0f | %.0f | %.0f | %.2f |" % (name, calls, avg, mn, mx, pct))
+    elif a.cmd == "overlap":
+        print(json.dumps(overlap(kernel_intervals(a.dir, a.kernel)), indent=1))
     else:
         res = traffic(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, copy_bytes=a.copy_mib << 20)
         text = json.dumps(res, indent=1)

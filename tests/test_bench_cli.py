@@ -39,3 +39,17 @@ def test_algorithmic_bytes_model():
     assert alb.algorithmic_bytes("bfs", st) == 16 * 10 + 8 * 100 + 4 * 7
     assert alb.algorithmic_bytes("kcore", st) == alb.algorithmic_bytes("cc", st) == alb.algorithmic_bytes("bfs", st)
     assert alb.algorithmic_bytes("pagerank", st, n=5, iterations=3) == 8 * 100 + 24 * 5 * 3
+
+
+def test_rocprof_overlap_sweep():
+    """The lane-overlap summary of a kernel trace: time with two or more of
+    the dispatches running at once, on hand-made intervals."""
+    from paper_1911_09135_amd import rocprof_summary as rs
+    iv = [(0, 10, 1), (5, 15, 2), (15, 20, 1), (30, 40, 2), (32, 34, 1), (33, 35, 3)]
+    r = rs.overlap(iv)
+    assert r["busy_ns"] == 20 + 10
+    assert r["two_or_more_ns"] == 5 + 3  # [5, 10) and [32, 35)
+    assert r["most_at_once"] == 3
+    assert r["streams"] == {1: 3, 2: 2, 3: 1}
+    assert r["kernel_ns_summed"] == 10 + 10 + 5 + 10 + 2 + 2
+    assert rs.overlap([])["busy_ns"] == 0
