@@ -395,6 +395,8 @@ typedef struct {
   int64_t submitted, completed, failed, timed_out, cancelled, rejected, batches;
   int64_t pending, running;  /* now */
   double busy_ms;            /* summed over lanes: time spent running batches */
+  int64_t direct_outputs;    /* join_running: results the launch wrote straight into the request's output
+                                (pinned host memory); the others were copied from the lane's output area */
 } alb_server_stats;
 
 alb_status alb_server_config_init(alb_server_config *cfg);

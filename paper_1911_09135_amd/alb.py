@@ -125,7 +125,7 @@ class RequestInfo(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "timed_out", "cancelled",
                                               "rejected", "batches", "pending", "running")] + \
-               [("busy_ms", ctypes.c_double)]
+               [("busy_ms", ctypes.c_double), ("direct_outputs", ctypes.c_int64)]
 
 
 class QueryTuning(ctypes.Structure):

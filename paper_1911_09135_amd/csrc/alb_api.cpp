@@ -2296,6 +2296,7 @@ struct OpenLane {
   int32_t *qsrc = nullptr, *qn = nullptr, *q_last = nullptr, *q_active = nullptr, *q_admit = nullptr;
   int32_t *q_conv = nullptr;  // finished slots per round
   int32_t *q_unit = nullptr;  // per slot: BFS (unit weights)
+  unsigned long long *q_out = nullptr;  // per slot: device address of its pinned output, or 0
   Ctl *ctl = nullptr;
   // pinned host
   OpenShared *sh = nullptr;     // coherent: read and written while the launch runs
@@ -2312,7 +2313,7 @@ struct OpenLane {
 void open_lane_destroy(OpenLane *L) {
   if (!L) return;
   void *d[] = {L->q0, L->q1, L->word, L->bar, L->huge_rec, L->hint, L->qoff, L->qlbase, L->qsrc, L->qn,
-               L->q_last, L->q_active, L->q_admit, L->q_conv, L->q_unit, L->ctl};
+               L->q_last, L->q_active, L->q_admit, L->q_conv, L->q_unit, L->q_out, L->ctl};
   for (void *x : d) (void)hipFree(x);
   if (L->sh) (void)hipHostFree(L->sh);
   if (L->h_ctl) (void)hipHostFree(L->h_ctl);
@@ -2365,7 +2366,7 @@ alb_status open_lane_create(alb_graph g, const alb_options &o, int32_t slots, lo
       (e = dalloc(&L->q_last, S, L->bytes)) != hipSuccess || (e = dalloc(&L->q_active, S, L->bytes)) != hipSuccess ||
       (e = dalloc(&L->q_admit, 2 * (size_t)kOpenRing, L->bytes)) != hipSuccess ||
       (e = dalloc(&L->q_conv, 2 * (size_t)kOpenRing, L->bytes)) != hipSuccess ||
-      (e = dalloc(&L->q_unit, S, L->bytes)) != hipSuccess ||
+      (e = dalloc(&L->q_unit, S, L->bytes)) != hipSuccess || (e = dalloc(&L->q_out, S, L->bytes)) != hipSuccess ||
       (e = dalloc(&L->ctl, 1, L->bytes)) != hipSuccess)
     return bail(fail(e == hipErrorOutOfMemory ? ALB_E_NOMEM : ALB_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e)));
   if (alloc_failure_injected()) return bail(fail(ALB_E_NOMEM, "hipHostMalloc: out of memory"));
@@ -2451,6 +2452,7 @@ alb_status open_lane_start(OpenLane *L, hipStream_t s, double idle_us, int64_t e
   a.q_admit = L->q_admit;
   a.q_conv = L->q_conv;
   a.q_unit = L->q_unit;
+  a.q_out = (int32_t **)L->q_out;
   a.open_out = L->out_dev;
   a.nslots = L->slots;
   a.idle_ticks = (uint64_t)std::max(1.0, idle_us * (double)g->clock_khz / 1000.0);
@@ -2471,14 +2473,30 @@ uint64_t open_lane_backlog(OpenLane *L) {
 }
 
 // Publish one request into `slot`, its labels at [lbase, lbase + n).
+// The device address of pinned host memory (hipHostMalloc'd or registered
+// with the runtime), or 0 for any other pointer.
+static unsigned long long pinned_device_address(const void *p) {
+  if (!p) return 0;
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof at);
+  const hipError_t e = hipPointerGetAttributes(&at, p);
+  (void)hipGetLastError();  // an unregistered pointer leaves no error behind for the next caller
+  if (e != hipSuccess || at.type != hipMemoryTypeHost || !at.devicePointer) return 0;
+  return (unsigned long long)(uintptr_t)at.devicePointer;
+}
+
 alb_status open_lane_publish(OpenLane *L, int32_t algo, int32_t slot, int32_t member, int32_t source,
-                             long long lbase) {
+                             long long lbase, int32_t *host_out, bool *direct) {
   alb_graph g = L->g;
+  *direct = false;
   if (member < 0 || member >= (int32_t)g->mem_n.size()) return fail(ALB_E_INVAL, "member out of range");
   if (algo == ALB_ALGO_SSSP && !g->weighted) return fail(ALB_E_INVAL, "SSSP needs a graph set created with weights");
   if (L->published - __atomic_load_n(&L->sh->head, __ATOMIC_ACQUIRE) >= (uint64_t)kOpenRing)
     return fail(ALB_E_INVAL, "request ring full");
+  const unsigned long long out_dev = pinned_device_address(host_out);
   OpenReq &q = L->sh->req[L->published % kOpenRing];
+  q.out = out_dev;
+  *direct = out_dev != 0;
   q.slot = slot;
   q.unit = algo == ALB_ALGO_BFS ? 1 : 0;
   q.src = g->mem_vbase[member] + source;
@@ -2516,6 +2534,8 @@ alb_status open_lane_finish(OpenLane *L, hipStream_t s, double *begin_ms, double
   const Ctl &c = *L->h_ctl;
   *begin_ms = (double)c.t_begin / (double)L->g->clock_khz;
   *end_ms = (double)c.t_end / (double)L->g->clock_khz;
+  if (getenv("ALB_TIMELINE"))  // profiling aid: the launch's first rounds on stderr
+    print_timeline(c, (int)L->op, (int)c.rounds, (long long)c.threshold_used, L->g->clock_khz);
   if (c.abort) return abort_error(c);
   if (c.overflow != 0xffffffffu)
     return fail(ALB_E_OVERFLOW, "a worklist exceeded its capacity of %llu entries in round %u",

@@ -30,7 +30,8 @@ bool last_launch_window(double *begin_ms, double *end_ms);
 // without work, or once stopped and idle); publish hands one BFS or SSSP
 // query to the running launch; poll returns finished slots; copy_out
 // fetches a finished query's int32 labels (the launch wrote them to pinned
-// host memory); finish reads the ended launch's status and device window.
+// host memory) unless the launch wrote them into the request's own pinned
+// output; finish reads the ended launch's status and device window.
 struct OpenLane;
 constexpr int32_t kOpenMaxSlots = 1024;  // query slots of one launch (the rings' size)
 // Slots published but never taken by a launch that has ended.
@@ -41,8 +42,10 @@ void open_lane_destroy(OpenLane *L);
 alb_status open_lane_start(OpenLane *L, hipStream_t s, double idle_us, int64_t edges);
 bool open_lane_running(OpenLane *L, hipStream_t s);
 uint64_t open_lane_backlog(OpenLane *L);
+// host_out: the request's int32 output; when it is pinned host memory the
+// launch writes the labels there itself (*direct), else copy_out fetches them.
 alb_status open_lane_publish(OpenLane *L, int32_t algo, int32_t slot, int32_t member, int32_t source,
-                             long long lbase);
+                             long long lbase, int32_t *host_out, bool *direct);
 int32_t open_lane_poll(OpenLane *L, int32_t *slots, int32_t max);
 void open_lane_copy_out(OpenLane *L, long long lbase, int32_t n, int32_t *out);
 alb_status open_lane_finish(OpenLane *L, hipStream_t s, double *begin_ms, double *end_ms);

@@ -68,6 +68,7 @@ struct OpenReq {
   int32_t unit;    // 1: BFS (every edge weighs 1), 0: SSSP with the graph's weights
   long long qoff;  // label index of (slot, vertex v) = qoff + v
   long long lbase; // first label index of the slot (= qoff + member base)
+  unsigned long long out;  // device address of the caller's pinned int32 output, or 0 (open_out)
 };
 struct OpenShared {
   alignas(256) unsigned long long tail;  // requests published (host)
@@ -197,6 +198,7 @@ struct Args {
   int32_t *q_unit;      // per slot: 1 = a BFS query, run as shortest paths with unit weights
   int32_t *q_conv;      // [2][kOpenRing]: slots whose labels round r writes to open_out ([r & 1])
   int32_t *open_out;    // int32 labels of finished queries, at the slot's label indices
+  int32_t **q_out;      // per slot: the caller's pinned output (device address), or null: open_out
   int32_t nslots;
   uint64_t idle_ticks;
 };

@@ -660,12 +660,16 @@ __device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid 
       deg = a.off[v + 1] - beg;
     }
     if constexpr (M) {
-      // continuous serving: this round had an entry of query slot q (one
-      // store per run of equal slots in the wavefront)
+      // continuous serving: this round had an entry of query slot q.  One
+      // plain store per run of equal slots in the wavefront, skipped once
+      // the mark already reads this round (the grid barrier publishes it).
+      // A store from every wavefront, all to the one address of a lone
+      // query's slot, serialised the round: writing through to memory they
+      // tripled the inspection phase.
       if (a.q_last) {
         const int32_t qq = mine ? q : -1;
         const int32_t prev = __shfl_up(qq, 1);
-        if (mine && (lane == 0 || prev != qq)) st_relaxed(&a.q_last[qq], (int32_t)round);
+        if (mine && (lane == 0 || prev != qq) && a.q_last[qq] != (int32_t)round) a.q_last[qq] = (int32_t)round;
       }
     }
     V sv = V(0);
@@ -930,7 +934,8 @@ __device__ __forceinline__ bool bar_wait(const Args &a, unsigned long long *w, u
 // invalidate elsewhere was tried and gave stale reads).  Counters only grow,
 // so nothing is reset between barriers.
 template <class S>
-__device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round) {
+__device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round,
+                             bool sys = false) {
   wait_memory();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -939,7 +944,12 @@ __device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &
     const unsigned long long o1 = add_relaxed(&b[kBarXcdArrive + (size_t)kBarStride * gr.xcd], 1ull);
     bool ok;
     if ((o1 + 1) % gr.xcd_n == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // the XCD's last arrival releases every store its members made before
+      // arriving; `sys`: to the host as well (stores into host memory)
+      if (sys)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      else
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned long long o2 = add_relaxed(&b[kBarRoot], 1ull);
       if ((o2 + 1) % gr.n_xcd == 0) st_relaxed(&b[kBarGen], target);
       ok = bar_wait(a, &b[kBarGen], target, round);
@@ -1322,6 +1332,7 @@ __device__ void open_admit(const Args &a, int r, uint32_t nF) {
     ((int32_t *)a.qsrc)[slot] = ld_sys(&q->src);
     ((int32_t *)a.qn)[slot] = ld_sys(&q->n);
     a.q_unit[slot] = ld_sys(&q->unit);
+    a.q_out[slot] = (int32_t *)ld_sys(&q->out);
     a.q_last[slot] = r;  // not finished in this round's phase 2: its source is in round r + 1's worklist
     a.q_active[slot] = 1;
   }
@@ -1368,8 +1379,8 @@ __device__ void open_complete(const Args &a, int r, uint32_t *s_cnt) {
 
 // Every member in round r's phase 2: the slots admitted in round r get their
 // labels (INF, the source 0); the slots finished in round r - 1 get theirs
-// written to open_out as int32 (SSSP: the distance half of the label word;
-// BFS: the level).  Workgroup 0 then appends the new sources to round
+// written as int32 (SSSP: the distance half of the label word; BFS: the
+// level) into the caller's pinned output, or into open_out.  Workgroup 0 then appends the new sources to round
 // r + 1's worklist.
 template <class Op>
 __device__ void open_prepare(const Args &a, Grid gr, int B, int r, uint32_t k, uint32_t nc) {
@@ -1392,11 +1403,13 @@ __device__ void open_prepare(const Args &a, Grid gr, int B, int r, uint32_t k, u
     const int32_t slot = conv[i];
     const long long base = a.qlbase[slot];
     const int32_t n = a.qn[slot];
+    int32_t *dst = a.q_out[slot];  // the caller's pinned array, else the lane's output area
+    if (!dst) dst = a.open_out + base;
     for (int32_t v = (int32_t)(gr.id * B + threadIdx.x); v < n; v += (int32_t)(gr.n * B)) {
       if constexpr (std::is_same<Op, OpBFS>::value)
-        a.open_out[base + v] = a.level[base + v];
+        dst[v] = a.level[base + v];
       else
-        a.open_out[base + v] = (int32_t)(a.word[base + v] >> 32);
+        dst[v] = (int32_t)(a.word[base + v] >> 32);
     }
   }
   if (k && gr.id == 0 && threadIdx.x == 0) {
@@ -1440,7 +1453,9 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
   for (;; ++r) {
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;
     const uint32_t nF = round_size(a, r);
+    const bool tl = gr.id == 0 && threadIdx.x == 0 && r < kTimeline;
     if (gr.id == 0 && threadIdx.x == 0) clear_ahead(a, r);
+    if (tl) a.ctl->tl[4 * r] = (unsigned long long)wall_clock64();
     Entry<true> *qn = round_next<true>(a, r);
     uint32_t *qn_cnt = &a.ctl->qcount[(r + 1) % 3];
     const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
@@ -1456,8 +1471,15 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
     const uint32_t nc = ld_relaxed(&a.ctl->conv_n[r & 1]);
     open_prepare<Op>(a, gr, B, r, k, nc);
     const unsigned long long hc = nF ? ld_relaxed(&a.ctl->huge[r & 1]) : 0ull;
+    if (tl) {
+      a.ctl->tl[4 * r + 1] = (unsigned long long)wall_clock64();
+      a.ctl->tl[4 * r + 3] = (unsigned long long)nF | ((hc >> 32) << 32);
+    }
     if ((hc >> 32) != 0) phase_lb<B, Op, true>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
-    if (!grid_barrier(a, sm, gr, epoch, r)) break;
+    // a round that wrote finished labels into host memory releases them at
+    // system scope on every XCD before workgroup 0 publishes the slots
+    if (!grid_barrier(a, sm, gr, epoch, r, nc != 0)) break;
+    if (tl) a.ctl->tl[4 * r + 2] = (unsigned long long)wall_clock64();
     if (nc && gr.id == 0 && threadIdx.x == 0) open_publish(a, r, nc);
   }
   if (gr.id == 0 && threadIdx.x == 0) {

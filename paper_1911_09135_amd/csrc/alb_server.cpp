@@ -170,6 +170,7 @@ struct alb_server_s {
     std::vector<int32_t> free_slots;
     for (int32_t q = nslots - 1; q >= 0; --q) free_slots.push_back(q);
     std::vector<int32_t> done((size_t)nslots);
+    std::vector<char> direct((size_t)nslots, 0);  // the launch writes the slot's labels into its pinned output
     const double idle_us = cfg.join_idle_us > 0 ? (double)cfg.join_idle_us : 500.0;
     int64_t *edges_in_launch = nullptr;
     auto release = [&](Request &r) {
@@ -250,12 +251,16 @@ struct alb_server_s {
         }
         lk.unlock();
         std::vector<std::pair<uint64_t, alb_status>> fin;
+        int64_t direct_done = 0;
         for (const Request &r : todo) {
-          const alb_status ps = alb::open_lane_publish(L, r.algo, r.slot, r.member, r.source, r.lbase);
+          bool dir = false;
+          const alb_status ps = alb::open_lane_publish(L, r.algo, r.slot, r.member, r.source, r.lbase, r.out, &dir);
+          direct[(size_t)r.slot] = dir ? 1 : 0;
           if (ps != ALB_OK) fin.emplace_back(slot_ticket[(size_t)r.slot], ps);  // never published
         }
         // completions: each finished query's labels (already in pinned host
-        // memory) into its request's array
+        // memory) copied into its request's array, unless the launch wrote
+        // them there itself
         const int32_t k = alb::open_lane_poll(L, done.data(), nslots);
         for (int32_t i = 0; i < k; ++i) {
           const int32_t q = done[(size_t)i];
@@ -264,10 +269,12 @@ struct alb_server_s {
           lk.lock();
           const Request r = reqs[t];
           lk.unlock();
-          alb::open_lane_copy_out(L, r.lbase, member_n[r.member], r.out);
+          if (!direct[(size_t)q]) alb::open_lane_copy_out(L, r.lbase, member_n[r.member], r.out);
           fin.emplace_back(t, ALB_OK);
+          if (direct[(size_t)q]) ++direct_done;
         }
         lk.lock();
+        st.direct_outputs += direct_done;
         const Clock::time_point now = Clock::now();
         for (auto &f : fin) {
           Request &r = reqs[f.first];

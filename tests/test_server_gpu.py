@@ -152,3 +152,31 @@ def test_requests_join_a_running_launch(alb, gset, members):
     assert len(log) == 1, log
     assert log[0]["batch_size"] == len(wave1) + len(wave2) and log[0]["status"] == 0
     assert 0 < log[0]["device_begin_ms"] < log[0]["device_end_ms"]
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_join_running_writes_pinned_outputs(alb, gset, members, lanes):
+    """Continuous batching with outputs in pinned host memory: the launch
+    converts a finished query's labels straight into the request's array
+    (no host copy); pinned and pageable outputs mixed in one launch, every
+    array pre-filled with a value no result holds, all equal the oracle."""
+    import torch
+
+    reqs = requests(members, 120, seed=50 + lanes)
+    outs = []
+    for i, (a, m, s) in enumerate(reqs):
+        n = members[m].n
+        if i % 3 == 2:
+            o = np.full(n, -7, np.int32)  # pageable: the staged copy
+        else:
+            o = torch.full((n,), -7, dtype=torch.int32, pin_memory=True).numpy()
+        outs.append(o)
+    with alb.Server(gset, lanes=lanes, max_batch=64, join_running=True) as srv:
+        tickets = [srv.submit(a, m, s, out=o) for (a, m, s), o in zip(reqs, outs)]
+        for t, (a, m, s), o in zip(tickets, reqs, outs):
+            got, _ = srv.wait(t)
+            assert got is o
+            assert np.array_equal(o, reference(members, a, m, s)), (a, m, s)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["direct_outputs"] == sum(1 for i in range(len(reqs)) if i % 3 != 2)
