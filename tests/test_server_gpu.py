@@ -180,3 +180,30 @@ def test_join_running_writes_pinned_outputs(alb, gset, members, lanes):
         st = srv.stats()
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["direct_outputs"] == sum(1 for i in range(len(reqs)) if i % 3 != 2)
+
+
+def test_join_running_edge_sources_and_deadlines(alb, gset, members):
+    """Join mode on sources that end at once or run long: the directed path's
+    last vertex (no out-edges) and first vertex (499 rounds), the star's
+    centre and a leaf, an RMAT vertex without out-edges; then four 499-round
+    path queries hold every slot and a request queued behind them with a 1 ms
+    deadline completes as timed out, while the four still equal the oracle."""
+    deg0 = np.nonzero(members[0].degrees() == 0)[0]
+    iso = int(deg0[0]) if deg0.size else 0
+    reqs = [("bfs", 4, 499), ("sssp", 4, 499), ("bfs", 4, 0), ("sssp", 4, 0), ("sssp", 3, 0), ("bfs", 3, 7),
+            ("sssp", 0, iso), ("bfs", 0, iso)]
+    with alb.Server(gset, lanes=1, max_batch=4, join_running=True) as srv:
+        tickets = [srv.submit(*r) for r in reqs]
+        for t, r in zip(tickets, reqs):
+            out, _ = srv.wait(t)
+            assert np.array_equal(out, reference(members, *r)), r
+        long = [srv.submit("sssp", 4, 0) for _ in range(4)]
+        late = srv.submit("bfs", 1, 0, timeout_ms=1)
+        with pytest.raises(alb.AlbError) as e:
+            srv.wait(late)
+        assert e.value.status == alb.ALB_E_TIMEOUT
+        for t in long:
+            out, _ = srv.wait(t)
+            assert np.array_equal(out, reference(members, "sssp", 4, 0))
+        st = srv.stats()
+    assert st["timed_out"] == 1 and st["failed"] == 0 and st["completed"] == len(reqs) + 4
