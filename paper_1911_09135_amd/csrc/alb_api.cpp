@@ -505,6 +505,8 @@ namespace alb {
 // edges: fewer, cheaper-to-synchronise workgroups win on small graphs and a
 // full device only pays off near 10^8 edges (RMAT-14 BFS 0.17 vs 0.26 ms,
 // RMAT-20 SSSP 1.27 vs 1.54 ms against every resident workgroup).
+alb_status check_options(const alb_options *user, alb_options *out) { return resolve_options(user, *out); }
+
 int auto_grid(int64_t edges, int wg, int resident) {
   const double w256 = std::max(16.0, 2.0 * std::cbrt((double)std::max<int64_t>(edges, 1)));
   const int g = (int)std::lround(w256 * 256.0 / (double)wg);
@@ -2431,9 +2433,10 @@ alb_status open_lane_start(OpenLane *L, hipStream_t s, double idle_us, int64_t e
   a.bar = L->bar;
   a.ctl = L->ctl;
   a.threshold = L->threshold;
-  a.c_wave = 64;
-  a.c_wg = L->wg;
-  a.dedup = 1;
+  a.c_wave = o.wave_cutoff;
+  a.c_wg = o.wg_cutoff;
+  a.blocked = o.distribution == 1;
+  a.dedup = o.dedup != 0;  // on unless turned off (the default for shortest paths)
   a.adaptive = L->adaptive ? 1 : 0;
   a.small_threshold = L->small_threshold;
   a.max_rounds = INT32_MAX;

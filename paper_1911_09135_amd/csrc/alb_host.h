@@ -10,6 +10,9 @@ namespace alb {
 // Set the calling thread's alb_last_error() text; returns s.
 alb_status set_error(alb_status s, const char *fmt, ...);
 
+// Validate `user` (NULL: the defaults) and fill its defaults into *out.
+alb_status check_options(const alb_options *user, alb_options *out);
+
 // The automatic grid of a traversal over `edges` edges (alb_options.grid_wgs = 0).
 int auto_grid(int64_t edges, int wg, int resident);
 

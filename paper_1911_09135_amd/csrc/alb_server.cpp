@@ -508,6 +508,12 @@ alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_ser
   if (cfg.join_running && (cfg.executor || !g))
     return set_error(ALB_E_INVAL, "join_running needs the GPU: a graph and no executor");
   if (cfg.join_idle_us < 0) return set_error(ALB_E_INVAL, "join_idle_us must be >= 0");
+  {  // the traversal options every batch or launch of the server uses, defaults filled in
+    alb_options o;
+    const alb_status st = alb::check_options(&cfg.options, &o);
+    if (st != ALB_OK) return st;
+    cfg.options = o;
+  }
   alb_server s = new (std::nothrow) alb_server_s();
   if (!s) return set_error(ALB_E_NOMEM, "host allocation failed");
   s->g = g;
@@ -539,14 +545,11 @@ alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_ser
   s->cfg.member_vertices = nullptr;  // not kept
   if (!cfg.executor) {
     if (!g) return bail(set_error(ALB_E_INVAL, "graph handle is NULL"));
-    alb_options o;
-    alb_status st = alb_options_init(&o);
-    if (st != ALB_OK) return bail(st);
-    const int wg = cfg.options.wg_size ? cfg.options.wg_size : 256;
+    const int wg = cfg.options.wg_size;  // filled in above
     for (int32_t algo = 0; algo < 2; ++algo) {
       int res = 0;
       // also makes g's device current for the streams below
-      st = alb::batch_resident_workgroups(g, algo, wg, &res);
+      const alb_status st = alb::batch_resident_workgroups(g, algo, wg, &res);
       if (st != ALB_OK) return bail(st);
       s->grid[algo] = std::max(1, res / cfg.lanes);
       s->grid_all[algo] = res;

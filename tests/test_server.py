@@ -250,3 +250,14 @@ def test_join_running_needs_the_gpu(alb):
     assert ei.value.status == alb.ALB_E_INVAL
     with pytest.raises(alb.AlbError):
         alb.Server(None, lanes=1, executor=Fake(), member_vertices=[10], join_idle_us=-1)
+
+
+def test_bad_traversal_options_are_refused_at_create(alb):
+    """The server validates its traversal options when it is created, not
+    when its first batch runs."""
+    with pytest.raises(alb.AlbError) as e:
+        alb.Server(None, lanes=1, executor=Fake(), member_vertices=[10], wg_size=128)
+    assert e.value.status == alb.ALB_E_UNSUPPORTED
+    with pytest.raises(alb.AlbError) as e:
+        alb.Server(None, lanes=1, executor=Fake(), member_vertices=[10], wave_cutoff=-3)
+    assert e.value.status == alb.ALB_E_INVAL

@@ -207,3 +207,17 @@ def test_join_running_edge_sources_and_deadlines(alb, gset, members):
             assert np.array_equal(out, reference(members, "sssp", 4, 0))
         st = srv.stats()
     assert st["timed_out"] == 1 and st["failed"] == 0 and st["completed"] == len(reqs) + 4
+
+
+@pytest.mark.parametrize("opts", [dict(threshold=64, wave_cutoff=32, wg_cutoff=512),
+                                  dict(threshold=64, distribution=1), dict(mode="twc")])
+def test_join_running_with_traversal_options(alb, gset, members, opts):
+    """The serving launch takes the server's traversal options: a low huge
+    threshold with other TWC cutoffs, the blocked distribution of huge
+    edges, TWC only; every result equals the oracle's."""
+    reqs = requests(members, 60, seed=70)
+    with alb.Server(gset, lanes=1, max_batch=32, join_running=True, **opts) as srv:
+        tickets = [srv.submit(a, m, s) for a, m, s in reqs]
+        for t, (a, m, s) in zip(tickets, reqs):
+            out, _ = srv.wait(t)
+            assert np.array_equal(out, reference(members, a, m, s)), (a, m, s, opts)
