@@ -82,6 +82,9 @@ def main():
                          "requests over 32 graphs through the serving loop")
     ap.add_argument("--requests", type=int, default=5000, help="serve: requests per arrival rate")
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000", help="serve: arrival rates per second")
+    ap.add_argument("--join-long-edges", type=int, default=0,
+                    help="serve: the joining server runs two lanes, requests on members with at least this many "
+                         "edges on lane 0 and the rest on lane 1 (0: one lane with the whole device)")
     ap.add_argument("--tune", action="store_true",
                     help="batch: also run with autotuned per-query settings (always in the default line's summary)")
     ap.add_argument("--random-probe", action="store_true",
@@ -924,7 +927,11 @@ def bench_serve(args, alb, gg, emit=True):
     single = alb.Server(gset, lanes=1, max_batch=1, hbm_budget=32 << 30)
     # continuous batching inside a launch: requests join a running launch of
     # their algorithm between rounds and leave when their traversal converges
-    joined = alb.Server(gset, lanes=1, max_batch=512, hbm_budget=32 << 30, join_running=True)
+    if args.join_long_edges > 0:  # long and short requests on lanes of their own
+        join_cfg = dict(lanes=2, max_batch=512, join_running=True, join_long_edges=args.join_long_edges)
+    else:
+        join_cfg = dict(lanes=1, max_batch=512, join_running=True)
+    joined = alb.Server(gset, hbm_budget=32 << 30, **join_cfg)
     warm = make_requests(200, 99)
     serve_run(alb, batched, pool, warm, None)
     serve_run(alb, single, pool, warm[:50], None)
@@ -1006,7 +1013,8 @@ def bench_serve(args, alb, gg, emit=True):
                           "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99)}, "failed": f1},
         "join_running": {"value": round(capj, 1), "unit": "queries/s", "requests": len(reqs),
                          "latency_ms": {"p50": pct(latj, 50), "p99": pct(latj, 99)}, "failed": fj,
-                         "launches": launches_j, "completed": stj["completed"]},
+                         "launches": launches_j, "completed": stj["completed"],
+                         "lanes": join_cfg["lanes"], "join_long_edges": join_cfg.get("join_long_edges", 0)},
         "poisson": rates,
         "results_checked_against_oracle": checked,
         "server_stats": st,

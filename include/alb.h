@@ -379,7 +379,12 @@ typedef struct {
                                 Needs the GPU (no executor).  0 (default): a batch is fixed when its launch
                                 starts. */
   int32_t join_idle_us;      /* join_running: idle time before a launch ends; 0 = 500 us */
-  int32_t reserved[5];
+  int32_t reserved0;
+  int64_t join_long_edges;   /* join_running with lanes >= 2: a request whose member graph has at least this
+                                many edges runs on lane 0, every other request on the other lanes, so that
+                                short queries do not advance in rounds shared with long ones; 0 (default):
+                                any lane takes any request */
+  int32_t reserved[2];
 } alb_server_config;
 
 typedef struct {

@@ -107,7 +107,9 @@ class ServerConfig(ctypes.Structure):
         ("whole_device_when_alone", ctypes.c_int32),
         ("join_running", ctypes.c_int32),
         ("join_idle_us", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("reserved0", ctypes.c_int32),
+        ("join_long_edges", ctypes.c_int64),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -544,13 +546,14 @@ class Server:
 
     def __init__(self, gs: Optional[GraphSet] = None, lanes: int = 2, max_batch: int = 256, max_wait_us: int = 0,
                  hbm_budget: int = 0, executor=None, member_vertices=None, whole_device_when_alone: bool = True,
-                 join_running: bool = False, join_idle_us: int = 0, **opts):
+                 join_running: bool = False, join_idle_us: int = 0, join_long_edges: int = 0, **opts):
         cfg = ServerConfig()
         _check(_lib.alb_server_config_init(ctypes.byref(cfg)), "alb_server_config_init")
         cfg.lanes, cfg.max_batch, cfg.max_wait_us, cfg.hbm_budget = lanes, max_batch, max_wait_us, hbm_budget
         cfg.whole_device_when_alone = 1 if whole_device_when_alone else 0
         cfg.join_running = 1 if join_running else 0
         cfg.join_idle_us = int(join_idle_us)
+        cfg.join_long_edges = int(join_long_edges)
         cfg.options = make_options(**opts)
         if gs is not None:
             self.member_n = [m[0] for m in gs.members]

@@ -157,6 +157,18 @@ struct alb_server_s {
   // running; queued requests of that algorithm join it between rounds while
   // a slot and label memory are free, and complete as soon as their own
   // traversal has converged.  The launch ends by itself when idle.
+  // join_long_edges: which requests lane `lane` takes
+  bool lane_takes(int lane, const Request &r) const {
+    if (cfg.join_long_edges <= 0 || cfg.lanes < 2) return true;
+    return (r.edges >= cfg.join_long_edges) == (lane == 0);
+  }
+
+  bool pending_for(int lane) {
+    for (uint64_t t : pending)
+      if (lane_takes(lane, reqs[t])) return true;
+    return false;
+  }
+
   void lane_main_join(int lane) {
     const long long cap = (long long)(lane_budget / kBytesPerVertex);
     const int32_t nslots = std::min(cfg.max_batch, alb::kOpenMaxSlots);
@@ -182,14 +194,14 @@ struct alb_server_s {
     };
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      cv_work.wait(lk, [&] { return stop || pending_for(lane); });
       expire(Clock::now());
-      if (pending.empty()) {
+      if (!pending_for(lane)) {
         if (stop) break;
         continue;
       }
       if (cst != ALB_OK) {  // the lane has no device workspace: fail what it would have run
-        fail_pending(-1, cst, Clock::now());
+        fail_pending(-1, cst, Clock::now(), lane);
         continue;
       }
       ++busy_lanes;
@@ -198,14 +210,14 @@ struct alb_server_s {
       {
         int32_t cnt = 0;
         for (uint64_t t : pending)
-          if (cnt++ < nslots) queued_edges += reqs[t].edges;
+          if (lane_takes(lane, reqs[t]) && cnt++ < nslots) queued_edges += reqs[t].edges;
       }
       lk.unlock();
       const Clock::time_point t0 = Clock::now();
       const alb_status ls = alb::open_lane_start(L, streams[lane], idle_us, queued_edges);
       lk.lock();
       if (ls != ALB_OK) {
-        fail_pending(-1, ls, Clock::now());
+        fail_pending(-1, ls, Clock::now(), lane);
         --busy_lanes;
         continue;
       }
@@ -224,6 +236,10 @@ struct alb_server_s {
           uint64_t room = (uint64_t)alb::kOpenMaxSlots - alb::open_lane_backlog(L);
           for (auto it = pending.begin(); it != pending.end() && !free_slots.empty() && room > 0;) {
             Request &r = reqs[*it];
+            if (!lane_takes(lane, r)) {  // another lane's class
+              ++it;
+              continue;
+            }
             if (active_edges + r.edges >= kMaxPositions) break;  // one round's huge edges stay 32-bit
             // a query that wants a bigger grid than the launch was started
             // with would run on too few workgroups: the launch ends once it
@@ -364,10 +380,11 @@ struct alb_server_s {
     if (any) cv_done.notify_all();
   }
 
-  void fail_pending(int32_t algo, alb_status status, Clock::time_point now) {  // algo -1: every request
+  // algo -1: every algorithm; lane >= 0: only the requests that lane takes
+  void fail_pending(int32_t algo, alb_status status, Clock::time_point now, int lane = -1) {
     for (auto it = pending.begin(); it != pending.end();) {
       Request &r = reqs[*it];
-      if (algo < 0 || r.algo == algo) {
+      if ((algo < 0 || r.algo == algo) && (lane < 0 || lane_takes(lane, r))) {
         complete(r, status, now);
         it = pending.erase(it);
       } else {
@@ -508,6 +525,9 @@ alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_ser
   if (cfg.join_running && (cfg.executor || !g))
     return set_error(ALB_E_INVAL, "join_running needs the GPU: a graph and no executor");
   if (cfg.join_idle_us < 0) return set_error(ALB_E_INVAL, "join_idle_us must be >= 0");
+  if (cfg.join_long_edges < 0) return set_error(ALB_E_INVAL, "join_long_edges must be >= 0");
+  if (cfg.join_long_edges > 0 && (!cfg.join_running || cfg.lanes < 2))
+    return set_error(ALB_E_INVAL, "join_long_edges needs join_running and at least two lanes");
   {  // the traversal options every batch or launch of the server uses, defaults filled in
     alb_options o;
     const alb_status st = alb::check_options(&cfg.options, &o);
@@ -610,7 +630,11 @@ alb_status alb_server_submit(alb_server s, int32_t algo, int32_t member, int32_t
     ++s->st.submitted;
     *ticket = t;
   }
-  s->cv_work.notify_one();
+  // with join_long_edges a lane waits for its own class of requests: wake them all
+  if (s->cfg.join_running && s->cfg.join_long_edges > 0)
+    s->cv_work.notify_all();
+  else
+    s->cv_work.notify_one();
   return ALB_OK;
 }
 

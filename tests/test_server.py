@@ -261,3 +261,12 @@ def test_bad_traversal_options_are_refused_at_create(alb):
     with pytest.raises(alb.AlbError) as e:
         alb.Server(None, lanes=1, executor=Fake(), member_vertices=[10], wave_cutoff=-3)
     assert e.value.status == alb.ALB_E_INVAL
+
+
+def test_join_long_edges_needs_join_running_and_two_lanes(alb):
+    with pytest.raises(alb.AlbError) as e:
+        alb.Server(None, lanes=2, executor=Fake(), member_vertices=[10], join_long_edges=5)
+    assert e.value.status == alb.ALB_E_INVAL
+    with pytest.raises(alb.AlbError) as e:
+        alb.Server(None, lanes=2, executor=Fake(), member_vertices=[10], join_long_edges=-1)
+    assert e.value.status == alb.ALB_E_INVAL

@@ -221,3 +221,19 @@ def test_join_running_with_traversal_options(alb, gset, members, opts):
         for t, (a, m, s) in zip(tickets, reqs):
             out, _ = srv.wait(t)
             assert np.array_equal(out, reference(members, a, m, s)), (a, m, s, opts)
+
+
+def test_join_running_long_and_short_lanes(alb, gset, members):
+    """join_long_edges: requests on the member with the most edges run on
+    lane 0, all others on lane 1, each lane keeping its own running launch;
+    every result equals the oracle's."""
+    big = int(np.argmax([g.m for g in members]))
+    reqs = requests(members, 120, seed=90)
+    with alb.Server(gset, lanes=2, max_batch=64, join_running=True, join_long_edges=members[big].m) as srv:
+        tickets = [srv.submit(a, m, s) for a, m, s in reqs]
+        for t, (a, m, s) in zip(tickets, reqs):
+            out, info = srv.wait(t)
+            assert np.array_equal(out, reference(members, a, m, s)), (a, m, s)
+            assert info["lane"] == (0 if m == big else 1), (m, info)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
