@@ -53,3 +53,32 @@ def test_rocprof_overlap_sweep():
     assert r["streams"] == {1: 3, 2: 2, 3: 1}
     assert r["kernel_ns_summed"] == 10 + 10 + 5 + 10 + 2 + 2
     assert rs.overlap([])["busy_ns"] == 0
+
+
+def test_rocprof_traffic_scaling(tmp_path):
+    """The HBM-traffic summary on hand-made counter files: per-dispatch sums
+    over the counter's instances, averaged over dispatches, scaled by what
+    the same counter read for a copy of known size."""
+    from paper_1911_09135_amd import rocprof_summary as rs
+
+    def write(d, kernel, counter, per_dispatch):
+        d.mkdir()
+        with open(d / "run_counter_collection.csv", "w") as f:
+            f.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+            for i, vals in enumerate(per_dispatch):
+                for v in vals:  # one row per counter instance
+                    f.write('%d,"%s","%s",%s\n' % (i + 1, kernel, counter, v))
+        return str(d)
+
+    gib = 1 << 30
+    fk = write(tmp_path / "f", "k_persistent<256>", "FETCH_SIZE", [[100, 300], [200, 200]])  # 400 KiB each
+    wk = write(tmp_path / "w", "k_persistent<256>", "WRITE_SIZE", [[50, 50], [30, 70]])  # 100 KiB each
+    # the copy's FETCH_SIZE reads half its bytes (factor 2), WRITE_SIZE all of them (factor 1)
+    fc = write(tmp_path / "cf", "copyBuffer", "FETCH_SIZE", [[gib / 1024 / 2]])
+    wc = write(tmp_path / "cw", "copyBuffer", "WRITE_SIZE", [[gib / 1024]])
+    r = rs.traffic(fk, wk, fc, wc, "k_persistent", copy_bytes=gib)
+    assert r["dispatches"] == [2, 2]
+    assert r["fetch_scale"] == 2.0 and r["write_scale"] == 1.0
+    assert r["fetch_bytes_per_launch"] == 400 * 1024 * 2
+    assert r["write_bytes_per_launch"] == 100 * 1024
+    assert r["bytes_per_launch"] == 400 * 1024 * 2 + 100 * 1024
