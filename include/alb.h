@@ -108,7 +108,12 @@ typedef struct {
   int64_t worklist_capacity; /* 0 = automatic (n with dedup, n + m without) */
   void *stream;              /* hipStream_t; NULL = the library's stream */
   uint32_t out_on_device;    /* outputs are device pointers (see above) */
-  int32_t reserved[7];
+  int32_t visited_filter;    /* BFS, persistent launch: once at least half of the vertices have been reached,
+                                a bitmap of the reached ones (one bit per vertex, built from the levels in one
+                                pass) is checked before a destination's level is read, so that edges into
+                                reached vertices touch the small bitmap instead of the level array.
+                                0 = automatic (on for graphs of at least 2^20 vertices), 1 = on, -1 = off */
+  int32_t reserved[6];
 } alb_options;
 
 typedef struct {

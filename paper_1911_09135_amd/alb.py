@@ -61,7 +61,8 @@ class Options(ctypes.Structure):
         ("worklist_capacity", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
         ("out_on_device", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("visited_filter", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -206,7 +207,7 @@ def _check(status: int, where: str) -> None:
 def make_options(mode: str = "alb", threshold: Optional[int] = None, wg_size: int = 0, wave_cutoff: int = 0,
                  wg_cutoff: int = 0, dedup: Optional[bool] = None, launch: str = "auto", grid_wgs: int = 0,
                  worklist_capacity: int = 0, stream=None, out_on_device: bool = False,
-                 distribution: int = 0) -> Options:
+                 distribution: int = 0, visited_filter: Optional[bool] = None) -> Options:
     o = Options()
     _check(_lib.alb_options_init(ctypes.byref(o)), "alb_options_init")
     o.mode = MODES[mode]
@@ -228,6 +229,7 @@ def make_options(mode: str = "alb", threshold: Optional[int] = None, wg_size: in
     o.worklist_capacity = int(worklist_capacity)
     o.stream = _stream_handle(stream)
     o.out_on_device = 1 if out_on_device else 0
+    o.visited_filter = 0 if visited_filter is None else (1 if visited_filter else -1)
     return o
 
 

@@ -455,6 +455,7 @@ alb_status resolve_options(const alb_options *user, alb_options &o) {
   if (o.distribution != 0 && o.distribution != 1)
     return fail(ALB_E_UNSUPPORTED, "distribution %d (0 cyclic, 1 blocked)", o.distribution);
   if (o.dedup < -1 || o.dedup > 1) return fail(ALB_E_INVAL, "bad dedup %d", o.dedup);
+  if (o.visited_filter < -1 || o.visited_filter > 1) return fail(ALB_E_INVAL, "bad visited_filter %d", o.visited_filter);
   if (o.launch < ALB_LAUNCH_AUTO || o.launch > ALB_LAUNCH_PERSISTENT) return fail(ALB_E_INVAL, "bad launch %d", o.launch);
   if (o.grid_wgs < ALB_GRID_ALL) return fail(ALB_E_INVAL, "grid_wgs must be >= -1");
   if (o.worklist_capacity < 0 || o.worklist_capacity > 0xfffffffeLL) return fail(ALB_E_INVAL, "bad worklist_capacity");
@@ -753,7 +754,12 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
   a.timeout_ticks = g->clock_khz * barrier_timeout_ms();
   a.join_window_ticks = std::max<uint64_t>(g->clock_khz / 100, 1);  // 10 us without a new member
   a.profile = (getenv("ALB_TIMELINE") && !fixed) ? 1 : 0;
-  if (job.op == OP_BFS) a.level = dev_out ? (int32_t *)dev_out : ws->labels;
+  if (job.op == OP_BFS) {
+    a.level = dev_out ? (int32_t *)dev_out : ws->labels;
+    // the reached-vertex bitmap lives in the label words, which BFS does not use
+    const bool filter = o.visited_filter == 1 || (o.visited_filter == 0 && g->n >= kVisitedFilterMinVertices);
+    if (filter && launch == ALB_LAUNCH_PERSISTENT) a.vbits = (uint32_t *)ws->word;
+  }
   if (job.op == OP_SSSP || job.op == OP_CC) {
     a.word = ws->word;
     a.out = dev_out ? (int32_t *)dev_out : ws->labels;

@@ -44,6 +44,9 @@ constexpr int kHintMinShift = 10;
 // worth of edges goes to the cyclic distribution, which keeps every
 // workgroup busy.
 constexpr int kAdaptiveSmall = 64;
+// BFS turns the reached-vertex filter on by default from this many vertices
+// (a level array of 4 MB, one XCD's L2; its bitmap is 32 times smaller).
+constexpr int32_t kVisitedFilterMinVertices = 1 << 20;
 constexpr int kHintMaxShift = 20;
 // Queries in one batch launch (the output kernel puts one query on each grid row).
 constexpr int32_t kMaxBatch = 65535;
@@ -165,6 +168,7 @@ struct Args {
   uint32_t *prof_wg;       // profiling: [kTimeline][kProfMembers] edges per round and member, or null
   // operator state
   int32_t *level;       // BFS levels; k-core: remaining degrees
+  uint32_t *vbits;      // BFS: room for the reached-vertex bitmap (ceil(n / 32) words), or null: no filter
   int32_t kcore_k;      // k-core: k
   unsigned long long *word;  // SSSP / CC: (label << 32) | tag, tag = 1 + last round that lowered it
   int32_t *out;         // SSSP / CC: int32 labels written by the finishing kernel

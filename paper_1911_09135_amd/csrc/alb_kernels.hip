@@ -98,10 +98,17 @@ struct OpBFS {
   };
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false, kBatch = true;
   int32_t *level;
+  // reached-vertex bitmap, set once the persistent launch has built it: a
+  // destination whose bit is set is not unreached, and its level is not read
+  // (a clear bit says nothing: the level decides)
+  const uint32_t *vbits = nullptr;
   __device__ __forceinline__ val_t load_src(long long, int32_t, uint32_t tag, bool &) const {
     return (int32_t)tag - 1;
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const { return {level[dl]}; }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const {
+    if (vbits && ((vbits[dl >> 5] >> (dl & 31)) & 1u)) return {0};
+    return {level[dl]};
+  }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
     if (p.cur != kInf) return false;
@@ -1222,6 +1229,24 @@ __global__ __launch_bounds__(B) void k_pr_update(Args a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->rounds, (uint32_t)a.round + 1u);
 }
 
+// BFS reached-vertex bitmap from the levels: word x holds vertices
+// [32x, 32x + 32).  Each wavefront of the members tests 64 consecutive
+// levels (coalesced) and two of its lanes store the ballot's halves.
+template <int B>
+__device__ void build_visited(const Args &a, Grid gr) {
+  const uint32_t n = (uint32_t)a.n;
+  const uint32_t words = (n + 31u) / 32u;
+  const uint32_t lane = lane_id();
+  const uint32_t nwaves = (uint32_t)gr.n * (B / kWave);
+  for (uint32_t base = ((uint32_t)gr.id * (B / kWave) + threadIdx.x / kWave) * kWave; base < n;
+       base += nwaves * kWave) {
+    const uint32_t v = base + lane;
+    const unsigned long long m = __ballot(v < n && a.level[v] != kInf);
+    const uint32_t x = base / 32u + lane;
+    if (lane < 2 && x < words) a.vbits[x] = (uint32_t)(m >> (32 * lane));
+  }
+}
+
 template <int B, class Op, bool M>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER_EU))) void k_persistent(Args a,
                                                                                                            Op op) {
@@ -1231,11 +1256,23 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
   if (!join_members(a, sm, &gr)) return;
   if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // the launched thread count (the paper's rule)
   unsigned long long epoch = 0, prof_last = 0;
+  uint64_t reached = 0;  // BFS: vertices in the worklists so far (each is in exactly one round's)
   int r = 0;
   for (; r < a.max_rounds; ++r) {
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;  // set in an earlier round: seen by all alike
     const uint32_t nF = round_size(a, r);
     if (nF == 0) break;
+    if constexpr (std::is_same<Op, OpBFS>::value && !M) {
+      // once half of the vertices have been reached, most edges lead to
+      // reached vertices: build the bitmap (every member decides alike from
+      // the worklist sizes) and filter with it from this round on
+      reached += nF;
+      if (a.vbits && !op.vbits && 2 * reached >= (uint64_t)a.n) {
+        build_visited<B>(a, gr);
+        if (!grid_barrier(a, sm, gr, epoch, r)) break;
+        op.vbits = a.vbits;
+      }
+    }
     const bool tl = gr.id == 0 && threadIdx.x == 0 && r < kTimeline;
     if (gr.id == 0 && threadIdx.x == 0) clear_ahead(a, r);
     if (tl) a.ctl->tl[4 * r] = (unsigned long long)wall_clock64();

@@ -212,3 +212,10 @@ def test_binding_has_no_cpu_fallback():
         r = subprocess.run(["python", "-c", code], capture_output=True, text=True, env=env)
     assert r.returncode != 0
     assert "not built" in r.stderr
+
+
+def test_visited_filter_option_is_validated(alb):
+    o = alb.make_options()
+    assert o.visited_filter == 0  # automatic
+    assert alb.make_options(visited_filter=True).visited_filter == 1
+    assert alb.make_options(visited_filter=False).visited_filter == -1

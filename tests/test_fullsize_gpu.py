@@ -72,8 +72,10 @@ def test_bfs_zipf24_full(alb, zipf24):
     ref = oracle.bfs(g, s)
     log("oracle bfs %.1fs" % (time.time() - t))
     dg = alb.Graph(g.off, g.col)
+    # the default turns the reached-vertex filter on at this size; also without it
     for c in [dict(), dict(threshold=4096), dict(mode="twc"), dict(threshold=4096, launch="host"),
-              dict(distribution=1), dict(mode="lb_all"), dict(threshold="adaptive"), dict(wg_size=1024)]:
+              dict(distribution=1), dict(mode="lb_all"), dict(threshold="adaptive"), dict(wg_size=1024),
+              dict(visited_filter=False), dict(mode="twc", visited_filter=False)]:
         lv, st = alb.bfs(dg, s, **c)
         assert np.array_equal(lv, ref), c
         log("bfs %s ok: rounds %d, huge %d, %.2f ms" % (c, st["rounds"], st["huge_vertices"], st["device_ms"]))
