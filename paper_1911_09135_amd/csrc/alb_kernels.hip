@@ -98,23 +98,28 @@ struct OpBFS {
   };
   static constexpr bool kPush = true, kNeedSrc = false, kRecord = false, kPR = false, kBatch = true;
   int32_t *level;
-  // reached-vertex bitmap, set once the persistent launch has built it: a
-  // destination whose bit is set is not unreached, and its level is not read
-  // (a clear bit says nothing: the level decides)
-  const uint32_t *vbits = nullptr;
   __device__ __forceinline__ val_t load_src(long long, int32_t, uint32_t tag, bool &) const {
     return (int32_t)tag - 1;
   }
-  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const {
-    if (vbits && ((vbits[dl >> 5] >> (dl & 31)) & 1u)) return {0};
-    return {level[dl]};
-  }
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const { return {level[dl]}; }
   __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t sv, int32_t, int32_t,
                                          uint32_t) const {
     if (p.cur != kInf) return false;
     int32_t expected = kInf;
     return __hip_atomic_compare_exchange_strong(&level[dl], &expected, sv + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// BFS once the persistent launch has built the reached-vertex bitmap: a
+// destination whose bit is set has been reached and its level is not read
+// (a clear bit says nothing: the level decides).  A type of its own, so that
+// the rounds before the bitmap exists run the plain operator's code.
+struct OpBFSFilter : OpBFS {
+  const uint32_t *vbits;
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const {
+    if ((vbits[dl >> 5] >> (dl & 31)) & 1u) return {0};
+    return {level[dl]};
   }
 };
 
@@ -355,7 +360,7 @@ struct Pusher {
 };
 
 template <int B, class Op, bool M>
-__device__ void flush_stats(Acc &acc, Smem<B, Op, M> &sm, Ctl *c) {
+__device__ __forceinline__ void flush_stats(Acc &acc, Smem<B, Op, M> &sm, Ctl *c) {
   const uint32_t lane = lane_id();
   const int w = threadIdx.x / kWave;
   unsigned long long v[5] = {acc.frontier, acc.edges_twc, acc.edges_lb, acc.huge_v, acc.pushes};
@@ -626,8 +631,8 @@ struct Claims {
 };
 
 
-template <int B, class Op, bool M>
-__device__ void phase_twc(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid gr, int round,
+template <int B, class Op, bool M, class S>
+__device__ __forceinline__ void phase_twc(const Args &a, const Op &op, S &sm, Grid gr, int round,
                           const Entry<M> *F, uint32_t nF, Entry<M> *qn, uint32_t *qn_cnt, unsigned long long *hctr,
                           int64_t threshold, uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
@@ -823,8 +828,8 @@ __device__ __forceinline__ uint32_t owner_of(const Args &a, uint32_t vh, uint32_
 // ---------------------------------------------------------------------------
 // Phase 2: execution (Algorithm 2) with the cyclic distribution.
 // ---------------------------------------------------------------------------
-template <int B, class Op, bool M>
-__device__ void phase_lb(const Args &a, const Op &op, Smem<B, Op, M> &sm, Grid gr, int round, unsigned long long hc,
+template <int B, class Op, bool M, class S>
+__device__ __forceinline__ void phase_lb(const Args &a, const Op &op, S &sm, Grid gr, int round, unsigned long long hc,
                          Entry<M> *qn, uint32_t *qn_cnt, uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
   const uint32_t vh = (uint32_t)(hc >> 32);
@@ -941,7 +946,7 @@ __device__ __forceinline__ bool bar_wait(const Args &a, unsigned long long *w, u
 // invalidate elsewhere was tried and gave stale reads).  Counters only grow,
 // so nothing is reset between barriers.
 template <class S>
-__device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round,
+__device__ __forceinline__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round,
                              bool sys = false) {
   wait_memory();
   __syncthreads();
@@ -1015,7 +1020,7 @@ __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
 // itself on its XCD, for the barrier.  Returns false for a non-member; *gr
 // gets (ticket, member count, XCD, members on that XCD, XCDs in use).
 template <class S>
-__device__ bool join_members(const Args &a, S &sm, Grid *gr) {
+__device__ __forceinline__ bool join_members(const Args &a, S &sm, Grid *gr) {
   constexpr unsigned long long kClosed = 1ull << 63;
   if (threadIdx.x == 0) {
     Ctl *c = a.ctl;
@@ -1233,7 +1238,7 @@ __global__ __launch_bounds__(B) void k_pr_update(Args a) {
 // [32x, 32x + 32).  Each wavefront of the members tests 64 consecutive
 // levels (coalesced) and two of its lanes store the ballot's halves.
 template <int B>
-__device__ void build_visited(const Args &a, Grid gr) {
+__device__ __forceinline__ void build_visited(const Args &a, Grid gr) {
   const uint32_t n = (uint32_t)a.n;
   const uint32_t words = (n + 31u) / 32u;
   const uint32_t lane = lane_id();
@@ -1257,6 +1262,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
   if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // the launched thread count (the paper's rule)
   unsigned long long epoch = 0, prof_last = 0;
   uint64_t reached = 0;  // BFS: vertices in the worklists so far (each is in exactly one round's)
+  bool filtered = false;  // BFS: the reached-vertex bitmap has been built
   int r = 0;
   for (; r < a.max_rounds; ++r) {
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;  // set in an earlier round: seen by all alike
@@ -1267,10 +1273,10 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
       // reached vertices: build the bitmap (every member decides alike from
       // the worklist sizes) and filter with it from this round on
       reached += nF;
-      if (a.vbits && !op.vbits && 2 * reached >= (uint64_t)a.n) {
+      if (a.vbits && !filtered && 2 * reached >= (uint64_t)a.n) {
         build_visited<B>(a, gr);
         if (!grid_barrier(a, sm, gr, epoch, r)) break;
-        op.vbits = a.vbits;
+        filtered = true;
       }
     }
     const bool tl = gr.id == 0 && threadIdx.x == 0 && r < kTimeline;
@@ -1281,8 +1287,20 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
     const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
     // batch with per-query thresholds: chunk index sized for the smallest one
     const uint32_t hs = hint_shift(M && a.qthr ? a.qthr_min : thr);
-    phase_twc<B, Op, M>(a, op, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], thr, hs,
-                        acc);
+    bool done_twc = false;
+    if constexpr (std::is_same<Op, OpBFS>::value && !M) {
+      if (filtered) {
+        OpBFSFilter fop;
+        fop.level = op.level;
+        fop.vbits = a.vbits;
+        phase_twc<B, OpBFSFilter, M>(a, fop, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1],
+                                     thr, hs, acc);
+        done_twc = true;
+      }
+    }
+    if (!done_twc)
+      phase_twc<B, Op, M>(a, op, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], thr, hs,
+                          acc);
     if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
     uint64_t pb = a.profile ? (uint64_t)wall_clock64() : 0;
     if (!grid_barrier(a, sm, gr, epoch, r)) break;
@@ -1293,7 +1311,17 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
       a.ctl->tl[4 * r + 3] = (unsigned long long)nF | ((hc >> 32) << 32);
     }
     if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
-      phase_lb<B, Op, M>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+      bool done_lb = false;
+      if constexpr (std::is_same<Op, OpBFS>::value && !M) {
+        if (filtered) {
+          OpBFSFilter fop;
+          fop.level = op.level;
+          fop.vbits = a.vbits;
+          phase_lb<B, OpBFSFilter, M>(a, fop, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+          done_lb = true;
+        }
+      }
+      if (!done_lb) phase_lb<B, Op, M>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
       pb = a.profile ? (uint64_t)wall_clock64() : 0;
       if (!grid_barrier(a, sm, gr, epoch, r)) break;
       prof_mark(a, acc, kProfBarrier, pb);
