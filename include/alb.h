@@ -112,7 +112,7 @@ typedef struct {
                                 a bitmap of the reached ones (one bit per vertex, built from the levels in one
                                 pass) is checked before a destination's level is read, so that edges into
                                 reached vertices touch the small bitmap instead of the level array.
-                                0 = automatic (on for graphs of at least 2^22 vertices), 1 = on, -1 = off */
+                                0 = automatic (on for graphs of at least 2^23 vertices), 1 = on, -1 = off */
   int32_t reserved[6];
 } alb_options;
 

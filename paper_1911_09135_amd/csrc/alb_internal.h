@@ -45,10 +45,11 @@ constexpr int kHintMinShift = 10;
 // workgroup busy.
 constexpr int kAdaptiveSmall = 64;
 // BFS turns the reached-vertex filter on by default from this many vertices
-// (a level array of 16 MB, four times one XCD's L2; its bitmap is 32 times
-// smaller).  Measured: neutral on RMAT scale 22, +2 % and +6 % kernel time
-// on scales 20 and 18, -35 % on the Zipf graph of 2^24 vertices.
-constexpr int32_t kVisitedFilterMinVertices = 1 << 22;
+// (a level array of 32 MB, eight times one XCD's L2; its bitmap is 32 times
+// smaller).  Measured: -35 % kernel time on the Zipf graph of 2^24
+// vertices; on RMAT scales 18 to 22 no gain, the filtering kernel 1-6 %
+// slower than the plain one.
+constexpr int32_t kVisitedFilterMinVertices = 1 << 23;
 constexpr int kHintMaxShift = 20;
 // Queries in one batch launch (the output kernel puts one query on each grid row).
 constexpr int32_t kMaxBatch = 65535;

@@ -360,7 +360,7 @@ struct Pusher {
 };
 
 template <int B, class Op, bool M>
-__device__ __forceinline__ void flush_stats(Acc &acc, Smem<B, Op, M> &sm, Ctl *c) {
+__device__ void flush_stats(Acc &acc, Smem<B, Op, M> &sm, Ctl *c) {
   const uint32_t lane = lane_id();
   const int w = threadIdx.x / kWave;
   unsigned long long v[5] = {acc.frontier, acc.edges_twc, acc.edges_lb, acc.huge_v, acc.pushes};
@@ -632,7 +632,7 @@ struct Claims {
 
 
 template <int B, class Op, bool M, class S>
-__device__ __forceinline__ void phase_twc(const Args &a, const Op &op, S &sm, Grid gr, int round,
+__device__ void phase_twc(const Args &a, const Op &op, S &sm, Grid gr, int round,
                           const Entry<M> *F, uint32_t nF, Entry<M> *qn, uint32_t *qn_cnt, unsigned long long *hctr,
                           int64_t threshold, uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
@@ -829,7 +829,7 @@ __device__ __forceinline__ uint32_t owner_of(const Args &a, uint32_t vh, uint32_
 // Phase 2: execution (Algorithm 2) with the cyclic distribution.
 // ---------------------------------------------------------------------------
 template <int B, class Op, bool M, class S>
-__device__ __forceinline__ void phase_lb(const Args &a, const Op &op, S &sm, Grid gr, int round, unsigned long long hc,
+__device__ void phase_lb(const Args &a, const Op &op, S &sm, Grid gr, int round, unsigned long long hc,
                          Entry<M> *qn, uint32_t *qn_cnt, uint32_t hs, Acc &acc) {
   using V = typename Op::val_t;
   const uint32_t vh = (uint32_t)(hc >> 32);
@@ -946,7 +946,7 @@ __device__ __forceinline__ bool bar_wait(const Args &a, unsigned long long *w, u
 // invalidate elsewhere was tried and gave stale reads).  Counters only grow,
 // so nothing is reset between barriers.
 template <class S>
-__device__ __forceinline__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round,
+__device__ bool grid_barrier(const Args &a, S &sm, Grid gr, unsigned long long &epoch, int round,
                              bool sys = false) {
   wait_memory();
   __syncthreads();
@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
 // itself on its XCD, for the barrier.  Returns false for a non-member; *gr
 // gets (ticket, member count, XCD, members on that XCD, XCDs in use).
 template <class S>
-__device__ __forceinline__ bool join_members(const Args &a, S &sm, Grid *gr) {
+__device__ bool join_members(const Args &a, S &sm, Grid *gr) {
   constexpr unsigned long long kClosed = 1ull << 63;
   if (threadIdx.x == 0) {
     Ctl *c = a.ctl;
@@ -1252,13 +1252,21 @@ __device__ __forceinline__ void build_visited(const Args &a, Grid gr) {
   }
 }
 
-template <int B, class Op, bool M>
+// F: BFS with the reached-vertex filter (a kernel of its own, so that every
+// other launch runs code without it).
+template <int B, class Op, bool M, bool F = false>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER_EU))) void k_persistent(Args a,
                                                                                                            Op op) {
   __shared__ Smem<B, Op, M> sm;
   Acc acc;
   Grid gr;
-  if (!join_members(a, sm, &gr)) return;
+  bool joined;
+  if constexpr (F) {  // the filtering kernel has two operator types' phases: everything inlined
+    [[clang::always_inline]] joined = join_members(a, sm, &gr);
+  } else {
+    joined = join_members(a, sm, &gr);
+  }
+  if (!joined) return;
   if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // the launched thread count (the paper's rule)
   unsigned long long epoch = 0, prof_last = 0;
   uint64_t reached = 0;  // BFS: vertices in the worklists so far (each is in exactly one round's)
@@ -1268,14 +1276,16 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;  // set in an earlier round: seen by all alike
     const uint32_t nF = round_size(a, r);
     if (nF == 0) break;
-    if constexpr (std::is_same<Op, OpBFS>::value && !M) {
+    if constexpr (F) {
       // once half of the vertices have been reached, most edges lead to
       // reached vertices: build the bitmap (every member decides alike from
       // the worklist sizes) and filter with it from this round on
       reached += nF;
-      if (a.vbits && !filtered && 2 * reached >= (uint64_t)a.n) {
+      if (!filtered && 2 * reached >= (uint64_t)a.n) {
         build_visited<B>(a, gr);
-        if (!grid_barrier(a, sm, gr, epoch, r)) break;
+        bool ok;
+        [[clang::always_inline]] ok = grid_barrier(a, sm, gr, epoch, r);
+        if (!ok) break;
         filtered = true;
       }
     }
@@ -1287,23 +1297,30 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
     const int64_t thr = round_threshold(a, nF, (uint64_t)gr.n * B);
     // batch with per-query thresholds: chunk index sized for the smallest one
     const uint32_t hs = hint_shift(M && a.qthr ? a.qthr_min : thr);
-    bool done_twc = false;
-    if constexpr (std::is_same<Op, OpBFS>::value && !M) {
+    if constexpr (F) {  // two operator types here: both phases inlined
       if (filtered) {
         OpBFSFilter fop;
         fop.level = op.level;
         fop.vbits = a.vbits;
-        phase_twc<B, OpBFSFilter, M>(a, fop, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1],
-                                     thr, hs, acc);
-        done_twc = true;
+        [[clang::always_inline]] phase_twc<B, OpBFSFilter, M>(a, fop, sm, gr, r, round_frontier<M>(a, r), nF, qn,
+                                                              qn_cnt, &a.ctl->huge[r & 1], thr, hs, acc);
+      } else {
+        [[clang::always_inline]] phase_twc<B, Op, M>(a, op, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt,
+                                                     &a.ctl->huge[r & 1], thr, hs, acc);
       }
-    }
-    if (!done_twc)
+    } else {
       phase_twc<B, Op, M>(a, op, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt, &a.ctl->huge[r & 1], thr, hs,
                           acc);
+    }
     if constexpr (Op::kPR) flush_dangling<B, Op>(acc, sm, &a.ctl->dangling[r & 1]);
     uint64_t pb = a.profile ? (uint64_t)wall_clock64() : 0;
-    if (!grid_barrier(a, sm, gr, epoch, r)) break;
+    bool ok1;
+    if constexpr (F) {
+      [[clang::always_inline]] ok1 = grid_barrier(a, sm, gr, epoch, r);
+    } else {
+      ok1 = grid_barrier(a, sm, gr, epoch, r);
+    }
+    if (!ok1) break;
     prof_mark(a, acc, kProfBarrier, pb);
     const unsigned long long hc = ld_relaxed(&a.ctl->huge[r & 1]);
     if (tl) {
@@ -1311,19 +1328,26 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
       a.ctl->tl[4 * r + 3] = (unsigned long long)nF | ((hc >> 32) << 32);
     }
     if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
-      bool done_lb = false;
-      if constexpr (std::is_same<Op, OpBFS>::value && !M) {
+      if constexpr (F) {
         if (filtered) {
           OpBFSFilter fop;
           fop.level = op.level;
           fop.vbits = a.vbits;
-          phase_lb<B, OpBFSFilter, M>(a, fop, sm, gr, r, hc, qn, qn_cnt, hs, acc);
-          done_lb = true;
+          [[clang::always_inline]] phase_lb<B, OpBFSFilter, M>(a, fop, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+        } else {
+          [[clang::always_inline]] phase_lb<B, Op, M>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
         }
+      } else {
+        phase_lb<B, Op, M>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
       }
-      if (!done_lb) phase_lb<B, Op, M>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
       pb = a.profile ? (uint64_t)wall_clock64() : 0;
-      if (!grid_barrier(a, sm, gr, epoch, r)) break;
+      bool ok2;
+      if constexpr (F) {
+        [[clang::always_inline]] ok2 = grid_barrier(a, sm, gr, epoch, r);
+      } else {
+        ok2 = grid_barrier(a, sm, gr, epoch, r);
+      }
+      if (!ok2) break;
       prof_mark(a, acc, kProfBarrier, pb);
     }
     if (tl) a.ctl->tl[4 * r + 2] = (unsigned long long)wall_clock64();
@@ -1338,7 +1362,11 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
     st_relaxed(&a.ctl->threshold_used, (long long)a.threshold);
     st_relaxed(&a.ctl->t_end, (unsigned long long)wall_clock64());
   }
-  flush_stats<B, Op>(acc, sm, a.ctl);
+  if constexpr (F) {
+    [[clang::always_inline]] flush_stats<B, Op>(acc, sm, a.ctl);
+  } else {
+    flush_stats<B, Op>(acc, sm, a.ctl);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1871,6 +1899,12 @@ struct LbF {
 template <int B, class Op>
 struct PersistentF {
   static hipError_t run(int grid, const Args *a, hipStream_t s) {
+    if constexpr (std::is_same<Op, OpBFS>::value) {
+      if (a->vbits) {  // BFS with the reached-vertex filter
+        hipLaunchKernelGGL((k_persistent<B, Op, false, true>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
+        return hipGetLastError();
+      }
+    }
     hipLaunchKernelGGL((k_persistent<B, Op, false>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
     return hipGetLastError();
   }

@@ -106,7 +106,7 @@ def test_bfs_matrix(alb, name):
         assert st["frontier_vertices"] == int(reached.sum()), (name, c, st)
         assert st["edges_examined"] == m_reached, (name, c, st)
         if c["launch"] == "persistent":
-            # the reached-vertex filter (automatic only from 2^22 vertices) forced on
+            # the reached-vertex filter (automatic only from 2^23 vertices) forced on
             lv, st = alb.bfs(dg, s, visited_filter=True, **c)
             assert np.array_equal(lv, ref), (name, c, "visited_filter")
             assert st["edges_examined"] == m_reached, (name, c, st)
