@@ -108,11 +108,14 @@ typedef struct {
   int64_t worklist_capacity; /* 0 = automatic (n with dedup, n + m without) */
   void *stream;              /* hipStream_t; NULL = the library's stream */
   uint32_t out_on_device;    /* outputs are device pointers (see above) */
-  int32_t visited_filter;    /* BFS, persistent launch: once at least half of the vertices have been reached,
-                                a bitmap of the reached ones (one bit per vertex, built from the levels in one
-                                pass) is checked before a destination's level is read, so that edges into
-                                reached vertices touch the small bitmap instead of the level array.
-                                0 = automatic (on for graphs of at least 2^23 vertices), 1 = on, -1 = off */
+  int32_t visited_filter;    /* BFS and CC, persistent launch: a bitmap (one bit per vertex, built from the
+                                labels in one pass) is checked before a destination's label is read, so that
+                                edges into vertices that cannot change touch the small bitmap instead of the
+                                label array.  BFS: the reached vertices, built once half of them are reached.
+                                CC: the vertices holding label 0 (the smallest id, final), rebuilt at each
+                                round's start from round 1 and used once they are half of all.
+                                0 = automatic (BFS: on for graphs of at least 2^23 vertices; CC: off),
+                                1 = on, -1 = off */
   int32_t reserved[6];
 } alb_options;
 

@@ -44,7 +44,7 @@ constexpr int kHintMinShift = 10;
 // worth of edges goes to the cyclic distribution, which keeps every
 // workgroup busy.
 constexpr int kAdaptiveSmall = 64;
-// BFS turns the reached-vertex filter on by default from this many vertices
+// BFS turns its filter on by default from this many vertices (CC only on request)
 // (a level array of 32 MB, eight times one XCD's L2; its bitmap is 32 times
 // smaller).  Measured: -35 % kernel time on the Zipf graph of 2^24
 // vertices; on RMAT scales 18 to 22 no gain, the filtering kernel 1-6 %
@@ -119,6 +119,8 @@ struct Ctl {
   // persistent launch: device wall-clock ticks when its first member joined
   // and when member 0 left the round loop
   unsigned long long t_begin, t_end;
+  // reached-vertex filter: vertices whose bit the build of round r set, at [r & 1]
+  unsigned long long filt_count[2];
   // continuous serving (member 0's bookkeeping): requests taken, slots
   // admitted in round r, its exit decision and the slots it converts
   // (finished in round r - 1), each at [r & 1] (a slow member may still read
@@ -171,7 +173,7 @@ struct Args {
   uint32_t *prof_wg;       // profiling: [kTimeline][kProfMembers] edges per round and member, or null
   // operator state
   int32_t *level;       // BFS levels; k-core: remaining degrees
-  uint32_t *vbits;      // BFS: room for the reached-vertex bitmap (ceil(n / 32) words), or null: no filter
+  uint32_t *vbits;      // BFS, CC: room for the filter bitmap (ceil(n / 32) words), or null: no filter
   int32_t kcore_k;      // k-core: k
   unsigned long long *word;  // SSSP / CC: (label << 32) | tag, tag = 1 + last round that lowered it
   int32_t *out;         // SSSP / CC: int32 labels written by the finishing kernel

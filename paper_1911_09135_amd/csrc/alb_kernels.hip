@@ -205,6 +205,44 @@ struct OpCC {  // min-label propagation
   }
 };
 
+// CC with the filter: a set bit says the destination's label is already 0,
+// the smallest vertex id, which no relaxation can lower; its word is not
+// read (a clear bit says nothing).
+struct OpCCFilter : OpCC {
+  const uint32_t *vbits;
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const {
+    if ((vbits[dl >> 5] >> (dl & 31)) & 1u) return {0ull};
+    return {word[dl]};
+  }
+};
+
+// The filtering operator of BFS and CC, and the property its bitmap records.
+template <class Op>
+struct Filtered;
+template <>
+struct Filtered<OpBFS> {
+  using type = OpBFSFilter;
+  __device__ static type make(const OpBFS &op, const Args &a) {
+    type f;
+    f.level = op.level;
+    f.vbits = a.vbits;
+    return f;
+  }
+  __device__ static bool bit(const Args &a, uint32_t v) { return a.level[v] != kInf; }  // reached
+};
+template <>
+struct Filtered<OpCC> {
+  using type = OpCCFilter;
+  __device__ static type make(const OpCC &op, const Args &a) {
+    type f;
+    f.word = op.word;
+    f.dedup = op.dedup;
+    f.vbits = a.vbits;
+    return f;
+  }
+  __device__ static bool bit(const Args &a, uint32_t v) { return (a.word[v] >> 32) == 0ull; }  // label 0
+};
+
 // k-core (peeling): an active vertex has left the core; each of its edges
 // lowers the neighbour's remaining degree, and the neighbour whose degree
 // falls from k to k - 1 leaves in the next round, so every vertex is pushed
@@ -1007,6 +1045,7 @@ __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
   st_relaxed(&a.ctl->qcount[(r + 2) % 3], 0u);
   st_relaxed(&a.ctl->huge[(r + 1) & 1], 0ull);
   st_relaxed(&a.ctl->dangling[(r + 1) & 1], 0ull);
+  st_relaxed(&a.ctl->filt_count[(r + 1) & 1], 0ull);
 }
 
 // Membership of the persistent launch.  The grid may be larger than what the
@@ -1129,6 +1168,7 @@ __global__ void k_init(Args a, int op, int32_t source, uint32_t nfront0) {
     c->st_frontier = c->st_edges_twc = c->st_edges_lb = c->st_huge_v = c->st_pushes = 0;
     c->dangling[0] = 0;
     c->dangling[1] = 0;
+    c->filt_count[0] = c->filt_count[1] = 0;
     c->members = 0;
     c->n_members = 0;
     c->diag_seen = c->diag_target = 0;
@@ -1234,25 +1274,29 @@ __global__ __launch_bounds__(B) void k_pr_update(Args a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->rounds, (uint32_t)a.round + 1u);
 }
 
-// BFS reached-vertex bitmap from the levels: word x holds vertices
+// The filter bitmap (BFS: reached; CC: label 0): word x holds vertices
 // [32x, 32x + 32).  Each wavefront of the members tests 64 consecutive
-// levels (coalesced) and two of its lanes store the ballot's halves.
-template <int B>
-__device__ __forceinline__ void build_visited(const Args &a, Grid gr) {
+// vertices (coalesced loads), two of its lanes store the ballot's halves,
+// and lane 0 adds the set bits to *count.
+template <int B, class Op>
+__device__ __forceinline__ void build_filter(const Args &a, Grid gr, unsigned long long *count) {
   const uint32_t n = (uint32_t)a.n;
   const uint32_t words = (n + 31u) / 32u;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = (uint32_t)gr.n * (B / kWave);
+  unsigned long long set = 0;
   for (uint32_t base = ((uint32_t)gr.id * (B / kWave) + threadIdx.x / kWave) * kWave; base < n;
        base += nwaves * kWave) {
     const uint32_t v = base + lane;
-    const unsigned long long m = __ballot(v < n && a.level[v] != kInf);
+    const unsigned long long m = __ballot(v < n && Filtered<Op>::bit(a, v));
     const uint32_t x = base / 32u + lane;
     if (lane < 2 && x < words) a.vbits[x] = (uint32_t)(m >> (32 * lane));
+    set += (unsigned long long)__popcll(m);
   }
+  if (lane == 0 && set) add_relaxed(count, set);
 }
 
-// F: BFS with the reached-vertex filter (a kernel of its own, so that every
+// F: BFS or CC with the filter bitmap (a kernel of its own, so that every
 // other launch runs code without it).
 template <int B, class Op, bool M, bool F = false>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER_EU))) void k_persistent(Args a,
@@ -1270,23 +1314,34 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
   if (a.threshold < 0) a.threshold = (int64_t)gr.n * B;  // the launched thread count (the paper's rule)
   unsigned long long epoch = 0, prof_last = 0;
   uint64_t reached = 0;  // BFS: vertices in the worklists so far (each is in exactly one round's)
-  bool filtered = false;  // BFS: the reached-vertex bitmap has been built
+  bool filtered = false;  // the filter bitmap is in use
   int r = 0;
   for (; r < a.max_rounds; ++r) {
     if (ld_relaxed(&a.ctl->overflow) < (uint32_t)r) break;  // set in an earlier round: seen by all alike
     const uint32_t nF = round_size(a, r);
     if (nF == 0) break;
     if constexpr (F) {
-      // once half of the vertices have been reached, most edges lead to
-      // reached vertices: build the bitmap (every member decides alike from
-      // the worklist sizes) and filter with it from this round on
-      reached += nF;
-      if (!filtered && 2 * reached >= (uint64_t)a.n) {
-        build_visited<B>(a, gr);
+      // BFS: once half of the vertices have been reached (every member
+      // decides alike from the worklist sizes), most edges lead to reached
+      // vertices: build the bitmap once and filter from this round on.
+      // CC: from round 1 on, rebuild the bitmap of label-0 vertices at each
+      // round's start and filter once they are at least half of all.
+      bool build = false;
+      if constexpr (std::is_same<Op, OpBFS>::value) {
+        reached += nF;
+        build = !filtered && 2 * reached >= (uint64_t)a.n;
+      } else {
+        build = r >= 1;
+      }
+      if (build) {
+        build_filter<B, Op>(a, gr, &a.ctl->filt_count[r & 1]);
         bool ok;
         [[clang::always_inline]] ok = grid_barrier(a, sm, gr, epoch, r);
         if (!ok) break;
-        filtered = true;
+        if constexpr (std::is_same<Op, OpBFS>::value)
+          filtered = true;
+        else
+          filtered = 2 * ld_relaxed(&a.ctl->filt_count[r & 1]) >= (unsigned long long)a.n;
       }
     }
     const bool tl = gr.id == 0 && threadIdx.x == 0 && r < kTimeline;
@@ -1299,11 +1354,10 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
     const uint32_t hs = hint_shift(M && a.qthr ? a.qthr_min : thr);
     if constexpr (F) {  // two operator types here: both phases inlined
       if (filtered) {
-        OpBFSFilter fop;
-        fop.level = op.level;
-        fop.vbits = a.vbits;
-        [[clang::always_inline]] phase_twc<B, OpBFSFilter, M>(a, fop, sm, gr, r, round_frontier<M>(a, r), nF, qn,
-                                                              qn_cnt, &a.ctl->huge[r & 1], thr, hs, acc);
+        using FOp = typename Filtered<Op>::type;
+        const FOp fop = Filtered<Op>::make(op, a);
+        [[clang::always_inline]] phase_twc<B, FOp, M>(a, fop, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt,
+                                                      &a.ctl->huge[r & 1], thr, hs, acc);
       } else {
         [[clang::always_inline]] phase_twc<B, Op, M>(a, op, sm, gr, r, round_frontier<M>(a, r), nF, qn, qn_cnt,
                                                      &a.ctl->huge[r & 1], thr, hs, acc);
@@ -1330,10 +1384,9 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
     if ((hc >> 32) != 0) {  // the execution phase runs only when there is imbalance to fix
       if constexpr (F) {
         if (filtered) {
-          OpBFSFilter fop;
-          fop.level = op.level;
-          fop.vbits = a.vbits;
-          [[clang::always_inline]] phase_lb<B, OpBFSFilter, M>(a, fop, sm, gr, r, hc, qn, qn_cnt, hs, acc);
+          using FOp = typename Filtered<Op>::type;
+          const FOp fop = Filtered<Op>::make(op, a);
+          [[clang::always_inline]] phase_lb<B, FOp, M>(a, fop, sm, gr, r, hc, qn, qn_cnt, hs, acc);
         } else {
           [[clang::always_inline]] phase_lb<B, Op, M>(a, op, sm, gr, r, hc, qn, qn_cnt, hs, acc);
         }
@@ -1899,8 +1952,8 @@ struct LbF {
 template <int B, class Op>
 struct PersistentF {
   static hipError_t run(int grid, const Args *a, hipStream_t s) {
-    if constexpr (std::is_same<Op, OpBFS>::value) {
-      if (a->vbits) {  // BFS with the reached-vertex filter
+    if constexpr (std::is_same<Op, OpBFS>::value || std::is_same<Op, OpCC>::value) {
+      if (a->vbits) {  // with the filter bitmap
         hipLaunchKernelGGL((k_persistent<B, Op, false, true>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
         return hipGetLastError();
       }

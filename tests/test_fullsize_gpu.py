@@ -90,7 +90,9 @@ def test_cc_zipf24_full(alb, zipf24):
     t = time.time()
     dg = alb.Graph(g.off, g.col, None, build_symmetric=True)
     log("symmetrised on the host in %.1fs: m=%d" % (time.time() - t, dg.m))
-    for c in [dict(), dict(threshold=4096), dict(mode="twc"), dict(distribution=1), dict(threshold=64)]:
+    # also with the label-0 filter (on request only)
+    for c in [dict(), dict(threshold=4096), dict(mode="twc"), dict(distribution=1), dict(threshold=64),
+              dict(visited_filter=True), dict(mode="twc", visited_filter=True)]:
         lab, st = alb.cc(dg, **c)
         assert np.array_equal(lab, ref), c
         log("cc %s ok: rounds %d, %.2f ms" % (c, st["rounds"], st["device_ms"]))

@@ -145,6 +145,10 @@ def test_cc_matrix(alb, name):
     for c in configs(dg.max_out_degree):
         lab, _ = alb.cc(dg, **c)
         assert np.array_equal(lab, ref), (name, c)
+        if c["launch"] == "persistent":
+            # the label-0 filter (on request only) forced on
+            lab, _ = alb.cc(dg, visited_filter=True, **c)
+            assert np.array_equal(lab, ref), (name, c, "visited_filter")
     check_no_dedup(alb, lambda **o: alb.cc(dg, **o)[0], ref, g)
 
 
