@@ -696,6 +696,12 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True, par
         res.setdefault("bfs", {})[label] = dict({"kernel_ms": round(ms, 4), "gteps": round(m_r / ms / 1e6, 3),
                                                  "huge_vertices": st["huge_vertices"]}, **rates(b, ms))
         log("bfs %s: %.3f ms" % (label, ms))
+    if "bfs" in parts and not args.only_alb:
+        # the reached-vertex filter (on by default at this size) switched off
+        ms, _ = timed(alb.bfs, dg, out, dict(alb_opts, visited_filter=False), src)
+        res["bfs"]["alb_without_filter"] = {"kernel_ms": round(ms, 4),
+                                            "same_result": bool(np.array_equal(out.cpu().numpy(), levels))}
+        log("bfs alb without the reached-vertex filter: %.3f ms" % ms)
     m_reached = None
     if "bfs" in parts:
         if not args.only_alb:
@@ -765,6 +771,12 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True, par
         log("cc %s: %.3f ms" % (label, ms))
     if "cc" in parts and not args.only_alb:
         res["cc"]["alb_over_twc"] = round(res["cc"]["twc_only"]["kernel_ms"] / res["cc"]["alb"]["kernel_ms"], 2)
+        # the label-0 filter (on request only)
+        lab_ref = out.cpu().numpy()
+        ms, _ = timed(lambda d, out=None, **o: alb.cc(d, out=out, **o), ds, out, dict(alb_opts, visited_filter=True))
+        res["cc"]["alb_with_label0_filter"] = {"kernel_ms": round(ms, 3),
+                                               "same_result": bool(np.array_equal(out.cpu().numpy(), lab_ref))}
+        log("cc alb with the label-0 filter: %.3f ms" % ms)
     # k-core (the paper's kcore) on the same symmetrised graph: peeling from
     # every vertex with fewer than k neighbours
     for k in ((8, 32) if kcore else ()):

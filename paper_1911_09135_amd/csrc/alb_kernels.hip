@@ -1045,7 +1045,6 @@ __device__ __forceinline__ void clear_ahead(const Args &a, int r) {
   st_relaxed(&a.ctl->qcount[(r + 2) % 3], 0u);
   st_relaxed(&a.ctl->huge[(r + 1) & 1], 0ull);
   st_relaxed(&a.ctl->dangling[(r + 1) & 1], 0ull);
-  st_relaxed(&a.ctl->filt_count[(r + 1) & 1], 0ull);
 }
 
 // Membership of the persistent launch.  The grid may be larger than what the
@@ -1333,6 +1332,9 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
       } else {
         build = r >= 1;
       }
+      // the next round's count: nobody reads it before then (this round's
+      // members read [r & 1] right after the build's barrier)
+      if (gr.id == 0 && threadIdx.x == 0) st_relaxed(&a.ctl->filt_count[(r + 1) & 1], 0ull);
       if (build) {
         build_filter<B, Op>(a, gr, &a.ctl->filt_count[r & 1]);
         bool ok;
