@@ -1026,6 +1026,7 @@ def bench_serve(args, alb, gg, emit=True):
         "join_running": {"value": round(capj, 1), "unit": "queries/s", "requests": len(reqs),
                          "latency_ms": {"p50": pct(latj, 50), "p99": pct(latj, 99)}, "failed": fj,
                          "launches": launches_j, "completed": stj["completed"],
+                         "direct_outputs": stj["direct_outputs"],
                          "lanes": join_cfg["lanes"], "join_long_edges": join_cfg.get("join_long_edges", 0)},
         "poisson": rates,
         "results_checked_against_oracle": checked,
