@@ -113,9 +113,10 @@ typedef struct {
                                 edges into vertices that cannot change touch the small bitmap instead of the
                                 label array.  BFS: the reached vertices, built once half of them are reached.
                                 CC: the vertices holding label 0 (the smallest id, final), rebuilt at each
-                                round's start from round 1 and used once they are half of all.
-                                0 = automatic (BFS: on for graphs of at least 2^23 vertices; CC: off),
-                                1 = on, -1 = off */
+                                round's start from round 1 and used once they are half of all.  k-core:
+                                the vertices already below k, rebuilt at each round's start (their
+                                decrements are skipped).  0 = automatic (BFS: on for graphs of at least
+                                2^23 vertices; CC and k-core: off), 1 = on, -1 = off */
   int32_t reserved[6];
 } alb_options;
 

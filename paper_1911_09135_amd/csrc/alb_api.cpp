@@ -764,10 +764,10 @@ alb_status run_job(alb_graph g, const Job &job, const alb_options &o, void *dev_
     a.word = ws->word;
     a.out = dev_out ? (int32_t *)dev_out : ws->labels;
   }
-  if (job.op == OP_CC && o.visited_filter == 1 && launch == ALB_LAUNCH_PERSISTENT) {
-    // only on request (it gains on graphs whose vertex 0 sits in a giant
-    // component, and costs elsewhere); the label-0 bitmap lives in the
-    // PageRank accumulator, which CC does not use
+  if ((job.op == OP_CC || job.op == OP_KCORE) && o.visited_filter == 1 && launch == ALB_LAUNCH_PERSISTENT) {
+    // only on request (CC gains on graphs whose vertex 0 sits in a giant
+    // component, and costs elsewhere); the bitmap lives in the PageRank
+    // accumulator, which CC and k-core do not use
     a.vbits = (uint32_t *)ws->acc;
   }
   if (job.op == OP_KCORE) {

@@ -266,6 +266,37 @@ struct OpKCore {
   }
 };
 
+// k-core with the filter: a set bit says the destination has already left
+// the core (remaining degree below k), so decrementing it changes nothing
+// (its degree stays below k and it is never pushed again); the atomic is
+// skipped.
+struct OpKCoreFilter : OpKCore {
+  const uint32_t *vbits;
+  struct pre_t {
+    bool gone;
+  };
+  __device__ __forceinline__ pre_t prepare(int32_t, long long dl, val_t, int32_t) const {
+    return {((vbits[dl >> 5] >> (dl & 31)) & 1u) != 0u};
+  }
+  __device__ __forceinline__ bool commit(const pre_t &p, int32_t, long long dl, val_t, int32_t, int32_t,
+                                         uint32_t) const {
+    if (p.gone) return false;
+    return __hip_atomic_fetch_add(&rem[dl], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k;
+  }
+};
+template <>
+struct Filtered<OpKCore> {
+  using type = OpKCoreFilter;
+  __device__ static type make(const OpKCore &op, const Args &a) {
+    type f;
+    f.rem = op.rem;
+    f.k = op.k;
+    f.vbits = a.vbits;
+    return f;
+  }
+  __device__ static bool bit(const Args &a, uint32_t v) { return a.level[v] < a.kcore_k; }  // left the core
+};
+
 struct OpPR {  // acc[dst] += rank[src] / outdeg(src): fp32 contribution, exact fixed-point sum
   using val_t = float;
   struct pre_t {};
@@ -1325,12 +1356,15 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(ALB_WAVES_PER
       // vertices: build the bitmap once and filter from this round on.
       // CC: from round 1 on, rebuild the bitmap of label-0 vertices at each
       // round's start and filter once they are at least half of all.
+      // k-core: the same from round 0 on, with the vertices below k.
       bool build = false;
       if constexpr (std::is_same<Op, OpBFS>::value) {
         reached += nF;
         build = !filtered && 2 * reached >= (uint64_t)a.n;
-      } else {
+      } else if constexpr (std::is_same<Op, OpCC>::value) {
         build = r >= 1;
+      } else {
+        build = true;
       }
       // the next round's count: nobody reads it before then (this round's
       // members read [r & 1] right after the build's barrier)
@@ -1954,7 +1988,8 @@ struct LbF {
 template <int B, class Op>
 struct PersistentF {
   static hipError_t run(int grid, const Args *a, hipStream_t s) {
-    if constexpr (std::is_same<Op, OpBFS>::value || std::is_same<Op, OpCC>::value) {
+    if constexpr (std::is_same<Op, OpBFS>::value || std::is_same<Op, OpCC>::value ||
+                  std::is_same<Op, OpKCore>::value) {
       if (a->vbits) {  // with the filter bitmap
         hipLaunchKernelGGL((k_persistent<B, Op, false, true>), dim3(grid), dim3(B), 0, s, *a, make_op<Op>(*a));
         return hipGetLastError();

@@ -113,7 +113,7 @@ def test_kcore_zipf20():
     assert dg.m == gs.m
     for k in (2, 12, 16, 18, 20, 24):  # the core shrinks from almost all vertices to none
         ref = oracle.kcore(gs, k)
-        for c in (dict(), dict(mode="twc")):
+        for c in (dict(), dict(mode="twc"), dict(visited_filter=True)):
             got, st = alb.kcore(dg, k, **c)
             assert np.array_equal(got, ref), (k, c)
         log("kcore k=%d ok: %d in core, rounds %d" % (k, int(ref.sum()), st["rounds"]))

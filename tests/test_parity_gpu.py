@@ -199,6 +199,10 @@ def test_kcore_matrix(alb, name):
         for k in (ks if i % 7 == 0 else ks[1:4]):
             got, st = alb.kcore(dg, k, **c)
             assert np.array_equal(got, refs[k]), (name, k, c)
+            if c["launch"] == "persistent" and i % 7 == 0:
+                # the left-the-core filter (on request only) forced on
+                got, _ = alb.kcore(dg, k, visited_filter=True, **c)
+                assert np.array_equal(got, refs[k]), (name, k, c, "visited_filter")
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
