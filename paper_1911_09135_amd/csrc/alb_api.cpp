@@ -2573,6 +2573,27 @@ int32_t open_lane_untaken(OpenLane *L, int32_t *slots, int32_t max) {
   return k;
 }
 
+// Allocate `count` batch workspaces for batches of up to `labels` labels and
+// `nq` queries and hand them back to g's pool, so that later batches of up
+// to that size find one ready.  A workspace that a batch outgrows is freed
+// and allocated anew, and freeing device memory waits for the device: done
+// while a serving lane's batches run, it stalls the other lanes.
+alb_status batch_reserve(alb_graph g, int count, long long labels, int32_t nq) {
+  if (!g || count < 1 || labels < 1 || nq < 1) return ALB_OK;
+  HIP_TRY(hipSetDevice(g->device));
+  const uint32_t qcap = (uint32_t)std::min<long long>(std::max<long long>(labels, nq), 0xfffffffeLL);
+  const BatchNeeds nd{labels, qcap, hint_entries(qcap, -1, g->max_deg), nq};
+  std::vector<BatchWs *> held;
+  alb_status st = ALB_OK;
+  for (int i = 0; i < count && st == ALB_OK; ++i) {
+    BatchWs *w = nullptr;
+    st = bws_acquire(g, nd, &w);
+    if (st == ALB_OK) held.push_back(w);
+  }
+  for (BatchWs *w : held) ws_release(g, w);
+  return st;
+}
+
 static_assert(kOpenMaxSlots == kOpenRing, "the server's slot bound is the rings' size");
 
 }  // namespace alb

@@ -20,6 +20,10 @@ int auto_grid(int64_t edges, int wg, int resident);
 // `algo` on g's device.
 alb_status batch_resident_workgroups(alb_graph g, int32_t algo, int32_t wg, int *out);
 
+// Keep `count` batch workspaces for batches of up to `labels` labels and
+// `nq` queries in g's pool (allocated now, free for the next batches).
+alb_status batch_reserve(alb_graph g, int count, long long labels, int32_t nq);
+
 // The device wall-clock window (ms, the device's own origin) of the last
 // persistent launch this thread completed through a batch call: when its
 // first workgroup joined and when it left its last round.  False if that

@@ -580,6 +580,18 @@ alb_status alb_server_create(alb_graph g, const alb_server_config *user, alb_ser
       if (e != hipSuccess) return bail(set_error(ALB_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
       s->streams.push_back(x);
     }
+    if (!cfg.join_running) {
+      // every lane's largest batch (its share of the budget, at most
+      // max_batch queries of the largest member) has a workspace from the
+      // start: a batch never frees and reallocates one while others run.
+      // Not fatal: without it batches allocate as they grow.
+      int32_t max_n = 1;
+      for (int32_t n : s->member_n) max_n = std::max(max_n, n);
+      const long long labels = std::min<long long>((long long)(s->lane_budget / kBytesPerVertex),
+                                                   (long long)cfg.max_batch * max_n);
+      if (alb::batch_reserve(g, cfg.lanes, std::min<long long>(labels, kMaxPositions - 1), cfg.max_batch) != ALB_OK)
+        alb::set_error(ALB_OK, "%s", "");
+    }
   }
   try {
     for (int i = 0; i < cfg.lanes; ++i) s->lanes.emplace_back([s, i] { s->lane_main(i); });
