@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each summary measurement")
     ap.add_argument("--parts", default="bfs,pagerank,pull,cc,kcore,grid",
                     help="zipf24: the parts to run (profiling runs take one)")
+    ap.add_argument("--visited-filter", default="auto", choices=["auto", "on", "off"],
+                    help="zipf24: the BFS/CC/k-core filter bitmap of the ALB runs (auto: the library's default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -684,6 +686,8 @@ def bench_zipf24(args, alb, gg, emit=True, cpu=False, kcore=True, grid=True, par
     dg = alb.Graph(g.off, g.col)
     out = torch.empty(g.n, dtype=torch.int32, device="cuda")
     alb_opts = {} if args.threshold is None else {"threshold": args.threshold}
+    if args.visited_filter != "auto":
+        alb_opts["visited_filter"] = args.visited_filter == "on"
     modes = (("alb", alb_opts),) if args.only_alb else (("alb", alb_opts), ("twc_only", {"mode": "twc"}))
     levels = None
     for label, opts in modes if "bfs" in parts else ():
